@@ -1,0 +1,295 @@
+"""Pins of the CPU oracle against things other than itself: brute force,
+closed forms, invariants of the graph Laplacian, and independent
+re-derivations (finite differences, a different simplex-projection algorithm,
+the dense implicit step of the scheme).  None of these call the GPU library.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_parameters.json")))
+
+
+# ---------------------------------------------------------------------------
+# weight matrix (Sec. 2, Sec. 4)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_kernel_matvec_brute_force(d):
+    g = gen.rng(7 + d)
+    n = 13
+    pts = g.uniform(-1, 1, size=(n, d))
+    sigma = 0.7
+    x = g.standard_normal(n)
+    y = oracle.kernel_matvec(pts, sigma, x)
+    for i in range(n):
+        terms = []
+        for j in range(n):
+            if j == i:
+                continue
+            r2 = math.fsum((pts[i, k] - pts[j, k]) ** 2 for k in range(d))
+            terms.append(math.exp(-r2 / sigma ** 2) * x[j])
+        ref = math.fsum(terms)
+        assert abs(y[i] - ref) <= 1e-15 * math.fsum(abs(t) for t in terms) + 1e-300
+
+
+def test_weight_matrix_is_bitwise_symmetric_and_zero_diagonal():
+    pts, _ = gen.gaussian_mixture(40, 3, 3, 0.2, 5)
+    W = oracle.kernel_matvec(pts, 0.3, np.eye(40))
+    assert np.all(np.diag(W) == 0.0)
+    assert np.array_equal(W, W.T)
+
+
+def test_sampled_rows_equal_full_rows():
+    pts, _ = gen.gaussian_mixture(300, 2, 3, 0.1, 6)
+    X = gen.test_vectors(300, 3, 11)
+    full = oracle.kernel_matvec(pts, 0.2, X)
+    rows = np.array([0, 17, 299, 150, 17])
+    part = oracle.kernel_rows(pts, 0.2, X, rows)
+    assert np.array_equal(part, full[rows])
+
+
+def test_kernel_matvec_matches_dense_numpy():
+    pts, _ = gen.gaussian_mixture(200, 3, 4, 0.1, 9)
+    X = gen.test_vectors(200, 4, 12)
+    W = oracle.dense_weight(pts, 0.15)
+    np.testing.assert_allclose(oracle.kernel_matvec(pts, 0.15, X), W @ X, rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Laplacians and their spectra (Sec. 2, Sec. 3)
+# ---------------------------------------------------------------------------
+def test_two_nodes_spectrum():
+    L = oracle.Layer(np.array([[0.0], [0.3]]), 0.5)
+    lam, _ = oracle.eigs_dense([L], 2)
+    np.testing.assert_allclose(lam, [0.0, 2.0], atol=1e-14)
+
+
+def test_equilateral_triangle_spectrum():
+    p = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, math.sqrt(3) / 2]])
+    L = oracle.Layer(p, 1.3)
+    lam, _ = oracle.eigs_dense([L], 3)
+    np.testing.assert_allclose(lam, [0.0, 1.5, 1.5], atol=1e-13)
+
+
+def circle_closed_form(n, R, sigma):
+    """W is circulant for equally spaced points on a circle; its normalised
+    adjacency has eigenvalues sum_j w_j cos(2 pi k j / n) / sum_j w_j."""
+    j = np.arange(1, n)
+    w = np.exp(-(2 * R * np.sin(np.pi * j / n)) ** 2 / sigma ** 2)
+    k = np.arange(n)
+    mu = (w[None, :] * np.cos(2 * np.pi * np.outer(k, j) / n)).sum(1) / w.sum()
+    return np.sort(1.0 - mu)
+
+
+def test_circle_graph_dense_closed_form():
+    n, R, s = 64, 1.0, 0.6
+    L = oracle.Layer(gen.circle_points(n, R), s)
+    lam, _ = oracle.eigs_dense([L], n)
+    np.testing.assert_allclose(lam, circle_closed_form(n, R, s), atol=1e-13)
+
+
+@pytest.mark.slow
+def test_circle_graph_iterative_closed_form():
+    n, R, s = 1500, 1.0, 0.05
+    L = oracle.Layer(gen.circle_points(n, R, d=3, phase=0.25), s)
+    lam, V = oracle.eigs_iterative([L], 8, tol=1e-13)
+    np.testing.assert_allclose(lam, circle_closed_form(n, R, s)[:8], atol=1e-10)
+
+
+def test_lsym_annihilates_sqrt_degree_vector():
+    pts, _ = gen.gaussian_mixture(250, 3, 3, 0.1, 21)
+    L = oracle.Layer(pts, 0.2)
+    v = np.sqrt(L.deg)
+    r = oracle.lsym_matvec([L], v)
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(v)
+
+
+def test_spectrum_range_and_trace():
+    pts, _ = gen.gaussian_mixture(150, 2, 3, 0.1, 22)
+    L = oracle.Layer(pts, 0.15)
+    A = oracle.dense_nadj([L])
+    Ls = np.eye(150) - A
+    assert abs(np.trace(Ls) - 150) < 1e-10
+    ev = np.linalg.eigvalsh(Ls)
+    assert ev.min() > -1e-12 and ev.max() < 2 + 1e-12
+
+
+def test_layer_mean_matches_dense_and_identical_layers():
+    pts1, _ = gen.gaussian_mixture(120, 3, 3, 0.1, 31)
+    pts2 = gen.uniform_ball(120, 2, 1.0, 32)
+    La, Lb = oracle.Layer(pts1, 0.2), oracle.Layer(pts2, 0.5)
+    X = gen.test_vectors(120, 2, 33)
+    np.testing.assert_allclose(oracle.nadj_matvec([La, Lb], X), oracle.dense_nadj([La, Lb]) @ X,
+                               rtol=1e-12, atol=1e-13)
+    # T identical layers give the operator of one layer
+    np.testing.assert_allclose(oracle.nadj_matvec([La, La, La], X), oracle.nadj_matvec([La], X),
+                               rtol=1e-14, atol=1e-15)
+
+
+def test_power_mean_single_layer_is_that_layer():
+    pts, _ = gen.gaussian_mixture(60, 2, 2, 0.2, 41)
+    L = oracle.Layer(pts, 0.3)
+    Ls = np.eye(60) - oracle.dense_nadj([L])
+    np.testing.assert_allclose(oracle.power_mean_dense([L], 1.0), Ls, atol=1e-12)
+    delta = math.log(1 + 2.0)
+    np.testing.assert_allclose(oracle.power_mean_dense([L], -2.0), Ls + delta * np.eye(60), atol=1e-10)
+
+
+def test_eigs_well_separated_clusters_count():
+    pts, _ = gen.gaussian_mixture(200, 2, 4, 0.01, 51, mean_low=0, mean_high=10)
+    L = oracle.Layer(pts, 0.05)
+    lam, _ = oracle.eigs_dense([L], 6)
+    assert np.all(np.abs(lam[:4]) < 1e-10) and lam[4] > 0.1
+
+
+def test_eigs_iterative_matches_dense():
+    c = gen.config1(400)
+    L = oracle.Layer(c["layers"][0], 0.1)
+    l1, V1 = oracle.eigs_dense([L], 6)
+    l2, V2 = oracle.eigs_iterative([L], 6, tol=1e-14)
+    np.testing.assert_allclose(l1, l2, atol=1e-10)
+
+
+def test_isolated_node_detected():
+    p = np.array([[0.0, 0.0], [0.01, 0.0], [100.0, 100.0]])
+    with pytest.raises(ValueError):
+        oracle.Layer(p, 0.1)
+
+
+# ---------------------------------------------------------------------------
+# Allen--Cahn pieces (Sec. 5, Sec. 6, Appendix B)
+# ---------------------------------------------------------------------------
+def psi(u):
+    m = len(u)
+    out = 1.0
+    for j in range(m):
+        e = np.zeros(m)
+        e[j] = 1
+        out *= 0.25 * np.abs(u - e).sum() ** 2
+    return out
+
+
+@pytest.mark.parametrize("m", [2, 3, 5, 8])
+def test_potential_grad_vs_finite_differences(m):
+    g = gen.rng(60 + m)
+    for _ in range(5):
+        u = g.uniform(0.05, 0.95, size=m)
+        T = oracle.potential_grad(u)
+        h = 1e-6
+        fd = np.array([(psi(u + h * np.eye(m)[j]) - psi(u - h * np.eye(m)[j])) / (2 * h)
+                       for j in range(m)])
+        np.testing.assert_allclose(T, fd, rtol=1e-6, atol=1e-9)
+
+
+@pytest.mark.parametrize("m", [2, 4, 7])
+def test_potential_grad_vanishes_at_corners(m):
+    for q in range(m):
+        assert np.all(oracle.potential_grad(np.eye(m)[q]) == 0.0)
+
+
+def bisection_projection(y):
+    """Simplex projection by bisection on the threshold tau with
+    sum max(y - tau, 0) = 1 (a different algorithm from Chen & Ye's)."""
+    lo, hi = y.min() - 1.0, y.max()
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if np.maximum(y - mid, 0).sum() > 1.0:
+            lo = mid
+        else:
+            hi = mid
+    return np.maximum(y - 0.5 * (lo + hi), 0)
+
+
+@pytest.mark.parametrize("m", [2, 3, 5, 10])
+def test_simplex_projection(m):
+    g = gen.rng(70 + m)
+    for _ in range(50):
+        y = g.standard_normal(m) * g.choice([0.1, 1, 10])
+        x = oracle.simplex_project(y)
+        assert np.all(x >= 0) and abs(x.sum() - 1) < 1e-14
+        np.testing.assert_allclose(x, bisection_projection(y), atol=1e-13)
+        np.testing.assert_allclose(oracle.simplex_project(x), x, atol=1e-15)
+    s = g.dirichlet(np.ones(m))
+    np.testing.assert_allclose(oracle.simplex_project(s), s, atol=1e-15)
+
+
+def dense_scheme(Ls, labels, m, eps, omega0, c, dt, iters):
+    """Implicit step of Sec. 5 with a dense solve of B = (1+c dt) I + eps dt L,
+    then projection: the scheme before the eigenbasis is introduced."""
+    n = Ls.shape[0]
+    F = np.zeros((n, m))
+    om = np.zeros(n)
+    U = np.full((n, m), 1.0 / m)
+    for i, l in enumerate(labels):
+        if l >= 0:
+            F[i, l] = 1
+            om[i] = omega0
+            U[i] = F[i]
+    B = (1 + c * dt) * np.eye(n) + eps * dt * Ls
+    for _ in range(iters):
+        A = np.abs(U[:, None, :] - np.eye(m)[None, :, :]).sum(-1)      # a_iq
+        S = 0.25 * A ** 2
+        T = np.zeros((n, m))
+        for q in range(m):
+            prod = np.prod(np.delete(S, q, axis=1), axis=1)
+            sgn = np.ones(m)
+            sgn[q] = -1
+            T += 0.5 * (A[:, q] * prod)[:, None] * sgn[None, :]
+        R = (1 + c * dt) * U - dt / (2 * eps) * T - dt * om[:, None] * (U - F)
+        Ut = np.linalg.solve(B, R)
+        U = np.array([bisection_projection(r) for r in Ut])
+    return U
+
+
+def test_allen_cahn_full_basis_equals_dense_scheme():
+    c = gen.config1(120)
+    L = oracle.Layer(c["layers"][0], 0.1)
+    lam, V = oracle.eigs_dense([L], 120)
+    lab = gen.label_set(120, c["classes"], 0.1, 5)
+    P = GOLD["allen_cahn_small_multilayer"]
+    eps, om0, dt = P["eps"], P["omega0"], P["dt"]
+    cc = om0 + P["c_minus_omega0_times_eps"] / eps
+    U, pred, it, _ = oracle.allen_cahn(lam, V, lab, 5, eps=eps, omega0=om0, c=cc, dt=dt,
+                                       tol=0.0, max_iter=6)
+    assert it == 6
+    Ls = np.eye(120) - oracle.dense_nadj([L])
+    Ud = dense_scheme(Ls, lab, 5, eps, om0, cc, dt, 6)
+    np.testing.assert_allclose(U, Ud, atol=1e-9)
+
+
+def test_allen_cahn_all_labelled_reproduces_labels():
+    c = gen.config1(300)
+    L = oracle.Layer(c["layers"][0], 0.1)
+    lam, V = oracle.eigs_dense([L], 40)
+    U, pred, it, _ = oracle.allen_cahn(lam, V, c["classes"], 5, omega0=1e4, c=1e4 + 3 / 5e-3,
+                                       tol=0.0, max_iter=50)
+    assert np.array_equal(pred, c["classes"])
+
+
+def test_allen_cahn_iteration_count_semantics():
+    c = gen.config1(200)
+    L = oracle.Layer(c["layers"][0], 0.1)
+    lam, V = oracle.eigs_dense([L], 8)
+    lab = gen.label_set(200, c["classes"], 0.05, 3)
+    _, _, it, _ = oracle.allen_cahn(lam, V, lab, 5, tol=0.0, max_iter=17)
+    assert it == 17
+    _, _, it, _ = oracle.allen_cahn(lam, V, lab, 5, tol=1e300, max_iter=17)
+    assert it == 1            # the loop body always runs once (do ... while)
+    U, _, _, _ = oracle.allen_cahn(lam, V, lab, 5, tol=0.0, max_iter=5)
+    assert np.all(U >= 0) and np.allclose(U.sum(1), 1.0, atol=1e-14)
+
+
+def test_allen_cahn_is_deterministic():
+    c = gen.config1(200)
+    L = oracle.Layer(c["layers"][0], 0.1)
+    lam, V = oracle.eigs_dense([L], 8)
+    lab = gen.label_set(200, c["classes"], 0.05, 3)
+    a = oracle.allen_cahn(lam, V, lab, 5, tol=0.0, max_iter=20)
+    b = oracle.allen_cahn(lam, V, lab, 5, tol=0.0, max_iter=20)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
