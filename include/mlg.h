@@ -1,0 +1,233 @@
+/*
+ * mlg.h -- C ABI of the MI355X multilayer-graph Laplacian library (libmlg.so).
+ *
+ * Operators (Bergermann, Stoll, Volkmer, "Semi-supervised learning for
+ * aggregated multilayer graphs using diffuse interface methods and fast
+ * matrix-vector products"):
+ *
+ *   W        layer weight matrix, W_ij = exp(-||x_i - x_j||^2 / sigma^2),
+ *            W_ii = 0                                   (Sec. 2, Sec. 4)
+ *   D        diag(W 1)                                  (Sec. 2)
+ *   L_sym    I - D^-1/2 W D^-1/2                        (Sec. 2)
+ *   I - L_1  (1/T) sum_t D_t^-1/2 W_t D_t^-1/2          (Sec. 3, eq. for I - L_1)
+ *
+ * W v is evaluated either by direct summation (Sec. 2, case (i)) or by NFFT
+ * fast summation (Algorithm 1 of Sec. 4; the self term is removed through
+ * W = W~ - K(0) I).
+ *
+ * Conventions shared by every call:
+ *  - Status codes are returned; nothing throws across the ABI.  On an error
+ *    the outputs are unspecified; mlg_last_error() gives a message
+ *    (thread-local, valid until the next call on the same thread).
+ *  - Blocks of vectors are column-major n x b FP64 arrays with a leading
+ *    dimension ld >= n.
+ *  - With MLG_DEVICE_PTRS in `flags`, array arguments are HIP device pointers
+ *    (e.g. torch.Tensor.data_ptr() of a CUDA/HIP tensor); otherwise they are
+ *    host pointers and the library stages them through device memory.
+ *  - The caller owns every array it passes.  The library never frees a
+ *    caller pointer and keeps none past the call.  A graph handle owns its
+ *    own device memory (points, plans, degrees, workspaces, HIP graphs).
+ *  - Work is enqueued on the HIP stream given at creation (NULL = the null
+ *    stream) and the call returns after that stream has drained, so device
+ *    outputs are ready when it returns.
+ *  - One handle must not be used from two threads at once.
+ *  - Same inputs and same parameters give bit-identical outputs: no kernel
+ *    accumulates floating point through atomics.
+ */
+#ifndef MLG_H
+#define MLG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLG_OK = 0,
+    MLG_WARN_NOT_CONVERGED = 1, /* Lanczos: best Ritz pairs returned, info filled */
+    MLG_ERR_ARG = -1,           /* null pointer, bad size, bad leading dimension  */
+    MLG_ERR_RANGE = -2,         /* d outside 1..3 for NFFT, N not a power of two,
+                                   sigma <= 0, window not even or too wide, ...    */
+    MLG_ERR_ISOLATED = -3,      /* a layer has a node of zero degree               */
+    MLG_ERR_NOMEM = -4,         /* device allocation failed                        */
+    MLG_ERR_HIP = -5,           /* a HIP runtime call failed                       */
+    MLG_ERR_NOT_IMPL = -6       /* valid request the library does not implement    */
+} mlg_status;
+
+#define MLG_DEVICE_PTRS 1
+
+/* summation method */
+#define MLG_METHOD_DIRECT 0 /* O(n^2) tiled direct sum (Sec. 2 case (i))       */
+#define MLG_METHOD_NFFT 1   /* NFFT fast summation (Algorithm 1, Sec. 4)       */
+
+/* operator selector for mlg_laplacian_matvec */
+#define MLG_OP_NADJ 0 /* D^-1/2 W D^-1/2 (one layer) or I - L_1 (layer = -1) */
+#define MLG_OP_LSYM 1 /* L_sym (one layer) or L_1 (layer = -1)               */
+#define MLG_OP_W 2    /* W itself (one layer only), zero diagonal            */
+
+/*
+ * Per-layer summation parameters (Sec. 4; fast-summation parameters of the
+ * image and hyperspectral experiments in Sec. 8).
+ *   method     MLG_METHOD_DIRECT or MLG_METHOD_NFFT.
+ *   precision  32 or 64: arithmetic of the summation itself (spreading, FFT,
+ *              interpolation or direct tiles).  Degrees, D^-1/2 scaling and
+ *              layer aggregation are always FP64.
+ *   N          NFFT bandwidth: frequencies l in {-N/2..N/2}^d are kept; the
+ *              FFT grid has 2N points per dimension.  Power of two, 8..256.
+ *   window     window support w in grid points, even, 2..16, with
+ *              bin + w/2 <= N/2 (0 = 6 for precision 32, 12 for precision 64).
+ *   eps_B      regularisation length of the periodised kernel, 0 < eps_B < 1/4.
+ *   p_reg      smoothness degree of the regularisation, 1..12.
+ *   bin        bin edge in grid cells used to group points (1, 2 or 4;
+ *              0 = 1).
+ * Ignored for MLG_METHOD_DIRECT except `precision`.
+ */
+typedef struct {
+    int method;
+    int precision;
+    int N;
+    int window;
+    double eps_B;
+    int p_reg;
+    int bin;
+} mlg_kparams;
+
+typedef struct mlg_graph mlg_graph;
+
+/* Message describing the last error on this thread ("" if none). */
+const char *mlg_last_error(void);
+
+/* Library version string. */
+const char *mlg_version(void);
+
+/*
+ * Build a multilayer graph (Sec. 2 multilayer graph; Sec. 7 feature
+ * grouping gives one layer per feature group).
+ *   n        nodes shared by all layers, n >= 2.
+ *   T        layers, 1..1024.
+ *   d        T layer dimensions (1..3 for NFFT, 1..16 for direct).
+ *   points   T pointers, layer t is n x d[t] row-major FP64 (host or device
+ *            per flags; only read during the call).
+ *   sigma    T kernel widths, > 0.
+ *   kp       T parameter records.
+ *   flags    MLG_DEVICE_PTRS or 0.
+ *   stream   hipStream_t for all work on this graph (NULL = null stream).
+ * Plans every layer (torus scaling, kernel Fourier coefficients, bin sort)
+ * and computes each layer's degrees in FP64.  Returns MLG_ERR_ISOLATED if a
+ * degree is not positive (below 1e-9 for NFFT layers).
+ */
+mlg_status mlg_graph_create(mlg_graph **out, int64_t n, int T, const int *d,
+                            const double *const *points, const double *sigma,
+                            const mlg_kparams *kp, int flags, void *stream);
+
+mlg_status mlg_graph_destroy(mlg_graph *g);
+
+/* Copy layer `layer`'s degrees deg(x_i) (Sec. 2) into deg (n FP64). */
+mlg_status mlg_graph_degrees(mlg_graph *g, int layer, double *deg, int flags);
+
+/*
+ * Y = W X for one point set, zero diagonal (Sec. 4: W v = W~ v - K(0) v).
+ * Stateless: plans, applies and frees.  points n x d row-major FP64.
+ */
+mlg_status mlg_kernel_matvec(int64_t n, int d, const double *points, double sigma,
+                             const mlg_kparams *kp, int b, const double *X, int64_t ldx,
+                             double *Y, int64_t ldy, int flags, void *stream);
+
+/*
+ * Y = op X with op one of MLG_OP_* for layer `layer` (0..T-1), or for the
+ * layer mean (layer = -1, p = 1 power mean of Sec. 2 eq. (1) and Sec. 3).
+ * b: 1..64 vectors.  X and Y must not overlap.  The first call for a given
+ * (layer, op, b) captures the launch sequence into a HIP graph; later calls
+ * replay it.
+ */
+mlg_status mlg_laplacian_matvec(mlg_graph *g, int layer, int op, int b, const double *X,
+                                int64_t ldx, double *Y, int64_t ldy, int flags);
+
+typedef struct {
+    int iters;        /* block expansion steps taken                       */
+    int restarts;     /* thick restarts                                    */
+    int matvecs;      /* operator applications to single vectors           */
+    int nconv;        /* wanted pairs whose residual is <= tol             */
+    double max_resid; /* max residual norm ||A phi - mu phi|| over the k   */
+} mlg_eig_info;
+
+/*
+ * k smallest eigenpairs of L_sym (layer >= 0) or of L_1 (layer = -1),
+ * computed as the k largest of D^-1/2 W D^-1/2 resp. I - L_1 with
+ * lambda = 1 - mu (Sec. 3; Algorithm 2 step 1).  FP64 block thick-restart
+ * Lanczos with full reorthogonalisation (CGS2).
+ *   p            power-mean exponent; only 1.0 is implemented.
+ *   k            1..n/2 wanted pairs.
+ *   block        vectors per Lanczos block, 1..32.
+ *   tol          stop when every residual ||A phi - mu phi||_2 <= tol.
+ *   max_restarts restarts allowed (0 = expand once, no restart).
+ *   seed         start block: counter-based N(0,1) draws (SplitMix64 +
+ *                Box-Muller) unless V0 is given.
+ *   V0           optional n x block start block (same pointer kind as the
+ *                outputs), or NULL.
+ *   evals        k eigenvalues lambda, ascending.
+ *   evecs        n x k column-major, leading dim ldv; unit 2-norm, sign
+ *                chosen so that the largest-magnitude entry is positive.
+ * Returns MLG_WARN_NOT_CONVERGED if the restarts ran out.
+ */
+mlg_status mlg_lanczos_eigs(mlg_graph *g, int layer, double p, int k, int block, double tol,
+                            int max_restarts, uint64_t seed, const double *V0, double *evals,
+                            double *evecs, int64_t ldv, mlg_eig_info *info, int flags);
+
+/* Allen--Cahn parameters (Algorithm 2): epsilon, omega_0, c, dt, tolerance,
+ * max_iter. */
+typedef struct {
+    double eps, omega0, c, dt, tol;
+    int max_iter;
+} mlg_ac_params;
+
+/*
+ * Multiclass Allen--Cahn scores in the truncated eigenbasis (Algorithm 2,
+ * steps 2-4; Sec. 5-6; Appendix B), FP64.
+ *   evals   k eigenvalues lambda_r of the Laplacian.
+ *   evecs   n x k column-major, leading dim ldv.
+ *   labels  n int32: -1 unlabelled, 0..m-1 class.
+ *   U       n x m row-major output scores (rows in the Gibbs simplex).
+ *   pred    n int32 output: row argmax, lowest class id on ties (Sec. 6).
+ *   iters   iterations run (the loop body runs at least once).
+ * The arithmetic follows one fixed FP64 operation order (documented with the
+ * kernels), so results are reproducible bit for bit.
+ */
+mlg_status mlg_allen_cahn_ssl(int64_t n, int k, int m, const double *evals,
+                              const double *evecs, int64_t ldv, const int32_t *labels,
+                              const mlg_ac_params *prm, double *U, int32_t *pred, int *iters,
+                              int flags, void *stream);
+
+/* ---- measurement helpers ------------------------------------------------ */
+
+/* Stages of one layer's matvec, for mlg_profile_stages. */
+#define MLG_STAGE_PRE 0     /* gather + D^-1/2 scaling + cast (Sec. 2)       */
+#define MLG_STAGE_SPREAD 1  /* window spreading, Alg. 1 step 1 (part)        */
+#define MLG_STAGE_GATHER 2  /* patch gather onto the grid (part of spread)   */
+#define MLG_STAGE_FFT 3     /* forward FFT, multiply, inverse FFT (Alg. 1)   */
+#define MLG_STAGE_INTERP 4  /* interpolation, Alg. 1 step 3 (part)           */
+#define MLG_STAGE_POST 5    /* self term, D^-1/2, layer mean (Sec. 2-4)      */
+#define MLG_STAGE_DIRECT 6  /* direct tiled summation                        */
+#define MLG_STAGE_IO 7      /* block transposes in and out                   */
+#define MLG_NSTAGES 8
+
+/*
+ * Run the matvec of mlg_laplacian_matvec `reps` times without a HIP graph,
+ * with HIP events around every kernel on the graph's stream, and return the
+ * average milliseconds per matvec spent in each stage (stage_ms has
+ * MLG_NSTAGES entries, summed over layers).
+ */
+mlg_status mlg_profile_stages(mlg_graph *g, int layer, int op, int b, const double *X,
+                              int64_t ldx, double *Y, int64_t ldy, int reps, double *stage_ms,
+                              int flags);
+
+/* Parameters each layer ended up with: 6 ints per layer
+ * (d, N, window, bin, precision, method) and 2 doubles per layer
+ * (scaled sigma, scale factor). */
+mlg_status mlg_graph_layer_info(mlg_graph *g, int layer, int *iparams, double *dparams);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLG_H */

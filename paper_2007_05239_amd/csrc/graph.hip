@@ -1,0 +1,571 @@
+// The mlg_graph handle and the C ABI entry points (declared in include/mlg.h).
+//
+// A matvec with the layer mean (Sec. 3, eq. for I - L_1) or one layer's
+// operator (Sec. 2) runs as
+//   block transpose X -> Xr (point-major FP64)
+//   per layer: z = D^-1/2 x gathered into the layer's sorted order and cast
+//              to the summation precision; F = W~ z (NFFT, Algorithm 1) or
+//              F = W z (direct); y (+)= coef D^-1/2 (F - K(0) z) in FP64
+//   block transpose Yr -> Y (with Y = X - Yr for L_sym / L_1).
+// The per-layer part is captured once into a HIP graph and replayed.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+
+#include "internal.h"
+
+namespace mlg {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+Graph::~Graph() {
+    for (auto &c : caps) (void)hipGraphExecDestroy(c.exec);
+    caps.clear();
+}
+
+__global__ void k_points_soa(int64_t n, int d, const double *__restrict__ pts,
+                             double *__restrict__ x64, float *__restrict__ x32) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int t = 0; t < d; ++t) {
+        double v = pts[i * d + t];
+        x64[(int64_t)t * n + i] = v;
+        x32[(int64_t)t * n + i] = (float)v;
+    }
+}
+
+static int block_stride(int b) {
+    int bs = 1;
+    while (bs < b) bs <<= 1;
+    return bs;
+}
+
+static int default_window(const Layer &L) {
+    if (L.kp.window > 0) return L.kp.window;
+    return L.kp.precision == 64 ? 12 : 6;
+}
+
+// Widest even window the plan admits (bin + w/2 <= N/2, bin + w - 1 <= 20).
+static int max_window(const NfftPlan &P) {
+    int w = 2 * (P.N / 2 - P.B);
+    w = std::min(w, 21 - P.B);
+    w = std::min(w, 16);
+    return w & ~1;
+}
+
+struct Workspace {
+    size_t zs = 0, patch = 0, grid = 0, part = 0;
+};
+
+static Workspace need(const Graph &g, int layer, int bs) {
+    Workspace w;
+    for (int t = 0; t < g.T; ++t) {
+        if (layer >= 0 && t != layer) continue;
+        const Layer &L = g.layers[t];
+        const size_t esz = L.kp.precision == 64 ? 8 : 4;
+        w.zs = std::max(w.zs, (size_t)g.n * bs * esz);
+        if (L.kp.method == MLG_METHOD_NFFT) {
+            w.patch = std::max(w.patch, nfft_patch_elems(L.nf, L.win, bs) * esz);
+            w.grid = std::max(w.grid, nfft_grid_elems(L.nf, bs) * esz);
+        } else {
+            size_t ps = esz == 8 ? direct_part_size<double>(g.n, bs) : direct_part_size<float>(g.n, bs);
+            w.part = std::max(w.part, ps * esz);
+        }
+    }
+    return w;
+}
+
+// Grow workspaces; returns true if any buffer moved (captured graphs stale).
+static bool ensure_ws(Graph &g, int layer, int b, int bs) {
+    Workspace w = need(g, layer, bs);
+    void *before[7] = {g.Xr.p, g.Yr.p, g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
+    g.Xr.ensure((size_t)g.n * b);
+    g.Yr.ensure((size_t)g.n * b);
+    g.Zs.ensure(w.zs);
+    g.Fs.ensure(w.zs);
+    g.patch.ensure(w.patch);
+    g.grid.ensure(w.grid);
+    g.part.ensure(w.part);
+    void *after[7] = {g.Xr.p, g.Yr.p, g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
+    for (int i = 0; i < 7; ++i)
+        if (before[i] != after[i]) return true;
+    return false;
+}
+
+struct StageTimer {
+    hipEvent_t ev[8];
+    double *acc;
+};
+
+template <class T>
+static void layer_core(Graph &g, Layer &L, int op, int b, int bs, double coef, bool accumulate,
+                       StageTimer *tm) {
+    hipStream_t s = g.stream;
+    const int *perm = L.sorted ? L.nf.perm.p : nullptr;
+    const double *dinv = (op == MLG_OP_W) ? nullptr : L.dinv_s.p;
+    T *Zs = reinterpret_cast<T *>(g.Zs.p);
+    T *Fs = reinterpret_cast<T *>(g.Fs.p);
+    float ms = 0.f;
+    if (tm) MLG_HIP(hipEventRecord(tm->ev[0], s));
+    launch_pre<T>(g.n, b, bs, perm, dinv, g.Xr.p, Zs, s);
+    if (tm) {
+        MLG_HIP(hipEventRecord(tm->ev[5], s));
+    }
+    if (L.kp.method == MLG_METHOD_NFFT) {
+        nfft_apply<T>(L.nf, L.win, bs, Zs, Fs, reinterpret_cast<T *>(g.patch.p),
+                      reinterpret_cast<T *>(g.grid.p), s, tm ? tm->ev + 0 : nullptr);
+    } else {
+        const T *x = nullptr;
+        if constexpr (sizeof(T) == 8) x = L.x64.p; else x = L.x32.p;
+        launch_direct<T>(g.n, L.d, x, 1.0 / (L.sigma * L.sigma), bs, Zs, Fs,
+                         reinterpret_cast<T *>(g.part.p), g.part.n / sizeof(T), s);
+        if (tm) MLG_HIP(hipEventRecord(tm->ev[4], s));
+    }
+    const double K0 = L.kp.method == MLG_METHOD_NFFT ? 1.0 : 0.0;
+    launch_post<T>(g.n, b, bs, perm, dinv, coef, K0, Fs, Zs, g.Yr.p, accumulate ? 1 : 0, s);
+    if (tm) {
+        MLG_HIP(hipEventRecord(tm->ev[6], s));
+        MLG_HIP(hipStreamSynchronize(s));
+        // ev[0]: start (pre begins); ev[5]: pre done.  For NFFT, nfft_apply
+        // re-records ev[0] is not used; its own events are ev[1..4] after ev[5].
+        MLG_HIP(hipEventElapsedTime(&ms, tm->ev[0], tm->ev[5]));
+        tm->acc[MLG_STAGE_PRE] += ms;
+        if (L.kp.method == MLG_METHOD_NFFT) {
+            MLG_HIP(hipEventElapsedTime(&ms, tm->ev[5], tm->ev[1]));
+            tm->acc[MLG_STAGE_SPREAD] += ms;
+            MLG_HIP(hipEventElapsedTime(&ms, tm->ev[1], tm->ev[2]));
+            tm->acc[MLG_STAGE_GATHER] += ms;
+            MLG_HIP(hipEventElapsedTime(&ms, tm->ev[2], tm->ev[3]));
+            tm->acc[MLG_STAGE_FFT] += ms;
+            MLG_HIP(hipEventElapsedTime(&ms, tm->ev[3], tm->ev[4]));
+            tm->acc[MLG_STAGE_INTERP] += ms;
+        } else {
+            MLG_HIP(hipEventElapsedTime(&ms, tm->ev[5], tm->ev[4]));
+            tm->acc[MLG_STAGE_DIRECT] += ms;
+        }
+        MLG_HIP(hipEventElapsedTime(&ms, tm->ev[4], tm->ev[6]));
+        tm->acc[MLG_STAGE_POST] += ms;
+    }
+}
+
+static void core(Graph &g, int layer, int op, int b, int bs, StageTimer *tm) {
+    bool first = true;
+    const double coef = layer < 0 ? 1.0 / g.T : 1.0;
+    for (int t = 0; t < g.T; ++t) {
+        if (layer >= 0 && t != layer) continue;
+        Layer &L = g.layers[t];
+        if (L.kp.precision == 64)
+            layer_core<double>(g, L, op, b, bs, coef, !first, tm);
+        else
+            layer_core<float>(g, L, op, b, bs, coef, !first, tm);
+        first = false;
+    }
+}
+
+static void check_op(const Graph &g, int layer, int op, int b) {
+    MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+    MLG_REQUIRE(op == MLG_OP_NADJ || op == MLG_OP_LSYM || op == MLG_OP_W, MLG_ERR_ARG, "bad op");
+    MLG_REQUIRE(!(op == MLG_OP_W && layer < 0), MLG_ERR_ARG, "MLG_OP_W needs one layer");
+    MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
+}
+
+void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, int64_t ldx,
+                          double *Y, int64_t ldy, double *stage_ms) {
+    check_op(g, layer, op, b);
+    const int bs = block_stride(b);
+    if (ensure_ws(g, layer, b, bs)) {
+        for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
+        g.caps.clear();
+    }
+    hipStream_t s = g.stream;
+    if (stage_ms) {
+        StageTimer tm;
+        tm.acc = stage_ms;
+        for (auto &e : tm.ev) MLG_HIP(hipEventCreate(&e));
+        hipEvent_t io0, io1;
+        MLG_HIP(hipEventCreate(&io0));
+        MLG_HIP(hipEventCreate(&io1));
+        float ms;
+        MLG_HIP(hipEventRecord(io0, s));
+        launch_to_rowmajor(g.n, b, X, ldx, g.Xr.p, s);
+        MLG_HIP(hipEventRecord(io1, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        MLG_HIP(hipEventElapsedTime(&ms, io0, io1));
+        stage_ms[MLG_STAGE_IO] += ms;
+        core(g, layer, op, b, bs, &tm);
+        MLG_HIP(hipEventRecord(io0, s));
+        launch_finish(g.n, b, g.Yr.p, X, ldx, Y, ldy, op == MLG_OP_LSYM, s);
+        MLG_HIP(hipEventRecord(io1, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        MLG_HIP(hipEventElapsedTime(&ms, io0, io1));
+        stage_ms[MLG_STAGE_IO] += ms;
+        for (auto &e : tm.ev) (void)hipEventDestroy(e);
+        (void)hipEventDestroy(io0);
+        (void)hipEventDestroy(io1);
+        return;
+    }
+    launch_to_rowmajor(g.n, b, X, ldx, g.Xr.p, s);
+    hipGraphExec_t exec = nullptr;
+    for (auto &c : g.caps)
+        if (c.layer == layer && c.op == op && c.b == b) exec = c.exec;
+    if (!exec) {
+        hipGraph_t graph;
+        MLG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            core(g, layer, op, b, bs, nullptr);
+        } catch (...) {
+            hipGraph_t junk;
+            (void)hipStreamEndCapture(s, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        MLG_HIP(hipStreamEndCapture(s, &graph));
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        MLG_HIP(e);
+        g.caps.push_back({layer, op, b, exec});
+    }
+    MLG_HIP(hipGraphLaunch(exec, s));
+    launch_finish(g.n, b, g.Yr.p, X, ldx, Y, ldy, op == MLG_OP_LSYM, s);
+}
+
+// Degrees deg = W 1 in FP64: for NFFT layers a high-accuracy FP64 window.
+static void compute_degrees(Graph &g, Layer &L) {
+    hipStream_t s = g.stream;
+    const int64_t n = g.n;
+    DevBuf<double> ones(n), Z(n * 1), F(n * 1);
+    launch_fill_ones(n, ones.p, s);
+    L.deg.alloc(n);
+    const int *perm = L.sorted ? L.nf.perm.p : nullptr;
+    launch_pre<double>(n, 1, 1, perm, nullptr, ones.p, Z.p, s);
+    double K0 = 0.0;
+    if (L.kp.method == MLG_METHOD_NFFT) {
+        NfftWindow Wd;
+        int wdeg = std::min(14, max_window(L.nf));
+        wdeg = std::max(wdeg, default_window(L));
+        nfft_make_window(L, Wd, wdeg, 64, 1, s);
+        DevBuf<double> patch(nfft_patch_elems(L.nf, Wd, 1)), grid(nfft_grid_elems(L.nf, 1));
+        nfft_apply<double>(L.nf, Wd, 1, Z.p, F.p, patch.p, grid.p, s, nullptr);
+        K0 = 1.0;
+        launch_post<double>(n, 1, 1, perm, nullptr, 1.0, K0, F.p, Z.p, L.deg.p, 0, s);
+        MLG_HIP(hipStreamSynchronize(s));
+    } else {
+        DevBuf<double> part(direct_part_size<double>(n, 1));
+        launch_direct<double>(n, L.d, L.x64.p, 1.0 / (L.sigma * L.sigma), 1, Z.p, F.p, part.p,
+                              part.n, s);
+        launch_post<double>(n, 1, 1, perm, nullptr, 1.0, 0.0, F.p, Z.p, L.deg.p, 0, s);
+        MLG_HIP(hipStreamSynchronize(s));
+    }
+    DevBuf<int> flag(1);
+    MLG_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+    const double thresh = L.kp.method == MLG_METHOD_NFFT ? 1e-9 : 0.0;
+    launch_check_degrees(n, L.deg.p, thresh, flag.p, s);
+    int hf = 0;
+    MLG_HIP(hipMemcpyAsync(&hf, flag.p, 4, hipMemcpyDeviceToHost, s));
+    MLG_HIP(hipStreamSynchronize(s));
+    MLG_REQUIRE(hf == 0, MLG_ERR_ISOLATED, "a node has zero degree (isolated) in some layer");
+    L.dinv_s.alloc(n);
+    launch_dinv(n, L.deg.p, perm, L.dinv_s.p, s);
+    MLG_HIP(hipStreamSynchronize(s));
+}
+
+static void build_layer(Graph &g, Layer &L, const double *pts, bool dev, bool degrees) {
+    hipStream_t s = g.stream;
+    const int64_t n = g.n;
+    DevBuf<double> pd;
+    const double *p = pts;
+    if (!dev) {
+        upload(pd, pts, (size_t)n * L.d, false, s);
+        p = pd.p;
+    }
+    L.n = n;
+    L.x64.alloc((size_t)n * L.d);
+    L.x32.alloc((size_t)n * L.d);
+    hipLaunchKernelGGL(k_points_soa, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, L.d, p, L.x64.p,
+                       L.x32.p);
+    MLG_LAUNCH_CHECK();
+    if (L.kp.method == MLG_METHOD_NFFT) {
+        nfft_plan_layer(L, p, s);
+        L.sorted = 1;
+        int w = default_window(L);
+        nfft_make_window(L, L.win, w, L.kp.precision, 1, s);
+    }
+    MLG_HIP(hipStreamSynchronize(s));
+    if (degrees) compute_degrees(g, L);
+}
+
+static hipStream_t make_stream(void *user) {
+    if (user) return (hipStream_t)user;
+    hipStream_t s;
+    MLG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+}
+
+}  // namespace mlg
+
+using namespace mlg;
+
+struct mlg_graph {
+    mlg::Graph g;
+    bool own_stream = false;
+};
+
+template <class F>
+static mlg_status guard(F f) {
+    try {
+        set_last_error("");
+        f();
+        return MLG_OK;
+    } catch (const mlg::Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return MLG_ERR_HIP;
+    }
+}
+
+extern "C" {
+
+const char *mlg_last_error(void) { return mlg::g_last_error.c_str(); }
+
+const char *mlg_version(void) { return "mlg 0.1 (gfx950)"; }
+
+static mlg_status create_graph(mlg_graph **out, int64_t n, int T, const int *d,
+                               const double *const *points, const double *sigma,
+                               const mlg_kparams *kp, int flags, void *stream, bool degrees) {
+    return guard([&] {
+        MLG_REQUIRE(out && d && points && sigma && kp, MLG_ERR_ARG, "null argument");
+        *out = nullptr;
+        MLG_REQUIRE(n >= 2, MLG_ERR_ARG, "n must be >= 2");
+        MLG_REQUIRE(T >= 1 && T <= 1024, MLG_ERR_ARG, "T must be in 1..1024");
+        for (int t = 0; t < T; ++t) {
+            MLG_REQUIRE(points[t], MLG_ERR_ARG, "null point array");
+            MLG_REQUIRE(sigma[t] > 0 && std::isfinite(sigma[t]), MLG_ERR_RANGE, "sigma must be > 0");
+            MLG_REQUIRE(kp[t].method == MLG_METHOD_DIRECT || kp[t].method == MLG_METHOD_NFFT,
+                        MLG_ERR_ARG, "bad method");
+            MLG_REQUIRE(kp[t].precision == 32 || kp[t].precision == 64, MLG_ERR_ARG,
+                        "precision must be 32 or 64");
+            if (kp[t].method == MLG_METHOD_NFFT)
+                MLG_REQUIRE(d[t] >= 1 && d[t] <= 3, MLG_ERR_RANGE, "NFFT layers need d in 1..3");
+            else
+                MLG_REQUIRE(d[t] >= 1 && d[t] <= 16, MLG_ERR_RANGE, "direct layers need d in 1..16");
+        }
+        std::unique_ptr<mlg_graph> h(new mlg_graph());
+        h->own_stream = stream == nullptr;
+        h->g.stream = make_stream(stream);
+        h->g.n = n;
+        h->g.T = T;
+        h->g.layers.resize(T);
+        try {
+            for (int t = 0; t < T; ++t) {
+                Layer &L = h->g.layers[t];
+                L.d = d[t];
+                L.sigma = sigma[t];
+                L.kp = kp[t];
+                build_layer(h->g, L, points[t], (flags & MLG_DEVICE_PTRS) != 0, degrees);
+            }
+        } catch (...) {
+            hipStream_t s = h->g.stream;
+            bool own = h->own_stream;
+            h.reset();
+            if (own) (void)hipStreamDestroy(s);
+            throw;
+        }
+        *out = h.release();
+    });
+}
+
+mlg_status mlg_graph_create(mlg_graph **out, int64_t n, int T, const int *d,
+                            const double *const *points, const double *sigma,
+                            const mlg_kparams *kp, int flags, void *stream) {
+    return create_graph(out, n, T, d, points, sigma, kp, flags, stream, true);
+}
+
+mlg_status mlg_graph_destroy(mlg_graph *g) {
+    return guard([&] {
+        if (!g) return;
+        hipStream_t s = g->g.stream;
+        bool own = g->own_stream;
+        (void)hipStreamSynchronize(s);
+        delete g;
+        if (own) (void)hipStreamDestroy(s);
+    });
+}
+
+mlg_status mlg_graph_degrees(mlg_graph *h, int layer, double *deg, int flags) {
+    return guard([&] {
+        MLG_REQUIRE(h && deg, MLG_ERR_ARG, "null argument");
+        Graph &g = h->g;
+        MLG_REQUIRE(layer >= 0 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+        MLG_HIP(hipMemcpyAsync(deg, g.layers[layer].deg.p, sizeof(double) * g.n,
+                               (flags & MLG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice
+                                                         : hipMemcpyDeviceToHost,
+                               g.stream));
+        MLG_HIP(hipStreamSynchronize(g.stream));
+    });
+}
+
+mlg_status mlg_graph_layer_info(mlg_graph *h, int layer, int *ip, double *dp) {
+    return guard([&] {
+        MLG_REQUIRE(h && ip && dp, MLG_ERR_ARG, "null argument");
+        Graph &g = h->g;
+        MLG_REQUIRE(layer >= 0 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+        const Layer &L = g.layers[layer];
+        ip[0] = L.d;
+        ip[1] = L.kp.method == MLG_METHOD_NFFT ? L.nf.N : 0;
+        ip[2] = L.kp.method == MLG_METHOD_NFFT ? L.win.w : 0;
+        ip[3] = L.kp.method == MLG_METHOD_NFFT ? L.nf.B : 0;
+        ip[4] = L.kp.precision;
+        ip[5] = L.kp.method;
+        dp[0] = L.kp.method == MLG_METHOD_NFFT ? L.nf.sigma_s : L.sigma;
+        dp[1] = L.kp.method == MLG_METHOD_NFFT ? L.nf.scale : 1.0;
+    });
+}
+
+mlg_status mlg_laplacian_matvec(mlg_graph *h, int layer, int op, int b, const double *X,
+                                int64_t ldx, double *Y, int64_t ldy, int flags) {
+    return guard([&] {
+        MLG_REQUIRE(h && X && Y, MLG_ERR_ARG, "null argument");
+        Graph &g = h->g;
+        check_op(g, layer, op, b);
+        MLG_REQUIRE(ldx >= g.n && ldy >= g.n, MLG_ERR_ARG, "leading dimension < n");
+        if (flags & MLG_DEVICE_PTRS) {
+            graph_matvec_enqueue(g, layer, op, b, X, ldx, Y, ldy, nullptr);
+            MLG_HIP(hipStreamSynchronize(g.stream));
+            return;
+        }
+        DevBuf<double> dX((size_t)g.n * b), dY((size_t)g.n * b);
+        MLG_HIP(hipMemcpy2DAsync(dX.p, g.n * 8, X, ldx * 8, g.n * 8, b, hipMemcpyHostToDevice,
+                                 g.stream));
+        graph_matvec_enqueue(g, layer, op, b, dX.p, g.n, dY.p, g.n, nullptr);
+        MLG_HIP(hipMemcpy2DAsync(Y, ldy * 8, dY.p, g.n * 8, g.n * 8, b, hipMemcpyDeviceToHost,
+                                 g.stream));
+        MLG_HIP(hipStreamSynchronize(g.stream));
+    });
+}
+
+mlg_status mlg_profile_stages(mlg_graph *h, int layer, int op, int b, const double *X, int64_t ldx,
+                              double *Y, int64_t ldy, int reps, double *stage_ms, int flags) {
+    return guard([&] {
+        MLG_REQUIRE(h && X && Y && stage_ms, MLG_ERR_ARG, "null argument");
+        MLG_REQUIRE(flags & MLG_DEVICE_PTRS, MLG_ERR_ARG, "profiling needs device pointers");
+        MLG_REQUIRE(reps >= 1, MLG_ERR_ARG, "reps must be >= 1");
+        Graph &g = h->g;
+        MLG_REQUIRE(ldx >= g.n && ldy >= g.n, MLG_ERR_ARG, "leading dimension < n");
+        for (int i = 0; i < MLG_NSTAGES; ++i) stage_ms[i] = 0.0;
+        for (int r = 0; r < reps; ++r)
+            graph_matvec_enqueue(g, layer, op, b, X, ldx, Y, ldy, stage_ms);
+        for (int i = 0; i < MLG_NSTAGES; ++i) stage_ms[i] /= reps;
+    });
+}
+
+mlg_status mlg_kernel_matvec(int64_t n, int d, const double *points, double sigma,
+                             const mlg_kparams *kp, int b, const double *X, int64_t ldx, double *Y,
+                             int64_t ldy, int flags, void *stream) {
+    mlg_graph *h = nullptr;
+    const double *pp[1] = {points};
+    mlg_status st = create_graph(&h, n, 1, &d, pp, &sigma, kp, flags, stream, false);
+    if (st != MLG_OK) return st;
+    st = guard([&] {
+        MLG_REQUIRE(X && Y, MLG_ERR_ARG, "null argument");
+    });
+    if (st == MLG_OK) st = mlg_laplacian_matvec(h, 0, MLG_OP_W, b, X, ldx, Y, ldy, flags);
+    std::string keep = mlg::g_last_error;
+    mlg_graph_destroy(h);
+    mlg::set_last_error(keep);
+    return st;
+}
+
+mlg_status mlg_lanczos_eigs(mlg_graph *h, int layer, double p, int k, int block, double tol,
+                            int max_restarts, uint64_t seed, const double *V0, double *evals,
+                            double *evecs, int64_t ldv, mlg_eig_info *info, int flags) {
+    mlg_status rc = MLG_OK;
+    mlg_status st = guard([&] {
+        MLG_REQUIRE(h && evals && evecs, MLG_ERR_ARG, "null argument");
+        Graph &g = h->g;
+        MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+        MLG_REQUIRE(p == 1.0, MLG_ERR_NOT_IMPL, "only the p = 1 power mean is implemented");
+        MLG_REQUIRE(k >= 1 && 2 * (int64_t)k <= g.n, MLG_ERR_ARG, "k must be in 1..n/2");
+        MLG_REQUIRE(block >= 1 && block <= 32, MLG_ERR_ARG, "block must be in 1..32");
+        MLG_REQUIRE(tol > 0, MLG_ERR_ARG, "tol must be > 0");
+        MLG_REQUIRE(max_restarts >= 0, MLG_ERR_ARG, "max_restarts must be >= 0");
+        MLG_REQUIRE(ldv >= g.n, MLG_ERR_ARG, "ldv < n");
+        const bool dev = (flags & MLG_DEVICE_PTRS) != 0;
+        DevBuf<double> dV0, dE;
+        const double *v0 = V0;
+        if (V0 && !dev) {
+            upload(dV0, V0, (size_t)g.n * block, false, g.stream);
+            v0 = dV0.p;
+        }
+        double *E = evecs;
+        int64_t lde = ldv;
+        if (!dev) {
+            dE.alloc((size_t)g.n * k);
+            E = dE.p;
+            lde = g.n;
+        }
+        std::vector<double> ev(k);
+        rc = lanczos_run(g, layer, k, block, tol, max_restarts, seed, v0, ev.data(), E, lde, info);
+        if (dev) {
+            MLG_HIP(hipMemcpyAsync(evals, ev.data(), 8 * k, hipMemcpyHostToDevice, g.stream));
+        } else {
+            std::copy(ev.begin(), ev.end(), evals);
+            MLG_HIP(hipMemcpy2DAsync(evecs, ldv * 8, E, g.n * 8, g.n * 8, k, hipMemcpyDeviceToHost,
+                                     g.stream));
+        }
+        MLG_HIP(hipStreamSynchronize(g.stream));
+    });
+    return st != MLG_OK ? st : rc;
+}
+
+mlg_status mlg_allen_cahn_ssl(int64_t n, int k, int m, const double *evals, const double *evecs,
+                              int64_t ldv, const int32_t *labels, const mlg_ac_params *prm,
+                              double *U, int32_t *pred, int *iters, int flags, void *stream) {
+    return guard([&] {
+        MLG_REQUIRE(evals && evecs && labels && prm && U && pred, MLG_ERR_ARG, "null argument");
+        MLG_REQUIRE(n >= 1 && k >= 1 && m >= 2 && m <= 64 && ldv >= n, MLG_ERR_ARG,
+                    "need n >= 1, k >= 1, 2 <= m <= 64, ldv >= n");
+        MLG_REQUIRE(prm->eps > 0 && prm->dt > 0 && prm->max_iter >= 1, MLG_ERR_ARG,
+                    "need eps > 0, dt > 0, max_iter >= 1");
+        hipStream_t s = make_stream(stream);
+        struct SD {
+            hipStream_t s;
+            bool own;
+            ~SD() { if (own) (void)hipStreamDestroy(s); }
+        } sd{s, stream == nullptr};
+        const bool dev = (flags & MLG_DEVICE_PTRS) != 0;
+        DevBuf<double> dE, dV, dU;
+        DevBuf<int32_t> dL, dP;
+        const double *E = evals, *V = evecs;
+        const int32_t *Lb = labels;
+        double *Uo = U;
+        int32_t *Po = pred;
+        int64_t ld = ldv;
+        if (!dev) {
+            upload(dE, evals, k, false, s);
+            dV.alloc((size_t)n * k);
+            MLG_HIP(hipMemcpy2DAsync(dV.p, n * 8, evecs, ldv * 8, n * 8, k, hipMemcpyHostToDevice, s));
+            upload(dL, labels, n, false, s);
+            dU.alloc((size_t)n * m);
+            dP.alloc(n);
+            E = dE.p;
+            V = dV.p;
+            Lb = dL.p;
+            Uo = dU.p;
+            Po = dP.p;
+            ld = n;
+        }
+        int it = 0;
+        ac_run(n, k, m, E, V, ld, Lb, *prm, Uo, Po, &it, s);
+        if (!dev) {
+            MLG_HIP(hipMemcpyAsync(U, Uo, sizeof(double) * n * m, hipMemcpyDeviceToHost, s));
+            MLG_HIP(hipMemcpyAsync(pred, Po, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        }
+        MLG_HIP(hipStreamSynchronize(s));
+        if (iters) *iters = it;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,627 @@
+// FP64 block thick-restart Lanczos for the k largest eigenpairs of
+// A = D^-1/2 W D^-1/2 (one layer) or I - L_1 = (1/T) sum_t D_t^-1/2 W_t D_t^-1/2,
+// returned as the k smallest of L_sym resp. L_1 with lambda = 1 - mu (Sec. 3;
+// Algorithm 2 step 1).  The paper used MATLAB's Krylov-Schur; for a symmetric
+// operator, thick restart with Ritz vectors is the same method.
+//
+// State kept between steps:  A V_m = V_m H_m + Q S,  V_m^T Q = 0,
+//   V_m  n x m orthonormal basis, H_m = V_m^T A V_m (m x m),
+//   Q    n x b next block, S (b x m) its coupling.
+// Expansion:  W = A Q; two passes of classical Gram-Schmidt against [V_m, Q]
+//   (CGS2, full reorthogonalisation) give the new column block of H; a
+//   Cholesky QR (twice) of W gives the next Q and its coupling R.
+// Restart:  H = Y Theta Y^T (one-workgroup Jacobi); residual of Ritz pair i is
+//   ||S y_i||; the k+b largest Ritz pairs are kept: V <- V Y_keep,
+//   H <- Theta_keep, S <- S Y_keep.
+// Every reduction runs in a fixed order (chunk partials, then a sequential
+// sum), so results are reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "internal.h"
+
+namespace mlg {
+
+constexpr int kTnMaxP = 256;   // rows of C = A^T B
+constexpr int kTnMaxQ = 32;    // columns of C
+constexpr int kRB = 16;        // rows per LDS batch
+
+// ---- C = A^T B, partials per row chunk --------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_tn_part(int64_t n, int p, int q,
+                                                      const double *__restrict__ A, int64_t lda,
+                                                      const double *__restrict__ B, int64_t ldb,
+                                                      int64_t rc, double *__restrict__ part) {
+    __shared__ double As[kRB][kTnMaxP];
+    __shared__ double Bs[kRB][kTnMaxQ];
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * rc;
+    const int64_t r1 = (r0 + rc < n) ? r0 + rc : n;
+    double acc[16][2];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) { acc[a][0] = 0.0; acc[a][1] = 0.0; }
+    for (int64_t rb = r0; rb < r1; rb += kRB) {
+        const int cnt = (int)((r1 - rb) < kRB ? (r1 - rb) : kRB);
+        __syncthreads();
+        for (int e = tid; e < kRB * p; e += 256) {
+            int rr = e % kRB, i = e / kRB;
+            As[rr][i] = rr < cnt ? A[rb + rr + (int64_t)i * lda] : 0.0;
+        }
+        for (int e = tid; e < kRB * q; e += 256) {
+            int rr = e % kRB, j = e / kRB;
+            Bs[rr][j] = rr < cnt ? B[rb + rr + (int64_t)j * ldb] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < kRB; ++rr) {
+            const double b0 = Bs[rr][tx], b1 = Bs[rr][tx + 16];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                const double av = As[rr][ty + 16 * a];
+                acc[a][0] += av * b0;
+                acc[a][1] += av * b1;
+            }
+        }
+    }
+    double *o = part + (int64_t)blockIdx.x * p * q;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+        const int i = ty + 16 * a;
+        if (i < p) {
+            if (tx < q) o[i * q + tx] = acc[a][0];
+            if (tx + 16 < q) o[i * q + tx + 16] = acc[a][1];
+        }
+    }
+}
+
+// C[e] = sum_c part[c][e], c ascending.
+__global__ void k_sum_parts(int nparts, int total, const double *__restrict__ part,
+                            double *__restrict__ C) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    double s = 0.0;
+    for (int c = 0; c < nparts; ++c) s += part[(int64_t)c * total + e];
+    C[e] = s;
+}
+
+// Out[:, j] (=, +=, -=) sum_i A[:, i] C[i][j] for the column group in blockIdx.y
+// (C row-major p x q).  mode 0: =, 1: -=.
+__global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int p, int q,
+                                                 const double *__restrict__ A, int64_t lda,
+                                                 const double *__restrict__ C,
+                                                 double *__restrict__ Out, int64_t ldo, int mode) {
+    __shared__ double Cs[kTnMaxP * 32];
+    const int j0 = blockIdx.y * 32;
+    const int qq = (q - j0) < 32 ? (q - j0) : 32;
+    for (int e = threadIdx.x; e < p * 32; e += 256) {
+        int i = e / 32, j = e % 32;
+        Cs[e] = j < qq ? C[i * q + j0 + j] : 0.0;
+    }
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    double acc[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+    for (int i = 0; i < p; ++i) {
+        const double a = A[r + (int64_t)i * lda];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) acc[j] += a * Cs[i * 32 + j];
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (j < qq) {
+            double *o = Out + r + (int64_t)(j0 + j) * ldo;
+            *o = mode ? *o - acc[j] : acc[j];
+        }
+    }
+}
+
+// W[r, :] <- W[r, :] M (q x q row-major), in place per row.
+__global__ void k_rowmul(int64_t n, int q, double *__restrict__ W, int64_t ldw,
+                         const double *__restrict__ M) {
+    __shared__ double Ms[kTnMaxQ * kTnMaxQ];
+    for (int e = threadIdx.x; e < q * q; e += blockDim.x) Ms[e] = M[e];
+    __syncthreads();
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double w[kTnMaxQ], o[kTnMaxQ];
+#pragma unroll
+    for (int i = 0; i < kTnMaxQ; ++i) w[i] = i < q ? W[r + (int64_t)i * ldw] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kTnMaxQ; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < q; ++i) s += w[i] * Ms[i * kTnMaxQ + j];
+        o[j] = s;
+    }
+    for (int j = 0; j < q; ++j) W[r + (int64_t)j * ldw] = o[j];
+}
+
+// Cholesky G = R^T R (G q x q row-major, symmetric); writes Rinv (q x q
+// row-major, upper) into out[0..q*q) and R into out[q*q..2q*q); flag = 1 if a
+// pivot is not positive relative to the largest diagonal.
+__global__ void k_chol_inv(int q, const double *__restrict__ G, double *__restrict__ out,
+                           int *flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double R[kTnMaxQ][kTnMaxQ], Ri[kTnMaxQ][kTnMaxQ];
+    double dmax = 0.0;
+    for (int i = 0; i < q; ++i) dmax = fmax(dmax, G[i * q + i]);
+    int bad = !(dmax > 0.0);
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) { R[i][j] = 0.0; Ri[i][j] = 0.0; }
+    for (int j = 0; j < q && !bad; ++j) {
+        double s = G[j * q + j];
+        for (int k = 0; k < j; ++k) s -= R[k][j] * R[k][j];
+        if (!(s > 1e-28 * dmax)) { bad = 1; break; }
+        const double rjj = sqrt(s);
+        R[j][j] = rjj;
+        for (int i = j + 1; i < q; ++i) {
+            double t = G[j * q + i];
+            for (int k = 0; k < j; ++k) t -= R[k][j] * R[k][i];
+            R[j][i] = t / rjj;
+        }
+    }
+    if (!bad) {
+        for (int j = q - 1; j >= 0; --j) {
+            Ri[j][j] = 1.0 / R[j][j];
+            for (int i = j - 1; i >= 0; --i) {
+                double s = 0.0;
+                for (int k = i + 1; k <= j; ++k) s += R[i][k] * Ri[k][j];
+                Ri[i][j] = -s / R[i][i];
+            }
+        }
+    }
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+            out[i * q + j] = Ri[i][j];
+            out[q * q + i * q + j] = R[i][j];
+        }
+    flag[0] = bad;
+}
+
+// C (m+b) x b row-major from CGS -> H columns [m, m+b) and rows; the diagonal
+// block is symmetrised.
+__global__ void k_store_H(int mtot, int m, int b, const double *__restrict__ C,
+                          double *__restrict__ H, int ldh) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= mtot * b) return;
+    const int i = e / b, j = e % b;
+    double v = C[i * b + j];
+    if (i >= m) v = 0.5 * (v + C[(m + j) * b + (i - m)]);
+    H[(int64_t)i * ldh + m + j] = v;
+    H[(int64_t)(m + j) * ldh + i] = v;
+}
+
+// R (b x b, upper, row-major) -> coupling rows H[m+b.., m..] = R, and the
+// transpose.
+__global__ void k_store_R(int m, int b, const double *__restrict__ R, double *__restrict__ H,
+                          int ldh) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= b * b) return;
+    const int i = e / b, j = e % b;
+    const double v = R[i * b + j];
+    H[(int64_t)(m + b + i) * ldh + m + j] = v;
+    H[(int64_t)(m + j) * ldh + m + b + i] = v;
+}
+
+// Parallel cyclic Jacobi (round-robin pairing) for a symmetric m x m matrix
+// in one workgroup.  A (ldh) is overwritten: diag = eigenvalues; Y (m x m,
+// row-major, column c = eigenvector c).
+__global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ A, int lda,
+                                                double *__restrict__ Y, int max_sweeps) {
+    __shared__ double cs[kTnMaxP / 2 + 1], sn[kTnMaxP / 2 + 1];
+    __shared__ int pp[kTnMaxP / 2 + 1], qq[kTnMaxP / 2 + 1];
+    __shared__ int rotated;
+    const int tid = threadIdx.x;
+    const int me = m + (m & 1);  // even, with a dummy index m if odd
+    for (int e = tid; e < m * m; e += 256) Y[e] = (e / m == e % m) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        for (int round = 0; round < me - 1; ++round) {
+            // pairs of the round-robin schedule: index me-1 fixed, others rotate
+            for (int k = tid; k < me / 2; k += 256) {
+                int a, b;
+                if (k == 0) {
+                    a = me - 1;
+                    b = round;
+                } else {
+                    a = (round + k) % (me - 1);
+                    b = (round - k + (me - 1)) % (me - 1);
+                }
+                int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
+                if (q < m) {
+                    const double apq = A[p * lda + q];
+                    const double app = A[p * lda + p], aqq = A[q * lda + q];
+                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+                        const double th = (aqq - app) / (2.0 * apq);
+                        const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                        rotated = 1;
+                    }
+                }
+                pp[k] = p;
+                qq[k] = q;
+                cs[k] = c;
+                sn[k] = s;
+            }
+            __syncthreads();
+            // columns: A <- A J
+            for (int e = tid; e < (me / 2) * m; e += 256) {
+                int k = e / m, r = e % m;
+                int p = pp[k], q = qq[k];
+                if (q >= m || sn[k] == 0.0) continue;
+                double c = cs[k], s = sn[k];
+                double ap = A[r * lda + p], aq = A[r * lda + q];
+                A[r * lda + p] = c * ap - s * aq;
+                A[r * lda + q] = s * ap + c * aq;
+                double yp = Y[r * m + p], yq = Y[r * m + q];
+                Y[r * m + p] = c * yp - s * yq;
+                Y[r * m + q] = s * yp + c * yq;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int e = tid; e < (me / 2) * m; e += 256) {
+                int k = e / m, cidx = e % m;
+                int p = pp[k], q = qq[k];
+                if (q >= m || sn[k] == 0.0) continue;
+                double c = cs[k], s = sn[k];
+                double ap = A[p * lda + cidx], aq = A[q * lda + cidx];
+                A[p * lda + cidx] = c * ap - s * aq;
+                A[q * lda + cidx] = s * ap + c * aq;
+            }
+            __syncthreads();
+        }
+        if (!rotated) break;
+        __syncthreads();
+    }
+}
+
+// Residual norms ||S y_c|| for the selected Ritz columns sel[0..ns).
+__global__ void k_ritz_resid(int m, int b, const double *__restrict__ S, int lds,
+                             const double *__restrict__ Y, const int *__restrict__ sel, int ns,
+                             double *__restrict__ res) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ns) return;
+    const int col = sel[c];
+    double acc = 0.0;
+    for (int r = 0; r < b; ++r) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += S[r * lds + i] * Y[i * m + col];
+        acc += s * s;
+    }
+    res[c] = sqrt(acc);
+}
+
+// Ysel (m x ns row-major) = Y[:, sel].
+__global__ void k_select_cols(int m, const double *__restrict__ Y, const int *__restrict__ sel,
+                              int ns, double *__restrict__ Ys) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * ns) return;
+    const int i = e / ns, c = e % ns;
+    Ys[e] = Y[i * m + sel[c]];
+}
+
+// S_new (b x ns) = S (b x m) Ysel; H <- diag(theta_sel).
+__global__ void k_restart_small(int m, int b, const double *__restrict__ S, int lds,
+                                const double *__restrict__ Ys, int ns,
+                                const double *__restrict__ theta, double *__restrict__ Snew,
+                                double *__restrict__ H, int ldh) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < b * ns) {
+        const int r = e / ns, c = e % ns;
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += S[r * lds + i] * Ys[i * ns + c];
+        Snew[r * lds + c] = s;
+    }
+    if (e < ldh * ldh) {
+        const int i = e / ldh, j = e % ldh;
+        H[e] = (i == j && i < ns) ? theta[i] : 0.0;
+    }
+}
+
+// Coupling after an expansion: S = [0 ... 0 R] with R at columns [m, m+b).
+__global__ void k_set_S(int mnew, int b, const double *__restrict__ R, double *__restrict__ S,
+                        int lds) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= b * mnew) return;
+    const int r = e / mnew, c = e % mnew;
+    const int m = mnew - b;
+    S[r * lds + c] = (c >= m) ? R[r * b + (c - m)] : 0.0;
+}
+
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// N(0,1) draws by Box-Muller from two SplitMix64 outputs per element.
+__global__ void k_randn(uint64_t seed, int64_t n, int b, double *__restrict__ X, int64_t ldx,
+                        int64_t offset) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * b) return;
+    const int64_t c = offset + e;
+    const uint64_t z1 = splitmix64(seed + 2ull * (uint64_t)c * 0x9E3779B97F4A7C15ull);
+    const uint64_t z2 = splitmix64(seed + (2ull * (uint64_t)c + 1ull) * 0x9E3779B97F4A7C15ull);
+    const double u1 = ((double)(z1 >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(z2 >> 11) * 0x1.0p-53;
+    const int64_t i = e % n, j = e / n;
+    X[i + j * ldx] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+// Sign convention: the largest-magnitude entry of each column is positive
+// (lowest index on ties).
+__global__ void k_fix_sign(int64_t n, double *__restrict__ V, int64_t ldv) {
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    double *col = V + (int64_t)blockIdx.x * ldv;
+    double best = -1.0;
+    int64_t bi = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        double a = fabs(col[i]);
+        if (a > best) { best = a; bi = i; }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            double a = sv[threadIdx.x + off];
+            int64_t ai = si[threadIdx.x + off];
+            if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
+                sv[threadIdx.x] = a;
+                si[threadIdx.x] = ai;
+            }
+        }
+        __syncthreads();
+    }
+    const bool flip = col[si[0]] < 0.0;
+    if (!flip) return;
+    for (int64_t i = threadIdx.x; i < n; i += 256) col[i] = -col[i];
+}
+
+__global__ void k_add(int cnt, double *a, const double *b) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < cnt) a[e] += b[e];
+}
+
+// ------------------------------------------------------------------------------
+struct Lz {
+    hipStream_t s;
+    int64_t n;
+    DevBuf<double> part, C, C2, G, RR;
+    DevBuf<int> flag;
+    int nchunks = 0;
+    int64_t rc = 0;
+    void setup(int64_t n_, hipStream_t s_) {
+        n = n_;
+        s = s_;
+        rc = std::max<int64_t>(1024, (n + 511) / 512);
+        rc = (rc + kRB - 1) / kRB * kRB;
+        nchunks = ceil_div(n, rc);
+        part.alloc((size_t)nchunks * kTnMaxP * kTnMaxQ);
+        C.alloc(kTnMaxP * kTnMaxQ);
+        C2.alloc(kTnMaxP * kTnMaxQ);
+        G.alloc(kTnMaxQ * kTnMaxQ);
+        RR.alloc(2 * kTnMaxQ * kTnMaxQ);
+        flag.alloc(1);
+    }
+    // Cout (p x q row-major) = A^T B
+    void tn(int p, int q, const double *A, int64_t lda, const double *B, int64_t ldb, double *Cout) {
+        hipLaunchKernelGGL(k_gemm_tn_part, dim3(nchunks), dim3(256), 0, s, n, p, q, A, lda, B, ldb, rc,
+                           part.p);
+        MLG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(p * q, 256)), dim3(256), 0, s, nchunks, p * q,
+                           part.p, Cout);
+        MLG_LAUNCH_CHECK();
+    }
+    void nn(int p, int q, const double *A, int64_t lda, const double *Cm, double *Out, int64_t ldo,
+            int mode) {
+        hipLaunchKernelGGL(k_gemm_nn, dim3(ceil_div(n, 256), ceil_div(q, 32)), dim3(256), 0, s, n, p,
+                           q, A, lda, Cm, Out, ldo, mode);
+        MLG_LAUNCH_CHECK();
+    }
+    // W (n x q) -> orthonormal, R (q x q upper) with W_in = W_out R.  Returns
+    // false if W is numerically rank deficient.
+    bool cholqr2(int q, double *W, int64_t ldw, std::vector<double> &Rhost) {
+        std::vector<double> R1(q * q), R2(q * q);
+        for (int pass = 0; pass < 2; ++pass) {
+            tn(q, q, W, ldw, W, ldw, G.p);
+            hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, s, q, G.p, RR.p, flag.p);
+            MLG_LAUNCH_CHECK();
+            int bad = 0;
+            MLG_HIP(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, s));
+            MLG_HIP(hipMemcpyAsync(pass == 0 ? R1.data() : R2.data(), RR.p + q * q, 8 * q * q,
+                                   hipMemcpyDeviceToHost, s));
+            MLG_HIP(hipStreamSynchronize(s));
+            if (bad) return false;
+            hipLaunchKernelGGL(k_rowmul, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, q, W, ldw, RR.p);
+            MLG_LAUNCH_CHECK();
+        }
+        // R = R2 R1 (upper triangular)
+        Rhost.assign(q * q, 0.0);
+        for (int i = 0; i < q; ++i)
+            for (int j = i; j < q; ++j) {
+                double acc = 0.0;
+                for (int k = i; k <= j; ++k) acc += R2[i * q + k] * R1[k * q + j];
+                Rhost[i * q + j] = acc;
+            }
+        return true;
+    }
+    // CGS2 of W (n x b) against V (n x p): W -= V (V^T W), twice; Csum = total.
+    void cgs2(int p, int b, const double *V, int64_t ldv, double *W, int64_t ldw) {
+        tn(p, b, V, ldv, W, ldw, C.p);
+        nn(p, b, V, ldv, C.p, W, ldw, 1);
+        tn(p, b, V, ldv, W, ldw, C2.p);
+        nn(p, b, V, ldv, C2.p, W, ldw, 1);
+        hipLaunchKernelGGL(k_add, dim3(ceil_div(p * b, 256)), dim3(256), 0, s, p * b, C.p, C2.p);
+        MLG_LAUNCH_CHECK();
+    }
+};
+
+mlg_status lanczos_run(Graph &g, int layer, int k, int b, double tol, int max_restarts,
+                       uint64_t seed, const double *V0, double *evals, double *evecs, int64_t ldv,
+                       mlg_eig_info *info) {
+    const int64_t n = g.n;
+    hipStream_t s = g.stream;
+    int mmax = std::max(2 * k, k + 3 * b);
+    mmax = (mmax + b - 1) / b * b;
+    while (mmax + b > kTnMaxP) mmax -= b;
+    MLG_REQUIRE(mmax >= k + b, MLG_ERR_ARG, "k + 2 block exceeds the basis limit of 256 columns");
+    MLG_REQUIRE((int64_t)mmax + b <= n, MLG_ERR_ARG, "basis larger than n");
+    Lz z;
+    z.setup(n, s);
+    DevBuf<double> V((size_t)n * (mmax + b)), W((size_t)n * b), Hd((size_t)kTnMaxP * kTnMaxP),
+        Ad((size_t)kTnMaxP * kTnMaxP), Yd((size_t)kTnMaxP * kTnMaxP), Sd((size_t)kTnMaxQ * kTnMaxP),
+        S2((size_t)kTnMaxQ * kTnMaxP), Ysel((size_t)kTnMaxP * kTnMaxP), theta(kTnMaxP),
+        res(kTnMaxP), Rd(kTnMaxQ * kTnMaxQ);
+    DevBuf<int> seld(kTnMaxP);
+    const int ldh = kTnMaxP;
+    MLG_HIP(hipMemsetAsync(Hd.p, 0, sizeof(double) * ldh * ldh, s));
+    MLG_HIP(hipMemsetAsync(Sd.p, 0, sizeof(double) * kTnMaxQ * kTnMaxP, s));
+    // start block
+    if (V0)
+        MLG_HIP(hipMemcpyAsync(V.p, V0, sizeof(double) * n * b, hipMemcpyDeviceToDevice, s));
+    else {
+        hipLaunchKernelGGL(k_randn, dim3(ceil_div(n * b, 256)), dim3(256), 0, s, seed, n, b, V.p, n,
+                           (int64_t)0);
+        MLG_LAUNCH_CHECK();
+    }
+    std::vector<double> Rh;
+    int64_t rnd_off = n * b;
+    auto orthonormalize_new = [&](double *blk, int m_before) {
+        // blk (n x b) against V[:, :m_before], then CholQR2; random refill on
+        // breakdown (coupling of the refilled block is zero).
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            if (m_before > 0) z.cgs2(m_before, b, V.p, n, blk, n);
+            if (z.cholqr2(b, blk, n, Rh)) return attempt == 0;
+            hipLaunchKernelGGL(k_randn, dim3(ceil_div(n * b, 256)), dim3(256), 0, s, seed, n, b, blk,
+                               n, rnd_off);
+            MLG_LAUNCH_CHECK();
+            rnd_off += n * b;
+        }
+        throw Error(MLG_ERR_HIP, "Lanczos: could not extend the basis (rank deficiency)");
+    };
+    orthonormalize_new(V.p, 0);
+    int m = 0;  // basis columns with complete H; Q = V[:, m : m+b]
+    int iters = 0, restarts = 0, matvecs = 0;
+    std::vector<double> th(kTnMaxP), rs(kTnMaxP);
+    std::vector<int> order(kTnMaxP);
+    mlg_status st = MLG_WARN_NOT_CONVERGED;
+    int nconv = 0;
+    double maxres = 0.0;
+    for (;;) {
+        // ---- expand to mmax columns ----
+        while (m + b <= mmax) {
+            double *Q = V.p + (int64_t)m * n;
+            graph_matvec_enqueue(g, layer, MLG_OP_NADJ, b, Q, n, W.p, n, nullptr);
+            matvecs += b;
+            ++iters;
+            const int mt = m + b;
+            z.cgs2(mt, b, V.p, n, W.p, n);
+            hipLaunchKernelGGL(k_store_H, dim3(ceil_div(mt * b, 256)), dim3(256), 0, s, mt, m, b, z.C.p,
+                               Hd.p, ldh);
+            MLG_LAUNCH_CHECK();
+            // next block
+            double *Qn = V.p + (int64_t)mt * n;
+            MLG_HIP(hipMemcpyAsync(Qn, W.p, sizeof(double) * n * b, hipMemcpyDeviceToDevice, s));
+            bool clean = false;
+            if (z.cholqr2(b, Qn, n, Rh)) {
+                clean = true;
+            } else {
+                orthonormalize_new(Qn, mt);
+                std::fill(Rh.begin(), Rh.end(), 0.0);
+                Rh.resize(b * b, 0.0);
+            }
+            (void)clean;
+            MLG_HIP(hipMemcpyAsync(Rd.p, Rh.data(), 8 * b * b, hipMemcpyHostToDevice, s));
+            if (mt + b <= mmax) {
+                hipLaunchKernelGGL(k_store_R, dim3(ceil_div(b * b, 256)), dim3(256), 0, s, m, b, Rd.p,
+                                   Hd.p, ldh);
+                MLG_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_set_S, dim3(ceil_div(b * mt, 256)), dim3(256), 0, s, mt, b, Rd.p, Sd.p,
+                               kTnMaxP);
+            MLG_LAUNCH_CHECK();
+            m = mt;
+            MLG_HIP(hipStreamSynchronize(s));
+        }
+        // ---- Rayleigh-Ritz on H (m x m) ----
+        MLG_HIP(hipMemcpy2DAsync(Ad.p, 8 * ldh, Hd.p, 8 * ldh, 8 * m, m, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, m, Ad.p, ldh, Yd.p, 40);
+        MLG_LAUNCH_CHECK();
+        std::vector<double> Ah((size_t)m * ldh);
+        MLG_HIP(hipMemcpy2DAsync(Ah.data(), 8 * ldh, Ad.p, 8 * ldh, 8 * m, m, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < m; ++i) th[i] = Ah[(size_t)i * ldh + i];
+        std::iota(order.begin(), order.begin() + m, 0);
+        std::stable_sort(order.begin(), order.begin() + m,
+                         [&](int a, int c) { return th[a] > th[c]; });
+        const int keep = std::min(m - b, k + b);
+        MLG_HIP(hipMemcpyAsync(seld.p, order.data(), 4 * keep, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_ritz_resid, dim3(ceil_div(keep, 64)), dim3(64), 0, s, m, b, Sd.p, kTnMaxP,
+                           Yd.p, seld.p, keep, res.p);
+        MLG_LAUNCH_CHECK();
+        MLG_HIP(hipMemcpyAsync(rs.data(), res.p, 8 * keep, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        nconv = 0;
+        maxres = 0.0;
+        for (int i = 0; i < k; ++i) {
+            if (rs[i] <= tol) ++nconv;
+            maxres = std::max(maxres, rs[i]);
+        }
+        const bool done = nconv == k || restarts >= max_restarts;
+        if (done) {
+            // Ritz vectors of the k wanted pairs, in descending mu
+            hipLaunchKernelGGL(k_select_cols, dim3(ceil_div(m * k, 256)), dim3(256), 0, s, m, Yd.p, seld.p,
+                               k, Ysel.p);
+            MLG_LAUNCH_CHECK();
+            z.nn(m, k, V.p, n, Ysel.p, evecs, ldv, 0);
+            hipLaunchKernelGGL(k_fix_sign, dim3(k), dim3(256), 0, s, n, evecs, ldv);
+            MLG_LAUNCH_CHECK();
+            for (int i = 0; i < k; ++i) evals[i] = 1.0 - th[order[i]];
+            st = nconv == k ? MLG_OK : MLG_WARN_NOT_CONVERGED;
+            MLG_HIP(hipStreamSynchronize(s));
+            break;
+        }
+        // ---- thick restart: keep the `keep` largest Ritz pairs ----
+        ++restarts;
+        std::vector<double> thk(keep);
+        for (int i = 0; i < keep; ++i) thk[i] = th[order[i]];
+        MLG_HIP(hipMemcpyAsync(theta.p, thk.data(), 8 * keep, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_select_cols, dim3(ceil_div(m * keep, 256)), dim3(256), 0, s, m, Yd.p,
+                           seld.p, keep, Ysel.p);
+        MLG_LAUNCH_CHECK();
+        // V[:, :keep] = V[:, :m] Ysel via W-sized chunks of columns into a temp
+        DevBuf<double> tmp((size_t)n * keep);
+        z.nn(m, keep, V.p, n, Ysel.p, tmp.p, n, 0);
+        MLG_HIP(hipMemcpyAsync(V.p, tmp.p, sizeof(double) * n * keep, hipMemcpyDeviceToDevice, s));
+        // move Q = V[:, m : m+b] to V[:, keep : keep+b]
+        MLG_HIP(hipMemcpyAsync(V.p + (int64_t)keep * n, V.p + (int64_t)m * n, sizeof(double) * n * b,
+                               hipMemcpyDeviceToDevice, s));
+        const int tot = std::max(b * keep, ldh * ldh);
+        hipLaunchKernelGGL(k_restart_small, dim3(ceil_div(tot, 256)), dim3(256), 0, s, m, b, Sd.p,
+                           kTnMaxP, Ysel.p, keep, theta.p, S2.p, Hd.p, ldh);
+        MLG_LAUNCH_CHECK();
+        // H's arrow: rows/cols [keep, keep+b) couple through S^T; written on
+        // the next expansion by CGS (C[0:keep] = S^T up to rounding).
+        MLG_HIP(hipMemcpyAsync(Sd.p, S2.p, sizeof(double) * kTnMaxQ * kTnMaxP, hipMemcpyDeviceToDevice,
+                               s));
+        m = keep;
+        MLG_HIP(hipStreamSynchronize(s));
+    }
+    if (info) {
+        info->iters = iters;
+        info->restarts = restarts;
+        info->matvecs = matvecs;
+        info->nconv = nconv;
+        info->max_resid = maxres;
+    }
+    return st;
+}
+
+}  // namespace mlg
