@@ -74,7 +74,10 @@ typedef enum {
  *              interpolation or direct tiles).  Degrees, D^-1/2 scaling and
  *              layer aggregation are always FP64.
  *   N          NFFT bandwidth: frequencies l in {-N/2..N/2}^d are kept; the
- *              FFT grid has 2N points per dimension.  Power of two, 8..256.
+ *              FFT grid has 2N points per dimension.  Power of two, 8..256,
+ *              or 0: the smallest power of two >= 16 whose dropped Gaussian
+ *              tail 2 d sqrt(pi) s exp(-(pi s N / 2)^2) (s = scaled sigma)
+ *              is below 1e-8 (precision 32) or 1e-13 (precision 64).
  *   window     window support w in grid points, even, 2..16, with
  *              bin + w/2 <= N/2 (0 = 6 for precision 32, 12 for precision 64).
  *   eps_B      regularisation length of the periodised kernel, 0 < eps_B < 1/4.

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int p, int q,
 __global__ void k_rowmul(int64_t n, int q, double *__restrict__ W, int64_t ldw,
                          const double *__restrict__ M) {
     __shared__ double Ms[kTnMaxQ * kTnMaxQ];
-    for (int e = threadIdx.x; e < q * q; e += blockDim.x) Ms[e] = M[e];
+    for (int e = threadIdx.x; e < q * q; e += blockDim.x) Ms[(e / q) * kTnMaxQ + e % q] = M[e];
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;

@@ -335,7 +335,7 @@ __device__ inline void stage_weights(const TaskGeom &g, const T *__restrict__ u,
 template <class T, int D>
 __global__ __launch_bounds__(256) void k_spread(TaskGeom g, const int4 *__restrict__ tasks,
                                                 const T *__restrict__ u, const T *__restrict__ Zs,
-                                                T beta, int chs, T *__restrict__ patch) {
+                                                T beta, int chs, int vg, T *__restrict__ patch) {
     extern __shared__ unsigned char smem_raw[];
     T *wts = reinterpret_cast<T *>(smem_raw);
     T *zv = wts + (size_t)chs * D * g.P;
@@ -349,9 +349,10 @@ __global__ __launch_bounds__(256) void k_spread(TaskGeom g, const int4 *__restri
     int PD = P;
     for (int t = 1; t < D; ++t) PD *= P;
     const int bs = g.bs;
-    const int v = tid % bs;
-    const int ostep = 256 / bs;
-    const int o0 = tid / bs;
+    // this workgroup handles vectors [blockIdx.y*vg, +vg) of the block
+    const int v = blockIdx.y * vg + tid % vg;
+    const int ostep = 256 / vg;
+    const int o0 = tid / vg;
     int qoff[kMaxSlots];
     T acc[kMaxSlots];
 #pragma unroll
@@ -562,7 +563,7 @@ template <class T, int D>
 __global__ __launch_bounds__(256) void k_interp(TaskGeom g, const int4 *__restrict__ tasks,
                                                 const T *__restrict__ u,
                                                 const T *__restrict__ grid, int bg, T beta,
-                                                int chs, T *__restrict__ Fs) {
+                                                int chs, int vg, T *__restrict__ Fs) {
     extern __shared__ unsigned char smem_raw[];
     T *wts = reinterpret_cast<T *>(smem_raw);
     T *red = wts + (size_t)chs * D * g.P;
@@ -576,9 +577,10 @@ __global__ __launch_bounds__(256) void k_interp(TaskGeom g, const int4 *__restri
     int PD = P;
     for (int t = 1; t < D; ++t) PD *= P;
     const int bs = g.bs;
-    const int v = tid % bs;
-    const int ostep = 256 / bs;
-    const int o0 = tid / bs;
+    const int v0 = blockIdx.y * vg;
+    const int v = v0 + tid % vg;
+    const int ostep = 256 / vg;
+    const int o0 = tid / vg;
     int qoff[kMaxSlots];
     T h[kMaxSlots];
 #pragma unroll
@@ -614,14 +616,15 @@ __global__ __launch_bounds__(256) void k_interp(TaskGeom g, const int4 *__restri
                     part += wgt * h[j];
                 }
             }
-            for (int off = bs; off < 64; off <<= 1) part += __shfl_xor(part, off, 64);
-            if (lane < bs) red[((size_t)wv * chs + pt) * bs + lane] = part;
+            for (int off = vg; off < 64; off <<= 1) part += __shfl_xor(part, off, 64);
+            if (lane < vg) red[((size_t)wv * chs + pt) * vg + lane] = part;
         }
         __syncthreads();
-        for (int e = tid; e < cnt * bs; e += 256) {
+        for (int e = tid; e < cnt * vg; e += 256) {
             T s = red[e];
-            for (int c = 1; c < kWaves; ++c) s += red[(size_t)c * chs * bs + e];
-            Fs[first * bs + e] = s;
+            for (int c = 1; c < kWaves; ++c) s += red[(size_t)c * chs * vg + e];
+            const int pt = e / vg, vv = e - pt * vg;
+            Fs[(first + pt) * bs + v0 + vv] = s;
         }
     }
 }
@@ -716,6 +719,20 @@ static KRParams make_kr(double sigma_s, double eps_B, int p) {
     return kr;
 }
 
+// Smallest power-of-two bandwidth (16..256) whose dropped Gaussian Fourier
+// tail, about 2 d sqrt(pi) sigma exp(-pi^2 sigma^2 N^2 / 4), is below a
+// precision-dependent bound.
+static int auto_bandwidth(double sigma_s, int d, int prec) {
+    const double tol = prec == 64 ? 1e-13 : 1e-8;
+    int N = 16;
+    while (N < 256) {
+        double x = M_PI * sigma_s * N / 2.0;
+        if (2.0 * d * std::sqrt(M_PI) * sigma_s * std::exp(-x * x) <= tol) break;
+        N *= 2;
+    }
+    return N;
+}
+
 template <class F>
 static void with_temp(DevBuf<char> &tmp, size_t bytes, F f) {
     tmp.ensure(bytes ? bytes : 1);
@@ -727,20 +744,15 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     const int d = L.d;
     const int64_t n = L.n;
     MLG_REQUIRE(d >= 1 && d <= 3, MLG_ERR_RANGE, "NFFT layers need d in 1..3");
-    MLG_REQUIRE(is_pow2(L.kp.N) && L.kp.N >= 8 && L.kp.N <= 256, MLG_ERR_RANGE,
-                "NFFT bandwidth N must be a power of two in 8..256");
+    MLG_REQUIRE(L.kp.N == 0 || (is_pow2(L.kp.N) && L.kp.N >= 8 && L.kp.N <= 256), MLG_ERR_RANGE,
+                "NFFT bandwidth N must be 0 (automatic) or a power of two in 8..256");
     MLG_REQUIRE(L.kp.eps_B > 0.0 && L.kp.eps_B < 0.25, MLG_ERR_RANGE, "eps_B must be in (0, 1/4)");
     MLG_REQUIRE(L.kp.p_reg >= 1 && L.kp.p_reg <= 12, MLG_ERR_RANGE, "p_reg must be in 1..12");
     MLG_REQUIRE(n < (int64_t)1 << 31, MLG_ERR_RANGE, "NFFT layers need n < 2^31");
     P.d = d;
     P.n = n;
-    P.N = L.kp.N;
-    P.nos = 2 * P.N;
     P.B = L.kp.bin > 0 ? L.kp.bin : 1;
     MLG_REQUIRE(P.B == 1 || P.B == 2 || P.B == 4, MLG_ERR_RANGE, "bin must be 1, 2 or 4");
-    P.nb = P.nos / P.B;
-    P.nbins = 1;
-    for (int t = 0; t < d; ++t) P.nbins *= P.nb;
     P.eps_B = L.kp.eps_B;
     P.p_reg = L.kp.p_reg;
 
@@ -784,6 +796,11 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     const double rho = 0.25 - 0.5 * P.eps_B;
     P.scale = R > 0 ? rho / R : 1.0;
     P.sigma_s = P.scale * L.sigma;
+    P.N = L.kp.N > 0 ? L.kp.N : auto_bandwidth(P.sigma_s, d, L.kp.precision);
+    P.nos = 2 * P.N;
+    P.nb = P.nos / P.B;
+    P.nbins = 1;
+    for (int t = 0; t < d; ++t) P.nbins *= P.nb;
 
     // --- grid coordinates, keys, sort ---
     DevBuf<double> uun((size_t)d * n);
@@ -994,9 +1011,14 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     g.n = P.n;
     int PD = 1;
     for (int t = 0; t < D; ++t) PD *= g.P;
-    MLG_REQUIRE((int64_t)PD * bs <= (int64_t)kMaxSlots * 256, MLG_ERR_RANGE,
-                "patch too large for one task (reduce window, bin or block)");
     MLG_REQUIRE(256 % bs == 0, MLG_ERR_ARG, "block stride must divide 256");
+    // vectors per workgroup: the patch slots of one group must fit the
+    // register budget of 256 threads
+    int vg = bs;
+    while (vg > 1 && (int64_t)PD * vg > (int64_t)kMaxSlots * 256) vg >>= 1;
+    MLG_REQUIRE((int64_t)PD * vg <= (int64_t)kMaxSlots * 256, MLG_ERR_RANGE,
+                "patch too large for one task (reduce window or bin)");
+    const int ngroups = bs / vg;
     const int bg = bs < 2 ? 2 : bs;
     const T beta = (T)W.beta;
     const T *u = coords_of<T>(P);
@@ -1004,8 +1026,8 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
         const int per_pt = (D * g.P + bs) * (int)sizeof(T);
         int chs = std::min(kMaxTaskPoints, 49152 / per_pt);
         size_t lds = (size_t)chs * per_pt;
-        hipLaunchKernelGGL((k_spread<T, D>), dim3(P.ntasks), dim3(256), lds, s, g, P.tasks.p, u, Zs,
-                           beta, chs, patch);
+        hipLaunchKernelGGL((k_spread<T, D>), dim3(P.ntasks, ngroups), dim3(256), lds, s, g, P.tasks.p,
+                           u, Zs, beta, chs, vg, patch);
         MLG_LAUNCH_CHECK();
     }
     if (ev) MLG_HIP(hipEventRecord(ev[1], s));
@@ -1029,11 +1051,11 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     fft_all<T>(P, bg, reinterpret_cast<C2 *>(grid), +1, s);
     if (ev) MLG_HIP(hipEventRecord(ev[3], s));
     if (P.ntasks > 0) {
-        const int per_pt = (D * g.P + kWaves * bs) * (int)sizeof(T);
+        const int per_pt = (D * g.P + kWaves * vg) * (int)sizeof(T);
         int chs = std::min(kMaxTaskPoints, 49152 / per_pt);
         size_t lds = (size_t)chs * per_pt;
-        hipLaunchKernelGGL((k_interp<T, D>), dim3(P.ntasks), dim3(256), lds, s, g, P.tasks.p, u,
-                           grid, bg, beta, chs, Fs);
+        hipLaunchKernelGGL((k_interp<T, D>), dim3(P.ntasks, ngroups), dim3(256), lds, s, g, P.tasks.p,
+                           u, grid, bg, beta, chs, vg, Fs);
         MLG_LAUNCH_CHECK();
     }
     if (ev) MLG_HIP(hipEventRecord(ev[4], s));

@@ -111,7 +111,7 @@ def test_nfft_fp32_weight_matvec(mlg, b):
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_nfft_fp64_lsym_dims(mlg, d):
     pts, _ = gen.gaussian_mixture(3001, d, 4, 0.08, 40 + d)
-    sig = 0.12
+    sig = 0.3       # scaled width ~0.06: Gaussian tail at N = 64 below 1e-12
     L = oracle.Layer(pts, sig)
     g = mlg.Graph([pts], [sig], mlg.kparams("nfft", 64, N=64, window=12))
     np.testing.assert_allclose(g.degrees(0), L.deg, rtol=1e-8)
@@ -126,7 +126,7 @@ def test_nfft_fp32_multilayer_mean(mlg):
     p3, _ = gen.gaussian_mixture(n, 3, 5, 0.05, 61)
     p2 = gen.uniform_ball(n, 2, 10.0, 62)
     p1 = gen.uniform_ball(n, 1, 3.0, 63)
-    sig = [0.1, 3.0, 0.5]
+    sig = [0.4, 4.0, 0.8]   # scaled widths resolved by N = 32, 32, 64
     layers = [oracle.Layer(p, s) for p, s in zip([p3, p2, p1], sig)]
     kp = [mlg.kparams("nfft", 32, N=32, window=6), mlg.kparams("nfft", 32, N=32, window=6),
           mlg.kparams("nfft", 32, N=64, window=6)]
@@ -147,7 +147,7 @@ def test_mixed_direct_and_nfft_layers(mlg):
     n = 1500
     p3, _ = gen.gaussian_mixture(n, 3, 3, 0.06, 71)
     p2 = gen.uniform_ball(n, 2, 1.0, 72)
-    sig = [0.12, 0.3]
+    sig = [0.12, 0.5]
     layers = [oracle.Layer(p3, sig[0]), oracle.Layer(p2, sig[1])]
     g = mlg.Graph([p3, p2], sig, [mlg.kparams("direct", 64), mlg.kparams("nfft", 64, N=32, window=12)])
     X = gen.test_vectors(n, 2, 73)
@@ -196,7 +196,7 @@ def test_lanczos_nfft_fp64_multilayer(mlg):
     n = 2500
     p3, _ = gen.gaussian_mixture(n, 3, 4, 0.05, 81)
     p2 = gen.uniform_ball(n, 2, 1.0, 82)
-    sig = [0.12, 0.35]
+    sig = [0.3, 0.35]
     layers = [oracle.Layer(p3, sig[0]), oracle.Layer(p2, sig[1])]
     lam_ref, V_ref = oracle.eigs_dense(layers, 8)
     kp = mlg.kparams("nfft", 64, N=64, window=12)
