@@ -5,11 +5,8 @@
 
 namespace mlg {
 
-// Point-chunk capacity of one spreading/interpolation task.
+// Point-chunk capacity of one spreading task.
 constexpr int kMaxTaskPoints = 256;
-// Register slots per thread in the per-task kernels (256 threads each).
-constexpr int kMaxSlots = 32;
-constexpr int kTaskThreads = 256;
 
 // NFFT plan of one layer (Algorithm 1 of Sec. 4): torus scaling, bin-sorted
 // points, per-bin tasks, and the Fourier multipliers on the 2N grid.
@@ -23,10 +20,17 @@ struct NfftPlan {
     int64_t n = 0;
     DevBuf<int> perm;       // sorted position -> original index
     DevBuf<double> u64;     // d x n grid coordinates in sorted order, FP64
-    DevBuf<float> u32;      // same, FP32
-    int ntasks = 0;
-    DevBuf<int4> tasks;     // (bin key, first point, count, 0)
-    DevBuf<int2> bin_tasks; // per bin: (first task, task count)
+    DevBuf<int> c32;        // d x n grid cell of each sorted point
+    DevBuf<float> f32;      // d x n offset inside that cell, FP32
+    int nruns = 0;          // occupied bins
+    int ntasks = 0;         // tasks (runs cut into chunks of <= kMaxTaskPoints)
+    int nscratch = 0;       // task patches of runs with more than one task
+    int nmulti = 0;         // runs with more than one task
+    DevBuf<int4> tasks;     // (bin key, first point, count, destination patch slot)
+    DevBuf<int4> multi;     // (run, first scratch slot, task count, 0)
+    DevBuf<int> bin_run;    // per bin: run index or -1
+    int SB = 8, nsb = 0;    // superbin edge (bins) and superbins per dimension
+    DevBuf<unsigned char> occ;  // per superbin: 1 if occupied
     DevBuf<double> bhat;    // kernel Fourier coefficients b^_l, l in [0,N)^d (index l mod N)
     DevBuf<float2> tw32;    // exp(-2 pi i j / nos), j < nos/2
     DevBuf<double2> tw64;

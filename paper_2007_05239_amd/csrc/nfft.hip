@@ -5,9 +5,9 @@
 //   torus scaling   x -> s (x - c) with ||s (x - c)|| <= 1/4 - eps_B/2, so every
 //                   pair distance stays where the regularised kernel equals K;
 //                   sigma -> s sigma (Alg. 1 input domain).
-//   grid coords     u = (x_scaled + 1/2) * 2N lies in [N/2, 3N/2]: a window of
-//                   support w < N never wraps around the 2N grid.
-//   bin sort        points sorted by the grid cell of u grouped in bins of
+//   grid coords     u = (x_scaled + 1/2) * 2N lies in (N/2, 3N/2): a window of
+//                   support w with bin + w/2 <= N/2 never wraps around the grid.
+//   bin sort        points sorted by the grid cell of u, grouped in bins of
 //                   B^d cells (rocPRIM radix sort); each bin's points are cut
 //                   into tasks of at most 256 points.
 //   coefficients    b^_l = N^-d sum_{k in I_N} K_R(k/N) exp(-2 pi i l.k/N)
@@ -18,16 +18,18 @@
 //                   (the real part of the sum over I_N).  psi^ is the window's
 //                   Fourier transform by Gauss-Legendre quadrature.
 //
-// Apply (per block of vectors z, stride bs, sorted order):
-//   spread   per task: patch[o][v] = sum_p psi(u_p - o) z_p[v] over the task's
-//            points, accumulated in registers (no atomics);
-//   gather   per tile of the grid: sum of the patches covering it, one LDS
-//            copy per wavefront, copies added in a fixed order (no atomics);
+// Apply (per block of vectors z, stride bs, sorted order; no atomics):
+//   spread   one wavefront per task: lanes own the cells of the bin's patch
+//            (the union of its points' window footprints) and accumulate
+//            psi(u_p - k) z_p over the task's points in registers;
+//   reduce   bins cut into several tasks: task patches summed in task order;
+//   gather   one thread per grid cell: sum over the bins whose patch covers
+//            the cell (bin order), via a dense bin table and a coarse
+//            occupancy map that skips empty neighbourhoods;
 //   FFT      forward complex FFT (two real vectors per complex lane), times M,
-//            inverse FFT (Alg. 1 steps 1-3 with deconvolution folded into M);
-//   interp   per task: f_p[v] = sum_o psi(u_p - o) h[o][v], partial sums
-//            reduced across lanes by butterfly shuffles, then across the
-//            four wavefronts in a fixed order.
+//            inverse FFT (Alg. 1 steps 1-3; deconvolution folded into M);
+//   interp   one thread per point: f_p = sum over its window footprint of
+//            psi(u_p - k) h_k.
 #include <cmath>
 #include <cstring>
 
@@ -167,16 +169,25 @@ __global__ void k_coords_keys(int64_t n, int d, const double *__restrict__ pts, 
     idx[i] = (int)i;
 }
 
-__global__ void k_gather_coords(int64_t n, int d, const double *__restrict__ u,
+// Sorted coordinates: FP64 u, and for FP32 kernels the integer cell plus the
+// fractional offset (so the FP32 cell always equals the bin-key cell).
+__global__ void k_gather_coords(int64_t n, int d, int nos, const double *__restrict__ u,
                                 const int *__restrict__ perm, double *__restrict__ u64,
-                                float *__restrict__ u32) {
+                                int *__restrict__ c32, float *__restrict__ f32) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int64_t i = perm[p];
     for (int t = 0; t < d; ++t) {
         double v = u[(int64_t)t * n + i];
         u64[(int64_t)t * n + p] = v;
-        u32[(int64_t)t * n + p] = (float)v;
+        int cell = v > 0.0 ? (int)floor(v) : 0;
+        const int lo = nos / 4 - 1, hi = 3 * nos / 4;
+        cell = cell < lo ? lo : (cell > hi ? hi : cell);
+        double fr = v - (double)cell;
+        float ff = (float)fr;
+        ff = ff < 0.0f ? 0.0f : (ff >= 1.0f ? 0x1.fffffep-1f : ff);
+        c32[(int64_t)t * n + p] = cell;
+        f32[(int64_t)t * n + p] = ff;
     }
 }
 
@@ -186,11 +197,16 @@ __global__ void k_task_counts(int runs, const unsigned *__restrict__ counts, int
     if (r < runs) ntask[r] = (counts[r] + ch - 1) / ch;
 }
 
+// Tasks of each run (bin) of sorted points; a run cut into several tasks
+// accumulates into scratch patch slots that a reduction sums afterwards.
 __global__ void k_fill_tasks(int runs, const unsigned *__restrict__ ukeys,
                              const unsigned *__restrict__ counts,
                              const unsigned *__restrict__ run_start,
-                             const unsigned *__restrict__ task_first, int ch,
-                             int4 *__restrict__ tasks, int2 *__restrict__ bin_tasks) {
+                             const unsigned *__restrict__ task_first,
+                             const unsigned *__restrict__ scr_first,
+                             const unsigned *__restrict__ multi_idx, int ch,
+                             int4 *__restrict__ tasks, int *__restrict__ bin_run,
+                             int4 *__restrict__ multi) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= runs) return;
     const unsigned cnt = counts[r], st = run_start[r], tf = task_first[r];
@@ -198,9 +214,36 @@ __global__ void k_fill_tasks(int runs, const unsigned *__restrict__ ukeys,
     for (unsigned j = 0; j < nt; ++j) {
         unsigned first = st + j * ch;
         unsigned c = cnt - j * ch < (unsigned)ch ? cnt - j * ch : (unsigned)ch;
-        tasks[tf + j] = make_int4((int)ukeys[r], (int)first, (int)c, 0);
+        int dest = nt == 1 ? r : runs + (int)(scr_first[r] + j);
+        tasks[tf + j] = make_int4((int)ukeys[r], (int)first, (int)c, dest);
     }
-    bin_tasks[ukeys[r]] = make_int2((int)tf, (int)nt);
+    bin_run[ukeys[r]] = r;
+    if (nt > 1) multi[multi_idx[r]] = make_int4(r, runs + (int)scr_first[r], (int)nt, 0);
+}
+
+__global__ void k_scr_counts(int runs, const unsigned *__restrict__ ntask,
+                             unsigned *__restrict__ scr, unsigned *__restrict__ ism) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > runs) return;
+    const unsigned nt = r < runs ? ntask[r] : 0u;
+    scr[r] = nt > 1 ? nt : 0u;
+    ism[r] = nt > 1 ? 1u : 0u;
+}
+
+// Coarse occupancy: superbin (SB^d bins) holding at least one point.
+__global__ void k_superbins(int runs, const unsigned *__restrict__ ukeys, int d, int nb, int SB,
+                            int nsb, unsigned char *__restrict__ occ) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= runs) return;
+    unsigned key = ukeys[r];
+    int idx = 0, mul = 1;
+    for (int t = 0; t < d; ++t) {
+        int b = (int)(key % (unsigned)nb);
+        key /= (unsigned)nb;
+        idx += (b / SB) * mul;
+        mul *= nsb;
+    }
+    occ[idx] = 1;
 }
 
 // Samples S[k] = K_R(k~/N), k in [0,N)^d with k~ = k or k - N (the set I_N).
@@ -299,188 +342,226 @@ __global__ void k_twiddles(int L, float2 *__restrict__ t32, double2 *__restrict_
 // ------------------------------------------------------------------------------
 // apply kernels
 // ------------------------------------------------------------------------------
-struct TaskGeom {
-    int d, nos, B, nb, w, P, bs;
+struct Geom {
+    int d, nos, B, nb, w, P, PD, bs;
     int64_t n;
 };
 
-__device__ inline void decode_bin(unsigned key, int nb, int d, int b[3]) {
-    b[0] = b[1] = b[2] = 0;
-    for (int t = 0; t < d; ++t) {
-        b[t] = (int)(key % (unsigned)nb);
-        key /= (unsigned)nb;
-    }
+// (cell, fractional offset) of point p along dimension t.
+template <class T>
+__device__ inline void point_coord(const double *u64, const int *c32, const float *f32,
+                                   int64_t idx, int &cell, T &frac);
+template <>
+__device__ inline void point_coord<float>(const double *, const int *c32, const float *f32,
+                                          int64_t idx, int &cell, float &frac) {
+    cell = c32[idx];
+    frac = f32[idx];
+}
+template <>
+__device__ inline void point_coord<double>(const double *u64, const int *, const float *,
+                                           int64_t idx, int &cell, double &frac) {
+    const double u = u64[idx];
+    cell = (int)floor(u);
+    frac = u - (double)cell;
 }
 
-// Stage `cnt` points starting at `first`: 1D window weights at the P patch
-// positions of each dimension (zero outside the point's footprint).
-template <class T, int D>
-__device__ inline void stage_weights(const TaskGeom &g, const T *__restrict__ u, int64_t first,
-                                     int cnt, const int org[3], T beta, T *__restrict__ wts) {
-    const T two_over_w = T(2) / (T)g.w;
-    for (int e = threadIdx.x; e < cnt * D * g.P; e += blockDim.x) {
-        int pt = e / (D * g.P);
-        int r = e - pt * D * g.P;
-        int t = r / g.P, q = r - t * g.P;
-        T ut = u[(int64_t)t * g.n + first + pt];
-        int cell = (int)floor((double)ut);
-        int s0 = cell - g.w / 2 + 1;          // first footprint cell
-        int k = org[t] + q;                   // grid cell of this patch position
-        T val = T(0);
-        if (k >= s0 && k < s0 + g.w) val = es_psi<T>(ut - (T)k, two_over_w, beta);
-        wts[e] = val;
-    }
-}
+__device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-template <class T, int D>
-__global__ __launch_bounds__(256) void k_spread(TaskGeom g, const int4 *__restrict__ tasks,
-                                                const T *__restrict__ u, const T *__restrict__ Zs,
-                                                T beta, int chs, int vg, T *__restrict__ patch) {
-    extern __shared__ unsigned char smem_raw[];
-    T *wts = reinterpret_cast<T *>(smem_raw);
-    T *zv = wts + (size_t)chs * D * g.P;
-    const int4 tk = tasks[blockIdx.x];
-    int bb[3];
-    decode_bin((unsigned)tk.x, g.nb, D, bb);
-    int org[3] = {0, 0, 0};
-    for (int t = 0; t < D; ++t) org[t] = bb[t] * g.B - g.w / 2 + 1;
-    const int tid = threadIdx.x;
-    const int P = g.P;
-    int PD = P;
-    for (int t = 1; t < D; ++t) PD *= P;
-    const int bs = g.bs;
-    // this workgroup handles vectors [blockIdx.y*vg, +vg) of the block
-    const int v = blockIdx.y * vg + tid % vg;
-    const int ostep = 256 / vg;
-    const int o0 = tid / vg;
-    int qoff[kMaxSlots];
-    T acc[kMaxSlots];
+template <class T, int V>
+__device__ inline void load_vec(const T *__restrict__ p, T (&out)[V]) {
+    if constexpr (sizeof(T) == 4 && V % 4 == 0) {
 #pragma unroll
-    for (int j = 0; j < kMaxSlots; ++j) {
-        int o = o0 + j * ostep;
-        int qx = o % P, qy = (o / P) % P, qz = o / (P * P);
-        qoff[j] = (o < PD) ? (qx | (qy << 8) | (qz << 16)) : -1;
-        acc[j] = T(0);
+        for (int i = 0; i < V; i += 4) {
+            float4 q = *reinterpret_cast<const float4 *>(p + i);
+            out[i] = q.x; out[i + 1] = q.y; out[i + 2] = q.z; out[i + 3] = q.w;
+        }
+    } else if constexpr (sizeof(T) == 8 && V % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            double2 q = *reinterpret_cast<const double2 *>(p + i);
+            out[i] = q.x; out[i + 1] = q.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) out[i] = p[i];
     }
-    for (int c0 = 0; c0 < tk.z; c0 += chs) {
-        const int cnt = (tk.z - c0) < chs ? (tk.z - c0) : chs;
+}
+
+template <class T, int V>
+__device__ inline void store_vec(T *__restrict__ p, const T (&v)[V]) {
+    if constexpr (sizeof(T) == 4 && V % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < V; i += 4)
+            *reinterpret_cast<float4 *>(p + i) = make_float4(v[i], v[i + 1], v[i + 2], v[i + 3]);
+    } else if constexpr (sizeof(T) == 8 && V % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < V; i += 2)
+            *reinterpret_cast<double2 *>(p + i) = make_double2(v[i], v[i + 1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) p[i] = v[i];
+    }
+}
+
+// Spread: one 64-lane workgroup per (task, vector group).  Lane l owns patch
+// cells l, l+64, ... and VPL vectors of each; points are staged 64 at a time
+// (their 1D window weights at the P patch positions per dimension, and their
+// values) and accumulated in the task's point order.
+template <class T, int D, int VPL>
+__global__ __launch_bounds__(64) void k_spread(Geom g, const int4 *__restrict__ tasks,
+                                               const double *__restrict__ u64,
+                                               const int *__restrict__ c32,
+                                               const float *__restrict__ f32,
+                                               const T *__restrict__ Zs, T beta,
+                                               T *__restrict__ patch) {
+    constexpr int CMAX = 64 / VPL;
+    extern __shared__ unsigned char smem_raw[];
+    const int P = g.P, PD = g.PD, bs = g.bs;
+    T *wts = reinterpret_cast<T *>(smem_raw);       // [64][D][P]
+    T *zv = wts + 64 * D * P;                        // [64][VPL]
+    const int lane = threadIdx.x;
+    const int4 tk = tasks[blockIdx.x];
+    const int v0 = blockIdx.y * VPL;
+    int org[3] = {0, 0, 0};
+    {
+        unsigned key = (unsigned)tk.x;
+        for (int t = 0; t < D; ++t) {
+            org[t] = (int)(key % (unsigned)g.nb) * g.B - g.w / 2 + 1;
+            key /= (unsigned)g.nb;
+        }
+    }
+    int qoff[CMAX];
+    T acc[CMAX][VPL];
+#pragma unroll
+    for (int j = 0; j < CMAX; ++j) {
+        const int c = lane + 64 * j;
+        const int qx = c % P, qy = (c / P) % P, qz = c / (P * P);
+        qoff[j] = c < PD ? (qx | ((P + qy) << 8) | ((2 * P + qz) << 16)) : -1;
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) acc[j][v] = T(0);
+    }
+    const T two_over_w = T(2) / (T)g.w;
+    for (int c0 = 0; c0 < tk.z; c0 += 64) {
+        const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
         const int64_t first = (int64_t)tk.y + c0;
         __syncthreads();
-        stage_weights<T, D>(g, u, first, cnt, org, beta, wts);
-        for (int e = tid; e < cnt * bs; e += 256) zv[e] = Zs[first * bs + e];
+        if (lane < cnt) {
+            const int64_t p = first + lane;
+            for (int t = 0; t < D; ++t) {
+                int cell;
+                T frac;
+                point_coord<T>(u64, c32, f32, (int64_t)t * g.n + p, cell, frac);
+                const int s0 = cell - g.w / 2 + 1;
+                for (int q = 0; q < P; ++q) {
+                    const int k = org[t] + q;
+                    T val = T(0);
+                    if (k >= s0 && k < s0 + g.w) val = es_psi<T>((T)(cell - k) + frac, two_over_w, beta);
+                    wts[(lane * D + t) * P + q] = val;
+                }
+            }
+            T zz[VPL];
+            load_vec<T, VPL>(Zs + p * bs + v0, zz);
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) zv[lane * VPL + v] = zz[v];
+        }
         __syncthreads();
         for (int pt = 0; pt < cnt; ++pt) {
             const T *wp = wts + pt * D * P;
-            const T z = zv[pt * bs + v];
+            T zz[VPL];
 #pragma unroll
-            for (int j = 0; j < kMaxSlots; ++j) {
+            for (int v = 0; v < VPL; ++v) zz[v] = zv[pt * VPL + v];
+#pragma unroll
+            for (int j = 0; j < CMAX; ++j) {
                 if (qoff[j] >= 0) {
                     T wgt = wp[qoff[j] & 0xff];
-                    if (D > 1) wgt *= wp[P + ((qoff[j] >> 8) & 0xff)];
-                    if (D > 2) wgt *= wp[2 * P + ((qoff[j] >> 16) & 0xff)];
-                    acc[j] += wgt * z;
+                    if (D > 1) wgt *= wp[(qoff[j] >> 8) & 0xff];
+                    if (D > 2) wgt *= wp[(qoff[j] >> 16) & 0xff];
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) acc[j][v] += wgt * zz[v];
                 }
             }
         }
     }
-    T *out = patch + (int64_t)blockIdx.x * PD * bs;
+    T *out = patch + (int64_t)tk.w * PD * bs + v0;
 #pragma unroll
-    for (int j = 0; j < kMaxSlots; ++j)
-        if (qoff[j] >= 0) out[(o0 + j * ostep) * bs + v] = acc[j];
+    for (int j = 0; j < CMAX; ++j)
+        if (qoff[j] >= 0) store_vec<T, VPL>(out + (int64_t)(lane + 64 * j) * bs, acc[j]);
 }
 
-// Sum of the patches that cover one TS^D tile; the grid has stride bg >= bs
+// Bins cut into several tasks: patch[run] = sum of the run's task patches,
+// in task order.
+template <class T>
+__global__ void k_binreduce(int64_t elems, const int4 *__restrict__ multi, T *__restrict__ patch) {
+    const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= elems) return;
+    const int4 mr = multi[blockIdx.x];
+    T s = patch[(int64_t)mr.y * elems + e];
+    for (int j = 1; j < mr.z; ++j) s += patch[(int64_t)(mr.y + j) * elems + e];
+    patch[(int64_t)mr.x * elems + e] = s;
+}
+
+// Gather: one thread per (grid cell, vector group): sum over the bins whose
+// patch covers the cell, in bin order.  The grid has stride bg >= bs per cell
 // (extra components written as zero).
-template <class T, int D>
-__global__ __launch_bounds__(256) void k_gather(TaskGeom g, int TS, int ntd,
-                                                const int4 *__restrict__ tasks,
-                                                const int2 *__restrict__ bin_tasks,
+template <class T, int D, int VPL>
+__global__ __launch_bounds__(256) void k_gather(Geom g, int SB, int nsb,
+                                                const unsigned char *__restrict__ occ,
+                                                const int *__restrict__ bin_run,
                                                 const T *__restrict__ patch, int bg,
-                                                T *__restrict__ grid) {
-    extern __shared__ unsigned char smem_raw[];
-    T *cp = reinterpret_cast<T *>(smem_raw);
-    const int bs = g.bs, P = g.P;
-    int TC = TS;
-    for (int t = 1; t < D; ++t) TC *= TS;
-    const int csz = TC * bs;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    T *my = cp + (size_t)wv * csz;
-    for (int e = lane; e < csz; e += 64) my[e] = T(0);
-    int tix[3] = {0, 0, 0};
+                                                T *__restrict__ grid, int64_t G) {
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= G) return;
+    const int v0 = blockIdx.y * VPL;
+    const int P = g.P, bs = g.bs;
+    int c[3] = {0, 0, 0}, blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
     {
-        int rem = blockIdx.x;
-        for (int t = 0; t < D; ++t) { tix[t] = rem % ntd; rem /= ntd; }
-    }
-    int T0[3] = {0, 0, 0}, blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
-    int PD = P;
-    for (int t = 1; t < D; ++t) PD *= P;
-    for (int t = 0; t < D; ++t) {
-        T0[t] = tix[t] * TS;
-        int a = T0[t] - g.B - g.w / 2 + 1;                 // ceil(a / B)
-        int lo = a >= 0 ? (a + g.B - 1) / g.B : -((-a) / g.B);
-        int hb = T0[t] + TS - 2 + g.w / 2;                 // floor(hb / B), hb >= 0
-        int hi = hb / g.B;
-        blo[t] = lo < 0 ? 0 : lo;
-        bhi[t] = hi > g.nb - 1 ? g.nb - 1 : hi;
-    }
-    int ext[3] = {1, 1, 1};
-    int ncand = 1;
-    for (int t = 0; t < D; ++t) {
-        ext[t] = bhi[t] >= blo[t] ? bhi[t] - blo[t] + 1 : 0;
-        ncand *= ext[t];
-    }
-    __syncthreads();
-    for (int c = wv; c < ncand; c += kWaves) {
-        int rem = c, b3[3] = {0, 0, 0};
-        for (int t = 0; t < D; ++t) { b3[t] = blo[t] + rem % ext[t]; rem /= ext[t]; }
-        unsigned key = 0, mul = 1;
-        for (int t = 0; t < D; ++t) { key += (unsigned)b3[t] * mul; mul *= (unsigned)g.nb; }
-        const int2 bt = bin_tasks[key];
-        if (bt.y == 0) continue;
-        // intersection of this bin's patch with the tile
-        int lo[3] = {0, 0, 0}, ex[3] = {1, 1, 1}, po[3] = {0, 0, 0};
-        int tot = bs;
+        int64_t rem = cell;
         for (int t = 0; t < D; ++t) {
-            po[t] = b3[t] * g.B - g.w / 2 + 1;
-            int a = po[t] > T0[t] ? po[t] : T0[t];
-            int e2 = (po[t] + P) < (T0[t] + TS) ? (po[t] + P) : (T0[t] + TS);
-            lo[t] = a;
-            ex[t] = e2 - a;
-            tot *= ex[t];
+            c[t] = (int)(rem % g.nos);
+            rem /= g.nos;
+            int lo = floor_div(c[t] + g.w / 2 - P + g.B - 1, g.B);   // ceil((c+w/2-P)/B)
+            int hi = floor_div(c[t] + g.w / 2 - 1, g.B);
+            blo[t] = lo < 0 ? 0 : lo;
+            bhi[t] = hi > g.nb - 1 ? g.nb - 1 : hi;
         }
-        if (tot <= 0) continue;
-        for (int tsk = bt.x; tsk < bt.x + bt.y; ++tsk) {
-            const T *src = patch + (int64_t)tsk * PD * bs;
-            for (int e = lane; e < tot; e += 64) {
-                int vv = e % bs;
-                int r = e / bs;
-                int cx = r % ex[0];
-                r /= ex[0];
-                int cy = D > 1 ? r % ex[1] : 0;
-                int cz = D > 2 ? r / ex[1] : 0;
-                int gx = lo[0] + cx, gy = lo[1] + cy, gz = lo[2] + cz;
-                int pidx = gx - po[0];
-                int tidx = gx - T0[0];
-                if (D > 1) { pidx += (gy - po[1]) * P; tidx += (gy - T0[1]) * TS; }
-                if (D > 2) { pidx += (gz - po[2]) * P * P; tidx += (gz - T0[2]) * TS * TS; }
-                my[tidx * bs + vv] += src[pidx * bs + vv];
+    }
+    T acc[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc[v] = T(0);
+    bool any = true;
+    for (int t = 0; t < D; ++t)
+        if (bhi[t] < blo[t]) any = false;
+    if (any) {
+        any = false;
+        const int s2lo = D > 2 ? blo[2] / SB : 0, s2hi = D > 2 ? bhi[2] / SB : 0;
+        const int s1lo = D > 1 ? blo[1] / SB : 0, s1hi = D > 1 ? bhi[1] / SB : 0;
+        for (int s2 = s2lo; s2 <= s2hi; ++s2)
+            for (int s1 = s1lo; s1 <= s1hi; ++s1)
+                for (int s0 = blo[0] / SB; s0 <= bhi[0] / SB; ++s0)
+                    any |= occ[s0 + nsb * (s1 + nsb * s2)] != 0;
+    }
+    if (any) {
+        const int PD = g.PD;
+        for (int b2 = blo[2]; b2 <= bhi[2]; ++b2) {
+            const int o2 = D > 2 ? (c[2] - (b2 * g.B - g.w / 2 + 1)) * P * P : 0;
+            for (int b1 = blo[1]; b1 <= bhi[1]; ++b1) {
+                const int o1 = D > 1 ? (c[1] - (b1 * g.B - g.w / 2 + 1)) * P : 0;
+                const int64_t rowkey = (int64_t)g.nb * (b1 + (int64_t)g.nb * b2);
+                for (int b0 = blo[0]; b0 <= bhi[0]; ++b0) {
+                    const int r = bin_run[rowkey + b0];
+                    if (r < 0) continue;
+                    const int o = o2 + o1 + (c[0] - (b0 * g.B - g.w / 2 + 1));
+                    T h[VPL];
+                    load_vec<T, VPL>(patch + ((int64_t)r * PD + o) * bs + v0, h);
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) acc[v] += h[v];
+                }
             }
         }
     }
-    __syncthreads();
-    for (int e = tid; e < TC * bg; e += 256) {
-        int vv = e % bg, cell = e / bg;
-        T s = T(0);
-        if (vv < bs) {
-            s = cp[cell * bs + vv];
-            for (int c = 1; c < kWaves; ++c) s += cp[(size_t)c * csz + cell * bs + vv];
-        }
-        int cx = cell % TS, cy = D > 1 ? (cell / TS) % TS : 0, cz = D > 2 ? cell / (TS * TS) : 0;
-        int64_t gidx = T0[0] + cx;
-        if (D > 1) gidx += (int64_t)(T0[1] + cy) * g.nos;
-        if (D > 2) gidx += (int64_t)(T0[2] + cz) * g.nos * g.nos;
-        grid[gidx * bg + vv] = s;
-    }
+    store_vec<T, VPL>(grid + cell * bg + v0, acc);
+    if (bg > bs && blockIdx.y == 0)
+        for (int v = bs; v < bg; ++v) grid[cell * bg + v] = T(0);
 }
 
 template <class T>
@@ -501,8 +582,9 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
     extern __shared__ unsigned char smem_raw[];
     C2 *buf = reinterpret_cast<C2 *>(smem_raw);
     const int tid = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * IC;
-    const int64_t o0 = (int64_t)blockIdx.y * LB;
+    const int64_t nchunk = inner / IC;
+    const int64_t c0 = ((int64_t)blockIdx.x % nchunk) * IC;
+    const int64_t o0 = ((int64_t)blockIdx.x / nchunk) * LB;
     const int lines = IC * LB;
     for (int e = tid; e < L * lines; e += 256) {
         int ln = e % lines, k = e / lines;
@@ -559,74 +641,60 @@ __global__ void k_mul(typename Cplx<T>::type *__restrict__ grid, const T *__rest
     grid[e] = g;
 }
 
-template <class T, int D>
-__global__ __launch_bounds__(256) void k_interp(TaskGeom g, const int4 *__restrict__ tasks,
-                                                const T *__restrict__ u,
+// Interpolation: one thread per (point, vector group); window weights in
+// registers, the footprint read from the grid.
+template <class T, int D, int VPL>
+__global__ __launch_bounds__(256) void k_interp(Geom g, const double *__restrict__ u64,
+                                                const int *__restrict__ c32,
+                                                const float *__restrict__ f32,
                                                 const T *__restrict__ grid, int bg, T beta,
-                                                int chs, int vg, T *__restrict__ Fs) {
-    extern __shared__ unsigned char smem_raw[];
-    T *wts = reinterpret_cast<T *>(smem_raw);
-    T *red = wts + (size_t)chs * D * g.P;
-    const int4 tk = tasks[blockIdx.x];
-    int bb[3];
-    decode_bin((unsigned)tk.x, g.nb, D, bb);
-    int org[3] = {0, 0, 0};
-    for (int t = 0; t < D; ++t) org[t] = bb[t] * g.B - g.w / 2 + 1;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int P = g.P;
-    int PD = P;
-    for (int t = 1; t < D; ++t) PD *= P;
-    const int bs = g.bs;
-    const int v0 = blockIdx.y * vg;
-    const int v = v0 + tid % vg;
-    const int ostep = 256 / vg;
-    const int o0 = tid / vg;
-    int qoff[kMaxSlots];
-    T h[kMaxSlots];
-#pragma unroll
-    for (int j = 0; j < kMaxSlots; ++j) {
-        int o = o0 + j * ostep;
-        int qx = o % P, qy = (o / P) % P, qz = o / (P * P);
-        bool ok = o < PD;
-        qoff[j] = ok ? (qx | (qy << 8) | (qz << 16)) : -1;
-        T val = T(0);
-        if (ok) {
-            int64_t cell = org[0] + qx;
-            if (D > 1) cell += (int64_t)(org[1] + qy) * g.nos;
-            if (D > 2) cell += (int64_t)(org[2] + qz) * g.nos * g.nos;
-            val = grid[cell * bg + v];
-        }
-        h[j] = val;
+                                                T *__restrict__ Fs) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.n) return;
+    const int v0 = blockIdx.y * VPL;
+    const int w = g.w;
+    const T two_over_w = T(2) / (T)w;
+    // innermost dimension's weights in registers (compile-time indices);
+    // the outer dimensions' weights are evaluated in their loops
+    T phi0[16];
+    int s0[3] = {0, 0, 0};
+    T fr[3] = {T(0), T(0), T(0)};
+    for (int t = 0; t < D; ++t) {
+        int cell;
+        point_coord<T>(u64, c32, f32, (int64_t)t * g.n + p, cell, fr[t]);
+        s0[t] = cell - w / 2 + 1;
     }
-    for (int c0 = 0; c0 < tk.z; c0 += chs) {
-        const int cnt = (tk.z - c0) < chs ? (tk.z - c0) : chs;
-        const int64_t first = (int64_t)tk.y + c0;
-        __syncthreads();
-        stage_weights<T, D>(g, u, first, cnt, org, beta, wts);
-        __syncthreads();
-        for (int pt = 0; pt < cnt; ++pt) {
-            const T *wp = wts + pt * D * P;
-            T part = T(0);
 #pragma unroll
-            for (int j = 0; j < kMaxSlots; ++j) {
-                if (qoff[j] >= 0) {
-                    T wgt = wp[qoff[j] & 0xff];
-                    if (D > 1) wgt *= wp[P + ((qoff[j] >> 8) & 0xff)];
-                    if (D > 2) wgt *= wp[2 * P + ((qoff[j] >> 16) & 0xff)];
-                    part += wgt * h[j];
+    for (int k = 0; k < 16; ++k)
+        phi0[k] = k < w ? es_psi<T>((T)(w / 2 - 1 - k) + fr[0], two_over_w, beta) : T(0);
+    T acc[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc[v] = T(0);
+    const int n2 = D > 2 ? w : 1, n1 = D > 1 ? w : 1;
+    for (int k2 = 0; k2 < n2; ++k2) {
+        const T w2 = D > 2 ? es_psi<T>((T)(w / 2 - 1 - k2) + fr[2], two_over_w, beta) : T(1);
+        for (int k1 = 0; k1 < n1; ++k1) {
+            T wyz = w2;
+            int64_t base = s0[0];
+            if (D > 1) {
+                wyz *= es_psi<T>((T)(w / 2 - 1 - k1) + fr[1], two_over_w, beta);
+                base += (int64_t)g.nos * (s0[1] + k1);
+            }
+            if (D > 2) base += (int64_t)g.nos * g.nos * (s0[2] + k2);
+            const T *row = grid + base * bg + v0;
+#pragma unroll
+            for (int k0 = 0; k0 < 16; ++k0) {
+                if (k0 < w) {
+                    const T wgt = wyz * phi0[k0];
+                    T h[VPL];
+                    load_vec<T, VPL>(row + (int64_t)k0 * bg, h);
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) acc[v] += wgt * h[v];
                 }
             }
-            for (int off = vg; off < 64; off <<= 1) part += __shfl_xor(part, off, 64);
-            if (lane < vg) red[((size_t)wv * chs + pt) * vg + lane] = part;
-        }
-        __syncthreads();
-        for (int e = tid; e < cnt * vg; e += 256) {
-            T s = red[e];
-            for (int c = 1; c < kWaves; ++c) s += red[(size_t)c * chs * vg + e];
-            const int pt = e / vg, vv = e - pt * vg;
-            Fs[(first + pt) * bs + v0 + vv] = s;
         }
     }
+    store_vec<T, VPL>(Fs + p * g.bs + v0, acc);
 }
 
 // ------------------------------------------------------------------------------
@@ -821,9 +889,10 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     MLG_HIP(rocprim::radix_sort_pairs(tmp.p, tbytes, keys.p, skeys.p, idx.p, P.perm.p,
                                       (unsigned)n, 0u, endbit, s));
     P.u64.alloc((size_t)d * n);
-    P.u32.alloc((size_t)d * n);
-    hipLaunchKernelGGL(k_gather_coords, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, uun.p,
-                       P.perm.p, P.u64.p, P.u32.p);
+    P.c32.alloc((size_t)d * n);
+    P.f32.alloc((size_t)d * n);
+    hipLaunchKernelGGL(k_gather_coords, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, P.nos, uun.p,
+                       P.perm.p, P.u64.p, P.c32.p, P.f32.p);
     MLG_LAUNCH_CHECK();
 
     // --- runs of equal bins -> tasks ---
@@ -837,34 +906,51 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     unsigned runs = 0;
     MLG_HIP(hipMemcpyAsync(&runs, runs_dev.p, 4, hipMemcpyDeviceToHost, s));
     MLG_HIP(hipStreamSynchronize(s));
-    DevBuf<unsigned> run_start(runs + 1), ntask(runs + 1), task_first(runs + 1);
-    tbytes = 0;
-    MLG_HIP(rocprim::exclusive_scan(nullptr, tbytes, counts.p, run_start.p, 0u, (size_t)runs,
-                                    rocprim::plus<unsigned>(), s));
-    tmp.ensure(tbytes + 1);
-    MLG_HIP(rocprim::exclusive_scan(tmp.p, tbytes, counts.p, run_start.p, 0u, (size_t)runs,
-                                    rocprim::plus<unsigned>(), s));
+    DevBuf<unsigned> run_start(runs + 1), ntask(runs + 1), task_first(runs + 1), scr(runs + 1),
+        scr_first(runs + 1), ism(runs + 1), multi_idx(runs + 1);
+    auto xscan = [&](const unsigned *in, unsigned *out, size_t cnt) {
+        size_t tb = 0;
+        MLG_HIP(rocprim::exclusive_scan(nullptr, tb, in, out, 0u, cnt, rocprim::plus<unsigned>(), s));
+        tmp.ensure(tb + 1);
+        MLG_HIP(rocprim::exclusive_scan(tmp.p, tb, in, out, 0u, cnt, rocprim::plus<unsigned>(), s));
+    };
+    xscan(counts.p, run_start.p, runs);
     hipLaunchKernelGGL(k_task_counts, dim3(ceil_div(runs, 256)), dim3(256), 0, s, (int)runs,
                        counts.p, kMaxTaskPoints, ntask.p);
     MLG_LAUNCH_CHECK();
-    tbytes = 0;
-    MLG_HIP(rocprim::exclusive_scan(nullptr, tbytes, ntask.p, task_first.p, 0u, (size_t)runs + 1,
-                                    rocprim::plus<unsigned>(), s));
-    tmp.ensure(tbytes + 1);
-    // ntask[runs] is scratch: make it 0 so task_first[runs] is the total
+    // ntask[runs] = 0 so that the scans give totals at index runs
     MLG_HIP(hipMemsetAsync(ntask.p + runs, 0, 4, s));
-    MLG_HIP(rocprim::exclusive_scan(tmp.p, tbytes, ntask.p, task_first.p, 0u, (size_t)runs + 1,
-                                    rocprim::plus<unsigned>(), s));
-    unsigned total = 0;
-    MLG_HIP(hipMemcpyAsync(&total, task_first.p + runs, 4, hipMemcpyDeviceToHost, s));
+    xscan(ntask.p, task_first.p, (size_t)runs + 1);
+    hipLaunchKernelGGL(k_scr_counts, dim3(ceil_div(runs + 1, 256)), dim3(256), 0, s, (int)runs,
+                       ntask.p, scr.p, ism.p);
+    MLG_LAUNCH_CHECK();
+    xscan(scr.p, scr_first.p, (size_t)runs + 1);
+    xscan(ism.p, multi_idx.p, (size_t)runs + 1);
+    unsigned tot[3] = {0, 0, 0};
+    MLG_HIP(hipMemcpyAsync(&tot[0], task_first.p + runs, 4, hipMemcpyDeviceToHost, s));
+    MLG_HIP(hipMemcpyAsync(&tot[1], scr_first.p + runs, 4, hipMemcpyDeviceToHost, s));
+    MLG_HIP(hipMemcpyAsync(&tot[2], multi_idx.p + runs, 4, hipMemcpyDeviceToHost, s));
     MLG_HIP(hipStreamSynchronize(s));
-    P.ntasks = (int)total;
-    P.tasks.alloc(total);
-    P.bin_tasks.alloc(P.nbins);
-    MLG_HIP(hipMemsetAsync(P.bin_tasks.p, 0, sizeof(int2) * P.nbins, s));
+    P.nruns = (int)runs;
+    P.ntasks = (int)tot[0];
+    P.nscratch = (int)tot[1];
+    P.nmulti = (int)tot[2];
+    P.tasks.alloc(P.ntasks);
+    P.multi.alloc(P.nmulti > 0 ? P.nmulti : 1);
+    P.bin_run.alloc(P.nbins);
+    MLG_HIP(hipMemsetAsync(P.bin_run.p, 0xff, sizeof(int) * P.nbins, s));   // -1: empty bin
     hipLaunchKernelGGL(k_fill_tasks, dim3(ceil_div(runs, 256)), dim3(256), 0, s, (int)runs, ukeys.p,
-                       counts.p, run_start.p, task_first.p, kMaxTaskPoints, P.tasks.p,
-                       P.bin_tasks.p);
+                       counts.p, run_start.p, task_first.p, scr_first.p, multi_idx.p, kMaxTaskPoints,
+                       P.tasks.p, P.bin_run.p, P.multi.p);
+    MLG_LAUNCH_CHECK();
+    P.SB = std::min(8, P.nb);
+    P.nsb = (P.nb + P.SB - 1) / P.SB;
+    int64_t nsbd = 1;
+    for (int t = 0; t < d; ++t) nsbd *= P.nsb;
+    P.occ.alloc(nsbd);
+    MLG_HIP(hipMemsetAsync(P.occ.p, 0, nsbd, s));
+    hipLaunchKernelGGL(k_superbins, dim3(ceil_div(runs, 256)), dim3(256), 0, s, (int)runs, ukeys.p, d,
+                       P.nb, P.SB, P.nsb, P.occ.p);
     MLG_LAUNCH_CHECK();
 
     // --- kernel Fourier coefficients b^ (FP64) ---
@@ -891,19 +977,6 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
                        P.tw64.p);
     MLG_LAUNCH_CHECK();
     MLG_HIP(hipStreamSynchronize(s));
-}
-
-static int tile_edge(int d, int nos, int bs, int prec) {
-    // LDS holds kWaves copies of TS^d x bs values; keep it <= 64 KB.
-    const int esz = prec == 64 ? 8 : 4;
-    int TS = d == 3 ? 8 : (d == 2 ? 16 : 256);
-    for (;;) {
-        int64_t tc = 1;
-        for (int t = 0; t < d; ++t) tc *= TS;
-        if ((int64_t)kWaves * tc * bs * esz <= 65536 || TS == 1) break;
-        TS /= 2;
-    }
-    return TS > nos ? nos : TS;
 }
 
 void nfft_make_window(const Layer &L, NfftWindow &W, int w, int prec, int bs, hipStream_t s) {
@@ -940,10 +1013,14 @@ void nfft_make_window(const Layer &L, NfftWindow &W, int w, int prec, int bs, hi
 
 static int patch_side(const NfftPlan &P, const NfftWindow &W) { return P.B + W.w - 1; }
 
+static int patch_cells(const NfftPlan &P, const NfftWindow &W) {
+    int pd = 1;
+    for (int t = 0; t < P.d; ++t) pd *= patch_side(P, W);
+    return pd;
+}
+
 size_t nfft_patch_elems(const NfftPlan &P, const NfftWindow &W, int bs) {
-    size_t pd = 1;
-    for (int t = 0; t < P.d; ++t) pd *= (size_t)patch_side(P, W);
-    return pd * bs * (size_t)P.ntasks;
+    return (size_t)patch_cells(P, W) * bs * (size_t)(P.nruns + P.nscratch);
 }
 
 size_t nfft_grid_elems(const NfftPlan &P, int bs) {
@@ -958,12 +1035,6 @@ template <>
 const float *mult_of<float>(const NfftWindow &W) { return W.M32.p; }
 template <>
 const double *mult_of<double>(const NfftWindow &W) { return W.M64.p; }
-template <class T>
-static const T *coords_of(const NfftPlan &P);
-template <>
-const float *coords_of<float>(const NfftPlan &P) { return P.u32.p; }
-template <>
-const double *coords_of<double>(const NfftPlan &P) { return P.u64.p; }
 template <class T>
 static const typename Cplx<T>::type *tw_of(const NfftPlan &P);
 template <>
@@ -990,74 +1061,105 @@ static void fft_all(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, int
         int LB = std::max(1, maxlines / IC);
         if (LB > outer) LB = (int)outer;
         const size_t lds = (size_t)L * IC * LB * sizeof(typename Cplx<T>::type);
-        dim3 grd((unsigned)(inner / IC), (unsigned)((outer + LB - 1) / LB));
+        dim3 grd((unsigned)((inner / IC) * ((outer + LB - 1) / LB)));
         hipLaunchKernelGGL(k_fft<T>, grd, dim3(256), lds, s, grid, L, logL, outer, inner, IC, LB,
                            sign, tw_of<T>(P));
         MLG_LAUNCH_CHECK();
     }
 }
 
+// Widest vector group (power of two <= min(bs, 16)) whose patch slots fit the
+// spreading lanes' registers: ceil(PD/64) cells x VPL vectors <= 64.
+static int spread_vpl(int PD, int bs) {
+    int v = std::min(bs, 16);
+    while (v > 1 && ceil_div(PD, 64) * v > 64) v >>= 1;
+    return v;
+}
+
+template <class T, int D, int VPL>
+static void launch_spread(const Geom &g, const NfftPlan &P, const T *Zs, T beta, T *patch,
+                          hipStream_t s) {
+    const size_t lds = (size_t)64 * (D * g.P + VPL) * sizeof(T);
+    hipLaunchKernelGGL((k_spread<T, D, VPL>), dim3(P.ntasks, g.bs / VPL), dim3(64), lds, s, g,
+                       P.tasks.p, P.u64.p, P.c32.p, P.f32.p, Zs, beta, patch);
+    MLG_LAUNCH_CHECK();
+}
+
+template <class T, int D, int VPL>
+static void launch_gather(const Geom &g, const NfftPlan &P, const T *patch, int bg, T *grid,
+                          int64_t G, hipStream_t s) {
+    hipLaunchKernelGGL((k_gather<T, D, VPL>), dim3(ceil_div(G, 256), g.bs / VPL), dim3(256), 0, s, g,
+                       P.SB, P.nsb, P.occ.p, P.bin_run.p, patch, bg, grid, G);
+    MLG_LAUNCH_CHECK();
+}
+
+template <class T, int D, int VPL>
+static void launch_interp(const Geom &g, const NfftPlan &P, const T *grid, int bg, T beta, T *Fs,
+                          hipStream_t s) {
+    hipLaunchKernelGGL((k_interp<T, D, VPL>), dim3(ceil_div(g.n, 256), g.bs / VPL), dim3(256), 0, s,
+                       g, P.u64.p, P.c32.p, P.f32.p, grid, bg, beta, Fs);
+    MLG_LAUNCH_CHECK();
+}
+
+#define MLG_VPL_SWITCH(vpl, CALL)                                                   \
+    switch (vpl) {                                                                  \
+        case 1: CALL(1); break;                                                     \
+        case 2: CALL(2); break;                                                     \
+        case 4: CALL(4); break;                                                     \
+        case 8: CALL(8); break;                                                     \
+        case 16: CALL(16); break;                                                   \
+        default: throw Error(MLG_ERR_ARG, "unsupported vector group");              \
+    }
+
 template <class T, int D>
 static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs, T *Fs, T *patch,
                     T *grid, hipStream_t s, hipEvent_t *ev) {
-    TaskGeom g;
+    Geom g;
     g.d = D;
     g.nos = P.nos;
     g.B = P.B;
     g.nb = P.nb;
     g.w = W.w;
     g.P = patch_side(P, W);
+    g.PD = patch_cells(P, W);
     g.bs = bs;
     g.n = P.n;
-    int PD = 1;
-    for (int t = 0; t < D; ++t) PD *= g.P;
-    MLG_REQUIRE(256 % bs == 0, MLG_ERR_ARG, "block stride must divide 256");
-    // vectors per workgroup: the patch slots of one group must fit the
-    // register budget of 256 threads
-    int vg = bs;
-    while (vg > 1 && (int64_t)PD * vg > (int64_t)kMaxSlots * 256) vg >>= 1;
-    MLG_REQUIRE((int64_t)PD * vg <= (int64_t)kMaxSlots * 256, MLG_ERR_RANGE,
+    MLG_REQUIRE(bs >= 1 && bs <= 64 && is_pow2(bs), MLG_ERR_ARG, "block stride must be a power of two <= 64");
+    const int vs = spread_vpl(g.PD, bs);
+    MLG_REQUIRE(ceil_div(g.PD, 64) * vs <= 64, MLG_ERR_RANGE,
                 "patch too large for one task (reduce window or bin)");
-    const int ngroups = bs / vg;
     const int bg = bs < 2 ? 2 : bs;
     const T beta = (T)W.beta;
-    const T *u = coords_of<T>(P);
     if (P.ntasks > 0) {
-        const int per_pt = (D * g.P + bs) * (int)sizeof(T);
-        int chs = std::min(kMaxTaskPoints, 49152 / per_pt);
-        size_t lds = (size_t)chs * per_pt;
-        hipLaunchKernelGGL((k_spread<T, D>), dim3(P.ntasks, ngroups), dim3(256), lds, s, g, P.tasks.p,
-                           u, Zs, beta, chs, vg, patch);
-        MLG_LAUNCH_CHECK();
+#define SPREAD_CALL(V) launch_spread<T, D, V>(g, P, Zs, beta, patch, s)
+        MLG_VPL_SWITCH(vs, SPREAD_CALL)
+#undef SPREAD_CALL
+        if (P.nmulti > 0) {
+            const int64_t elems = (int64_t)g.PD * bs;
+            hipLaunchKernelGGL(k_binreduce<T>, dim3(P.nmulti, ceil_div(elems, 256)), dim3(256), 0, s,
+                               elems, P.multi.p, patch);
+            MLG_LAUNCH_CHECK();
+        }
     }
     if (ev) MLG_HIP(hipEventRecord(ev[1], s));
-    const int TS = tile_edge(D, P.nos, bs, sizeof(T) == 8 ? 64 : 32);
-    const int ntd = P.nos / TS;
-    int ntiles = 1;
-    for (int t = 0; t < D; ++t) ntiles *= ntd;
-    int TC = 1;
-    for (int t = 0; t < D; ++t) TC *= TS;
-    hipLaunchKernelGGL((k_gather<T, D>), dim3(ntiles), dim3(256), (size_t)kWaves * TC * bs * sizeof(T),
-                       s, g, TS, ntd, P.tasks.p, P.bin_tasks.p, patch, bg, grid);
-    MLG_LAUNCH_CHECK();
+    int64_t G = 1;
+    for (int t = 0; t < D; ++t) G *= P.nos;
+    const int vgat = std::min(bs, 16);
+#define GATHER_CALL(V) launch_gather<T, D, V>(g, P, patch, bg, grid, G, s)
+    MLG_VPL_SWITCH(vgat, GATHER_CALL)
+#undef GATHER_CALL
     if (ev) MLG_HIP(hipEventRecord(ev[2], s));
     using C2 = typename Cplx<T>::type;
     fft_all<T>(P, bg, reinterpret_cast<C2 *>(grid), -1, s);
-    int64_t G = 1;
-    for (int t = 0; t < D; ++t) G *= P.nos;
     hipLaunchKernelGGL(k_mul<T>, dim3(ceil_div(G * (bg / 2), 256)), dim3(256), 0, s,
                        reinterpret_cast<C2 *>(grid), mult_of<T>(W), G, bg / 2);
     MLG_LAUNCH_CHECK();
     fft_all<T>(P, bg, reinterpret_cast<C2 *>(grid), +1, s);
     if (ev) MLG_HIP(hipEventRecord(ev[3], s));
-    if (P.ntasks > 0) {
-        const int per_pt = (D * g.P + kWaves * vg) * (int)sizeof(T);
-        int chs = std::min(kMaxTaskPoints, 49152 / per_pt);
-        size_t lds = (size_t)chs * per_pt;
-        hipLaunchKernelGGL((k_interp<T, D>), dim3(P.ntasks, ngroups), dim3(256), lds, s, g, P.tasks.p,
-                           u, grid, bg, beta, chs, vg, Fs);
-        MLG_LAUNCH_CHECK();
-    }
+    const int vint = std::min(bs, 16);
+#define INTERP_CALL(V) launch_interp<T, D, V>(g, P, grid, bg, beta, Fs, s)
+    MLG_VPL_SWITCH(vint, INTERP_CALL)
+#undef INTERP_CALL
     if (ev) MLG_HIP(hipEventRecord(ev[4], s));
 }
 
