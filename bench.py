@@ -1,0 +1,163 @@
+"""Benchmark: batched Laplacian matvecs of the aggregated multilayer operator.
+
+One step = one application of L_1 = I - (1/T) sum_t D_t^-1/2 W_t D_t^-1/2 to a
+block of b = 16 vectors across all layers of the image-like graph
+(1000 x 1000 synthetic image, n = 10^6 nodes, 3 layers: RGB d=3, pixel xy
+d=2, 3x3-mean RGB d=3; Gaussian kernels, FP32 NFFT summation, FP64 degree
+scaling and aggregation), inputs and outputs resident in HBM.
+
+Metric: n * layers * b / s (node-layer-vector rows per second).
+
+Printed as ONE JSON line with the roofline of the dominant kernel (timed
+with HIP events on the library's stream), the FP64-plain comparison (one
+vector per matvec, FP64 NFFT), the relative error of sampled rows against
+the FP64 oracle, and the oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Laplacian matvecs/sec (n*layers/s) at 1e-4 rel err vs FP64; FP32-batched vs FP64 plain"
+UNIT = "node-layer-vector rows/s"
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--block", type=int, default=16)
+    ap.add_argument("--N", type=int, default=0, help="bandwidth (0 = automatic per layer)")
+    ap.add_argument("--window", type=int, default=6)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain leg")
+    ap.add_argument("--image", type=int, default=1000, help="image edge (n = edge^2)")
+    return ap.parse_args()
+
+
+def algorithmic_counts(infos, n, b):
+    """Per-kernel algorithmic work of one step (all layers): spreading and
+    interpolation do one multiply-add per (point, window cell, vector)."""
+    fl = 0.0
+    for inf in infos:
+        w, d = inf["window"], inf["d"]
+        fl += 2.0 * n * (w ** d) * b
+    return fl
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the layer-sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2007_05239_amd.mlg as mlg
+    from workloads import gen
+
+    dev = torch.device("cuda:0")
+    c = gen.config3(a.image, a.image)
+    n, T, b = c["n"], len(c["layers"]), a.block
+    kp = [mlg.kparams("nfft", 32, N=a.N, window=a.window, eps_B=1.0 / 16, p_reg=5)
+          for _ in range(T)]
+    layers_dev = [torch.from_numpy(L).to(dev) for L in c["layers"]]
+    t0 = time.time()
+    g = mlg.Graph(layers_dev, c["sigma"], kp)
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    infos = [g.layer_info(t) for t in range(T)]
+    X = torch.from_numpy(np.ascontiguousarray(gen.test_vectors(n, b, c["base_seed"] + 300))).to(dev)
+    for _ in range(a.warmup):
+        Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, X)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el / a.steps * 1e3
+    value = n * T * b * a.steps / el
+
+    # stage timings with HIP events on the library stream
+    st = g.profile_stages(-1, mlg.MLG_OP_LSYM, X, reps=5)
+    flops = algorithmic_counts(infos, n, b)
+    kern = {"spread": st["spread"], "interp": st["interp"]}
+    dom = max(kern, key=kern.get)
+    dur_ms = kern[dom]                     # summed over the T layer launches
+    achieved = flops / (dur_ms * 1e-3) / 1e12
+    roof = {"kernel": "k_%s (all %d layer launches)" % (dom, T), "bound": "alu",
+            "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "launch_ms": round(dur_ms / T, 4)}
+
+    # FP64 plain: FP64 NFFT, one vector per matvec
+    fp64 = None
+    if not a.no_fp64:
+        kp64 = [mlg.kparams("nfft", 64, N=a.N, window=a.window) for _ in range(T)]
+        g64 = mlg.Graph(layers_dev, c["sigma"], kp64)
+        x1 = X[:, :1].contiguous()
+        for _ in range(2):
+            g64.laplacian_matvec(-1, mlg.MLG_OP_LSYM, x1)
+        torch.cuda.synchronize()
+        k64 = max(3, a.steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(k64):
+            g64.laplacian_matvec(-1, mlg.MLG_OP_LSYM, x1)
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t0
+        r64 = n * T * k64 / el64
+        fp64 = {"value": r64, "ms_per_matvec": el64 / k64 * 1e3, "speedup_fp32_batched": value / r64}
+        g64.close()
+
+    # accuracy on sampled rows and the CPU oracle on the same sample
+    acc = None
+    cpu = None
+    if not a.no_cpu:
+        import oracle
+        rows = gen.rng(c["base_seed"] + 400).choice(n, size=64, replace=False)
+        Xh = X.cpu().numpy()
+        errs, derrs, t_cpu, work = [], [], 0.0, 0
+        for t in range(T):
+            gw = mlg.Graph([layers_dev[t]], [c["sigma"][t]], [kp[t]])
+            Wx = gw.laplacian_matvec(0, mlg.MLG_OP_W, X).cpu().numpy()[rows]
+            t1 = time.perf_counter()
+            ref = oracle.kernel_rows(c["layers"][t], c["sigma"][t], Xh, rows)
+            t_cpu += time.perf_counter() - t1
+            work += len(rows) * b
+            # relative error of the sampled rows, per vector, max over vectors
+            errs.append(float((np.linalg.norm(Wx - ref, axis=0) / np.linalg.norm(ref, axis=0)).max()))
+            dref = oracle.kernel_rows(c["layers"][t], c["sigma"][t], np.ones(n), rows)
+            derrs.append(float(np.abs(gw.degrees(0)[rows] - dref).max() / np.abs(dref).max()))
+            gw.close()
+        acc = {"rows": int(len(rows)), "max_rel_err_W_rows": max(errs),
+               "max_rel_err_degree_rows": max(derrs)}
+        cpu = {"value": work / t_cpu, "unit": UNIT, "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+               "kind": "oracle",
+               "sample": "64 sampled rows x all %d columns x %d layers x %d vectors of W_t X "
+                         "(FP64 direct sum with compensated summation)" % (n, T, b)}
+
+    out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "image1000x1000_3layer_L1_block16", "n": n, "layers": T,
+                      "block": b, "layer_params": infos, "plan_s": round(plan_s, 3),
+                      "parallelism": "single GPU"},
+           "stages_ms": {k: round(v, 4) for k, v in st.items()},
+           "roofline": roof, "fp64_plain": fp64, "accuracy": acc, "cpu_baseline": cpu}
+    g.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

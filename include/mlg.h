@@ -204,15 +204,15 @@ mlg_status mlg_allen_cahn_ssl(int64_t n, int k, int m, const double *evals,
 
 /* ---- measurement helpers ------------------------------------------------ */
 
-/* Stages of one layer's matvec, for mlg_profile_stages. */
-#define MLG_STAGE_PRE 0     /* gather + D^-1/2 scaling + cast (Sec. 2)       */
-#define MLG_STAGE_SPREAD 1  /* window spreading, Alg. 1 step 1 (part)        */
-#define MLG_STAGE_GATHER 2  /* patch gather onto the grid (part of spread)   */
-#define MLG_STAGE_FFT 3     /* forward FFT, multiply, inverse FFT (Alg. 1)   */
-#define MLG_STAGE_INTERP 4  /* interpolation, Alg. 1 step 3 (part)           */
-#define MLG_STAGE_POST 5    /* self term, D^-1/2, layer mean (Sec. 2-4)      */
-#define MLG_STAGE_DIRECT 6  /* direct tiled summation                        */
-#define MLG_STAGE_IO 7      /* block transposes in and out                   */
+/* Stages of one matvec, for mlg_profile_stages. */
+#define MLG_STAGE_PRE 0     /* scatter-in: z_t = D_t^-1/2 x, sorted, cast (Sec. 2) */
+#define MLG_STAGE_SPREAD 1  /* window spreading into bin patches, Alg. 1 step 1 */
+#define MLG_STAGE_GATHER 2  /* patch sums onto the grid (part of spreading)     */
+#define MLG_STAGE_FFT 3     /* forward FFT, multiply, inverse FFT (Alg. 1)      */
+#define MLG_STAGE_INTERP 4  /* interpolation, Alg. 1 step 3 (part)              */
+#define MLG_STAGE_POST 5    /* gather-out: self term, D^-1/2, layer mean, y     */
+#define MLG_STAGE_DIRECT 6  /* direct tiled summation                          */
+#define MLG_STAGE_IO 7      /* unused (kept for layout stability)               */
 #define MLG_NSTAGES 8
 
 /*

@@ -2,11 +2,11 @@
 //
 // A matvec with the layer mean (Sec. 3, eq. for I - L_1) or one layer's
 // operator (Sec. 2) runs as
-//   block transpose X -> Xr (point-major FP64)
-//   per layer: z = D^-1/2 x gathered into the layer's sorted order and cast
-//              to the summation precision; F = W~ z (NFFT, Algorithm 1) or
-//              F = W z (direct); y (+)= coef D^-1/2 (F - K(0) z) in FP64
-//   block transpose Yr -> Y (with Y = X - Yr for L_sym / L_1).
+//   scatter-in: z_t = D_t^-1/2 x for every layer, in the layer's sorted order
+//               and summation precision;
+//   per layer:  F_t = W~_t z_t (NFFT, Algorithm 1) or W_t z_t (direct);
+//   gather-out: y = coef sum_t D_t^-1/2 (F_t - K(0) z_t) in FP64 (y = x - that
+//               for L_sym / L_1), written column-major.
 // The per-layer part is captured once into a HIP graph and replayed.
 #include <algorithm>
 #include <cmath>
@@ -54,43 +54,53 @@ static int max_window(const NfftPlan &P) {
     return w & ~1;
 }
 
-struct Workspace {
+// Per-layer workspace slices: Zs/Fs hold n x bs values of each layer's
+// precision; patch and grid are shared by the layers (used one at a time).
+static void ensure_ws(Graph &g, int bs) {
     size_t zs = 0, patch = 0, grid = 0, part = 0;
-};
-
-static Workspace need(const Graph &g, int layer, int bs) {
-    Workspace w;
+    std::vector<size_t> slice(g.T);
     for (int t = 0; t < g.T; ++t) {
-        if (layer >= 0 && t != layer) continue;
         const Layer &L = g.layers[t];
         const size_t esz = L.kp.precision == 64 ? 8 : 4;
-        w.zs = std::max(w.zs, (size_t)g.n * bs * esz);
+        slice[t] = zs;
+        zs += ((size_t)g.n * bs * esz + 255) / 256 * 256;
         if (L.kp.method == MLG_METHOD_NFFT) {
-            w.patch = std::max(w.patch, nfft_patch_elems(L.nf, L.win, bs) * esz);
-            w.grid = std::max(w.grid, nfft_grid_elems(L.nf, bs) * esz);
+            patch = std::max(patch, nfft_patch_elems(L.nf, L.win, bs) * esz);
+            grid = std::max(grid, nfft_grid_elems(L.nf, bs) * esz);
         } else {
             size_t ps = esz == 8 ? direct_part_size<double>(g.n, bs) : direct_part_size<float>(g.n, bs);
-            w.part = std::max(w.part, ps * esz);
+            part = std::max(part, ps * esz);
         }
     }
-    return w;
-}
-
-// Grow workspaces; returns true if any buffer moved (captured graphs stale).
-static bool ensure_ws(Graph &g, int layer, int b, int bs) {
-    Workspace w = need(g, layer, bs);
-    void *before[7] = {g.Xr.p, g.Yr.p, g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
-    g.Xr.ensure((size_t)g.n * b);
-    g.Yr.ensure((size_t)g.n * b);
-    g.Zs.ensure(w.zs);
-    g.Fs.ensure(w.zs);
-    g.patch.ensure(w.patch);
-    g.grid.ensure(w.grid);
-    g.part.ensure(w.part);
-    void *after[7] = {g.Xr.p, g.Yr.p, g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
-    for (int i = 0; i < 7; ++i)
-        if (before[i] != after[i]) return true;
-    return false;
+    void *before[5] = {g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
+    g.Zs.ensure(zs);
+    g.Fs.ensure(zs);
+    g.patch.ensure(patch);
+    g.grid.ensure(grid);
+    g.part.ensure(part);
+    void *after[5] = {g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
+    bool moved = g.ws_bs != bs;
+    for (int i = 0; i < 5; ++i)
+        if (before[i] != after[i]) moved = true;
+    if (!moved) return;
+    for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
+    g.caps.clear();
+    g.slice = slice;
+    g.ws_bs = bs;
+    std::vector<LayerIO> io(g.T);
+    for (int t = 0; t < g.T; ++t) {
+        const Layer &L = g.layers[t];
+        io[t].Z = g.Zs.p + slice[t];
+        io[t].F = g.Fs.p + slice[t];
+        io[t].invperm = L.sorted ? L.invperm.p : nullptr;
+        io[t].dinv = L.dinv.p;
+        io[t].K0 = L.kp.method == MLG_METHOD_NFFT ? 1.0 : 0.0;
+        io[t].is64 = L.kp.precision == 64;
+        io[t].pad = 0;
+    }
+    g.io.alloc(g.T);
+    MLG_HIP(hipMemcpyAsync(g.io.p, io.data(), sizeof(LayerIO) * g.T, hipMemcpyHostToDevice, g.stream));
+    MLG_HIP(hipStreamSynchronize(g.stream));
 }
 
 struct StageTimer {
@@ -98,23 +108,18 @@ struct StageTimer {
     double *acc;
 };
 
+// F_t = W~ z_t (NFFT) or W z_t (direct) for one layer, in its slices.
 template <class T>
-static void layer_core(Graph &g, Layer &L, int op, int b, int bs, double coef, bool accumulate,
-                       StageTimer *tm) {
+static void layer_core(Graph &g, int t, int bs, StageTimer *tm) {
     hipStream_t s = g.stream;
-    const int *perm = L.sorted ? L.nf.perm.p : nullptr;
-    const double *dinv = (op == MLG_OP_W) ? nullptr : L.dinv_s.p;
-    T *Zs = reinterpret_cast<T *>(g.Zs.p);
-    T *Fs = reinterpret_cast<T *>(g.Fs.p);
+    Layer &L = g.layers[t];
+    T *Zs = reinterpret_cast<T *>(g.Zs.p + g.slice[t]);
+    T *Fs = reinterpret_cast<T *>(g.Fs.p + g.slice[t]);
     float ms = 0.f;
-    if (tm) MLG_HIP(hipEventRecord(tm->ev[0], s));
-    launch_pre<T>(g.n, b, bs, perm, dinv, g.Xr.p, Zs, s);
-    if (tm) {
-        MLG_HIP(hipEventRecord(tm->ev[5], s));
-    }
+    if (tm) MLG_HIP(hipEventRecord(tm->ev[5], s));
     if (L.kp.method == MLG_METHOD_NFFT) {
         nfft_apply<T>(L.nf, L.win, bs, Zs, Fs, reinterpret_cast<T *>(g.patch.p),
-                      reinterpret_cast<T *>(g.grid.p), s, tm ? tm->ev + 0 : nullptr);
+                      reinterpret_cast<T *>(g.grid.p), s, tm ? tm->ev : nullptr);
     } else {
         const T *x = nullptr;
         if constexpr (sizeof(T) == 8) x = L.x64.p; else x = L.x32.p;
@@ -122,15 +127,8 @@ static void layer_core(Graph &g, Layer &L, int op, int b, int bs, double coef, b
                          reinterpret_cast<T *>(g.part.p), g.part.n / sizeof(T), s);
         if (tm) MLG_HIP(hipEventRecord(tm->ev[4], s));
     }
-    const double K0 = L.kp.method == MLG_METHOD_NFFT ? 1.0 : 0.0;
-    launch_post<T>(g.n, b, bs, perm, dinv, coef, K0, Fs, Zs, g.Yr.p, accumulate ? 1 : 0, s);
     if (tm) {
-        MLG_HIP(hipEventRecord(tm->ev[6], s));
         MLG_HIP(hipStreamSynchronize(s));
-        // ev[0]: start (pre begins); ev[5]: pre done.  For NFFT, nfft_apply
-        // re-records ev[0] is not used; its own events are ev[1..4] after ev[5].
-        MLG_HIP(hipEventElapsedTime(&ms, tm->ev[0], tm->ev[5]));
-        tm->acc[MLG_STAGE_PRE] += ms;
         if (L.kp.method == MLG_METHOD_NFFT) {
             MLG_HIP(hipEventElapsedTime(&ms, tm->ev[5], tm->ev[1]));
             tm->acc[MLG_STAGE_SPREAD] += ms;
@@ -144,22 +142,16 @@ static void layer_core(Graph &g, Layer &L, int op, int b, int bs, double coef, b
             MLG_HIP(hipEventElapsedTime(&ms, tm->ev[5], tm->ev[4]));
             tm->acc[MLG_STAGE_DIRECT] += ms;
         }
-        MLG_HIP(hipEventElapsedTime(&ms, tm->ev[4], tm->ev[6]));
-        tm->acc[MLG_STAGE_POST] += ms;
     }
 }
 
-static void core(Graph &g, int layer, int op, int b, int bs, StageTimer *tm) {
-    bool first = true;
-    const double coef = layer < 0 ? 1.0 / g.T : 1.0;
+static void core(Graph &g, int layer, int bs, StageTimer *tm) {
     for (int t = 0; t < g.T; ++t) {
         if (layer >= 0 && t != layer) continue;
-        Layer &L = g.layers[t];
-        if (L.kp.precision == 64)
-            layer_core<double>(g, L, op, b, bs, coef, !first, tm);
+        if (g.layers[t].kp.precision == 64)
+            layer_core<double>(g, t, bs, tm);
         else
-            layer_core<float>(g, L, op, b, bs, coef, !first, tm);
-        first = false;
+            layer_core<float>(g, t, bs, tm);
     }
 }
 
@@ -174,48 +166,44 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
                           double *Y, int64_t ldy, double *stage_ms) {
     check_op(g, layer, op, b);
     const int bs = block_stride(b);
-    if (ensure_ws(g, layer, b, bs)) {
-        for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
-        g.caps.clear();
-    }
+    ensure_ws(g, bs);
     hipStream_t s = g.stream;
+    const LayerIO *io = layer >= 0 ? g.io.p + layer : g.io.p;
+    const int nl = layer >= 0 ? 1 : g.T;
+    const int use_dinv = op != MLG_OP_W;
+    const double coef = layer < 0 ? 1.0 / g.T : 1.0;
     if (stage_ms) {
         StageTimer tm;
         tm.acc = stage_ms;
         for (auto &e : tm.ev) MLG_HIP(hipEventCreate(&e));
-        hipEvent_t io0, io1;
-        MLG_HIP(hipEventCreate(&io0));
-        MLG_HIP(hipEventCreate(&io1));
         float ms;
-        MLG_HIP(hipEventRecord(io0, s));
-        launch_to_rowmajor(g.n, b, X, ldx, g.Xr.p, s);
-        MLG_HIP(hipEventRecord(io1, s));
+        MLG_HIP(hipEventRecord(tm.ev[6], s));
+        launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
+        MLG_HIP(hipEventRecord(tm.ev[7], s));
         MLG_HIP(hipStreamSynchronize(s));
-        MLG_HIP(hipEventElapsedTime(&ms, io0, io1));
-        stage_ms[MLG_STAGE_IO] += ms;
-        core(g, layer, op, b, bs, &tm);
-        MLG_HIP(hipEventRecord(io0, s));
-        launch_finish(g.n, b, g.Yr.p, X, ldx, Y, ldy, op == MLG_OP_LSYM, s);
-        MLG_HIP(hipEventRecord(io1, s));
+        MLG_HIP(hipEventElapsedTime(&ms, tm.ev[6], tm.ev[7]));
+        stage_ms[MLG_STAGE_PRE] += ms;
+        core(g, layer, bs, &tm);
+        MLG_HIP(hipEventRecord(tm.ev[6], s));
+        launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
+        MLG_HIP(hipEventRecord(tm.ev[7], s));
         MLG_HIP(hipStreamSynchronize(s));
-        MLG_HIP(hipEventElapsedTime(&ms, io0, io1));
-        stage_ms[MLG_STAGE_IO] += ms;
+        MLG_HIP(hipEventElapsedTime(&ms, tm.ev[6], tm.ev[7]));
+        stage_ms[MLG_STAGE_POST] += ms;
         for (auto &e : tm.ev) (void)hipEventDestroy(e);
-        (void)hipEventDestroy(io0);
-        (void)hipEventDestroy(io1);
         return;
     }
-    launch_to_rowmajor(g.n, b, X, ldx, g.Xr.p, s);
+    launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
     hipGraphExec_t exec = nullptr;
     for (auto &c : g.caps)
-        if (c.layer == layer && c.op == op && c.b == b) exec = c.exec;
+        if (c.layer == layer && c.b == bs) exec = c.exec;
     if (!exec) {
         hipGraph_t graph;
         MLG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-            core(g, layer, op, b, bs, nullptr);
+            core(g, layer, bs, nullptr);
         } catch (...) {
-            hipGraph_t junk;
+            hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(s, &junk);
             if (junk) (void)hipGraphDestroy(junk);
             throw;
@@ -224,37 +212,46 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         MLG_HIP(e);
-        g.caps.push_back({layer, op, b, exec});
+        g.caps.push_back({layer, 0, bs, exec});
     }
     MLG_HIP(hipGraphLaunch(exec, s));
-    launch_finish(g.n, b, g.Yr.p, X, ldx, Y, ldy, op == MLG_OP_LSYM, s);
+    launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
 }
 
 // Degrees deg = W 1 in FP64: for NFFT layers a high-accuracy FP64 window.
 static void compute_degrees(Graph &g, Layer &L) {
     hipStream_t s = g.stream;
     const int64_t n = g.n;
-    DevBuf<double> ones(n), Z(n * 1), F(n * 1);
+    DevBuf<double> ones(n), Z(n), F(n);
     launch_fill_ones(n, ones.p, s);
     L.deg.alloc(n);
-    const int *perm = L.sorted ? L.nf.perm.p : nullptr;
-    launch_pre<double>(n, 1, 1, perm, nullptr, ones.p, Z.p, s);
-    double K0 = 0.0;
+    LayerIO io{};
+    io.Z = Z.p;
+    io.F = F.p;
+    io.invperm = L.sorted ? L.invperm.p : nullptr;
+    io.dinv = nullptr;
+    io.is64 = 1;
+    DevBuf<LayerIO> dio(1);
     if (L.kp.method == MLG_METHOD_NFFT) {
         NfftWindow Wd;
         int wdeg = std::min(14, max_window(L.nf));
         wdeg = std::max(wdeg, default_window(L));
         nfft_make_window(L, Wd, wdeg, 64, 1, s);
+        io.K0 = 1.0;
+        MLG_HIP(hipMemcpyAsync(dio.p, &io, sizeof(io), hipMemcpyHostToDevice, s));
+        launch_scatter_in(n, 1, 1, ones.p, n, dio.p, 1, 0, s);
         DevBuf<double> patch(nfft_patch_elems(L.nf, Wd, 1)), grid(nfft_grid_elems(L.nf, 1));
         nfft_apply<double>(L.nf, Wd, 1, Z.p, F.p, patch.p, grid.p, s, nullptr);
-        K0 = 1.0;
-        launch_post<double>(n, 1, 1, perm, nullptr, 1.0, K0, F.p, Z.p, L.deg.p, 0, s);
+        launch_gather_out(n, 1, 1, ones.p, n, L.deg.p, n, dio.p, 1, 0, 0, 1.0, s);
         MLG_HIP(hipStreamSynchronize(s));
     } else {
+        io.K0 = 0.0;
+        MLG_HIP(hipMemcpyAsync(dio.p, &io, sizeof(io), hipMemcpyHostToDevice, s));
+        launch_scatter_in(n, 1, 1, ones.p, n, dio.p, 1, 0, s);
         DevBuf<double> part(direct_part_size<double>(n, 1));
         launch_direct<double>(n, L.d, L.x64.p, 1.0 / (L.sigma * L.sigma), 1, Z.p, F.p, part.p,
                               part.n, s);
-        launch_post<double>(n, 1, 1, perm, nullptr, 1.0, 0.0, F.p, Z.p, L.deg.p, 0, s);
+        launch_gather_out(n, 1, 1, ones.p, n, L.deg.p, n, dio.p, 1, 0, 0, 1.0, s);
         MLG_HIP(hipStreamSynchronize(s));
     }
     DevBuf<int> flag(1);
@@ -265,8 +262,8 @@ static void compute_degrees(Graph &g, Layer &L) {
     MLG_HIP(hipMemcpyAsync(&hf, flag.p, 4, hipMemcpyDeviceToHost, s));
     MLG_HIP(hipStreamSynchronize(s));
     MLG_REQUIRE(hf == 0, MLG_ERR_ISOLATED, "a node has zero degree (isolated) in some layer");
-    L.dinv_s.alloc(n);
-    launch_dinv(n, L.deg.p, perm, L.dinv_s.p, s);
+    L.dinv.alloc(n);
+    launch_dinv(n, L.deg.p, L.dinv.p, s);
     MLG_HIP(hipStreamSynchronize(s));
 }
 
@@ -288,6 +285,8 @@ static void build_layer(Graph &g, Layer &L, const double *pts, bool dev, bool de
     if (L.kp.method == MLG_METHOD_NFFT) {
         nfft_plan_layer(L, p, s);
         L.sorted = 1;
+        L.invperm.alloc(n);
+        launch_invperm(n, L.nf.perm.p, L.invperm.p, s);
         int w = default_window(L);
         nfft_make_window(L, L.win, w, L.kp.precision, 1, s);
     }

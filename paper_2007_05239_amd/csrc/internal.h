@@ -29,6 +29,10 @@ struct NfftPlan {
     DevBuf<int4> tasks;     // (bin key, first point, count, destination patch slot)
     DevBuf<int4> multi;     // (run, first scratch slot, task count, 0)
     DevBuf<int> bin_run;    // per bin: run index or -1
+    DevBuf<unsigned> run_key;   // per run: its bin key
+    int nred1 = 0, nred2 = 0;
+    DevBuf<int2> red1;      // level-1 reduction groups (first slot, count <= 32)
+    DevBuf<int4> red2;      // level-2 (run, first scratch slot, groups, 0)
     int SB = 8, nsb = 0;    // superbin edge (bins) and superbins per dimension
     DevBuf<unsigned char> occ;  // per superbin: 1 if occupied
     DevBuf<double> bhat;    // kernel Fourier coefficients b^_l, l in [0,N)^d (index l mod N)
@@ -43,6 +47,11 @@ struct NfftWindow {
     int prec = 32;
     DevBuf<float> M32;   // nos^d real multipliers
     DevBuf<double> M64;
+    // grid cell -> patch entries (run * PD + cell offset), sorted; empty
+    // when the table would be too large (the gather then walks the bins)
+    bool csr = false;
+    DevBuf<int> cell_ptr;   // nos^d + 1
+    DevBuf<int> cell_ent;
 };
 
 struct Layer {
@@ -57,23 +66,32 @@ struct Layer {
     NfftPlan nf;
     NfftWindow win;          // matvec window
     DevBuf<double> deg;      // degrees, original order
-    DevBuf<double> dinv_s;   // D^-1/2 in sorted (NFFT) or original (direct) order
-    int sorted = 0;          // 1 if perm applies
+    DevBuf<double> dinv;     // D^-1/2, original order
+    DevBuf<int> invperm;     // original index -> sorted position (NFFT layers)
+    int sorted = 0;          // 1 if the layer's points are kept in sorted order
+};
+
+// What the block entry/exit kernels need to know about one layer.
+struct LayerIO {
+    void *Z;                 // n x bs input of the summation (sorted order), float or double
+    const void *F;           // n x bs output of the summation
+    const int *invperm;      // null: identity
+    const double *dinv;      // D^-1/2, original order
+    double K0;               // self term removed after the summation (0 for direct)
+    int is64;
+    int pad;
 };
 
 // ---- layer_ops.hip ----------------------------------------------------------
-void launch_to_rowmajor(int64_t n, int b, const double *X, int64_t ldx, double *Xr, hipStream_t s);
-void launch_finish(int64_t n, int b, const double *Yr, const double *X, int64_t ldx, double *Y,
-                   int64_t ldy, int lsym, hipStream_t s);
-template <class T>
-void launch_pre(int64_t n, int b, int bs, const int *perm, const double *dinv, const double *Xr,
-                T *Zs, hipStream_t s);
-template <class T>
-void launch_post(int64_t n, int b, int bs, const int *perm, const double *dinv, double coef,
-                 double K0, const T *Fs, const T *Zs, double *Yr, int accumulate, hipStream_t s);
+void launch_scatter_in(int64_t n, int b, int bs, const double *X, int64_t ldx, const LayerIO *L,
+                       int nl, int use_dinv, hipStream_t s);
+void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, double *Y,
+                       int64_t ldy, const LayerIO *L, int nl, int use_dinv, int lsym, double coef,
+                       hipStream_t s);
 void launch_fill_ones(int64_t n, double *Xr, hipStream_t s);
 void launch_check_degrees(int64_t n, const double *deg, double thresh, int *flag, hipStream_t s);
-void launch_dinv(int64_t n, const double *deg, const int *perm, double *dinv_s, hipStream_t s);
+void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s);
+void launch_invperm(int64_t n, const int *perm, int *inv, hipStream_t s);
 
 // ---- direct.hip ---------------------------------------------------------------
 template <class T>
@@ -109,18 +127,18 @@ struct Graph {
     int T = 0;
     hipStream_t stream = nullptr;
     std::vector<Layer> layers;
-    // workspaces
-    DevBuf<double> Xr, Yr;         // n x b point-major FP64
-    DevBuf<char> Zs, Fs;           // n x bs, T
+    // workspaces: per-layer slices of Zs/Fs (n x bs, the layer's precision)
+    DevBuf<char> Zs, Fs;
     DevBuf<char> patch, grid, part;
+    int ws_bs = 0;                 // block stride the slices are laid out for
+    std::vector<size_t> slice;     // byte offset of layer t's slice
+    DevBuf<LayerIO> io;            // device copy of the T layer descriptors
     // captured graphs keyed by (layer, op, b)
     struct Cap {
         int layer, op, b;
         hipGraphExec_t exec;
     };
     std::vector<Cap> caps;
-    DevBuf<void *> argbuf;         // device copy of (X, Y) pointers for replays
-    DevBuf<int64_t> argld;
     ~Graph();
 };
 

@@ -32,6 +32,7 @@
 //            psi(u_p - k) h_k.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -441,6 +442,7 @@ __global__ __launch_bounds__(64) void k_spread(Geom g, const int4 *__restrict__ 
         for (int v = 0; v < VPL; ++v) acc[j][v] = T(0);
     }
     const T two_over_w = T(2) / (T)g.w;
+    const int cpl = (PD + 63) / 64;
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
         const int64_t first = (int64_t)tk.y + c0;
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(64) void k_spread(Geom g, const int4 *__restrict__ 
             for (int v = 0; v < VPL; ++v) zz[v] = zv[pt * VPL + v];
 #pragma unroll
             for (int j = 0; j < CMAX; ++j) {
-                if (qoff[j] >= 0) {
+                if (j < cpl && qoff[j] >= 0) {   // j < cpl is uniform
                     T wgt = wp[qoff[j] & 0xff];
                     if (D > 1) wgt *= wp[(qoff[j] >> 8) & 0xff];
                     if (D > 2) wgt *= wp[(qoff[j] >> 16) & 0xff];
@@ -488,16 +490,85 @@ __global__ __launch_bounds__(64) void k_spread(Geom g, const int4 *__restrict__ 
         if (qoff[j] >= 0) store_vec<T, VPL>(out + (int64_t)(lane + 64 * j) * bs, acc[j]);
 }
 
-// Bins cut into several tasks: patch[run] = sum of the run's task patches,
-// in task order.
+// Bins cut into several tasks: their task patches are summed in a fixed
+// two-level order.  Level 1: each group of up to 32 consecutive task patches
+// (int2: first slot, count) is summed in task order into its first slot.
 template <class T>
-__global__ void k_binreduce(int64_t elems, const int4 *__restrict__ multi, T *__restrict__ patch) {
+__global__ void k_reduce1(int64_t elems, const int2 *__restrict__ grp, T *__restrict__ patch) {
     const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
     if (e >= elems) return;
-    const int4 mr = multi[blockIdx.x];
-    T s = patch[(int64_t)mr.y * elems + e];
-    for (int j = 1; j < mr.z; ++j) s += patch[(int64_t)(mr.y + j) * elems + e];
-    patch[(int64_t)mr.x * elems + e] = s;
+    const int2 gr = grp[blockIdx.x];
+    const T *src = patch + (int64_t)gr.x * elems + e;
+    T s = src[0];
+    for (int j = 1; j < gr.y; ++j) s += src[(int64_t)j * elems];
+    patch[(int64_t)gr.x * elems + e] = s;
+}
+
+// Level 2 (int4: run, first scratch slot, groups, 0): the group sums, in
+// group order, into the run's own patch slot.
+template <class T>
+__global__ void k_reduce2(int64_t elems, const int4 *__restrict__ runs, T *__restrict__ patch) {
+    const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= elems) return;
+    const int4 r = runs[blockIdx.x];
+    const T *src = patch + (int64_t)r.y * elems + e;
+    T s = src[0];
+    for (int j = 1; j < r.z; ++j) s += src[(int64_t)j * 32 * elems];
+    patch[(int64_t)r.x * elems + e] = s;
+}
+
+// Patch entry e = run * PD + o covers grid cell key[e].
+__global__ void k_csr_keys(int64_t total, int d, int PD, int P, int nos, int B, int nb, int w,
+                           const unsigned *__restrict__ run_key, unsigned *__restrict__ keys,
+                           int *__restrict__ vals) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t u = e / PD;
+    int o = (int)(e - u * PD);
+    unsigned key = run_key[u];
+    int64_t cell = 0, mul = 1;
+    for (int t = 0; t < d; ++t) {
+        const int b = (int)(key % (unsigned)nb);
+        key /= (unsigned)nb;
+        const int q = o % P;
+        o /= P;
+        cell += (int64_t)(b * B - w / 2 + 1 + q) * mul;
+        mul *= nos;
+    }
+    keys[e] = (unsigned)cell;
+    vals[e] = (int)e;
+}
+
+__global__ void k_scatter_counts(int nu, const unsigned *__restrict__ ucell,
+                                 const unsigned *__restrict__ cnt, int *__restrict__ dense) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nu) dense[ucell[i]] = (int)cnt[i];
+}
+
+// Gather through the cell table: sum of the cell's patch entries in entry
+// order (entries of one cell are sorted by run).
+template <class T, int VPL>
+__global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
+                                                    const int *__restrict__ ptr,
+                                                    const int *__restrict__ ent,
+                                                    const T *__restrict__ patch,
+                                                    T *__restrict__ grid) {
+    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= G) return;
+    const int v0 = blockIdx.y * VPL;
+    T acc[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) acc[v] = T(0);
+    const int e1 = ptr[cell + 1];
+    for (int e = ptr[cell]; e < e1; ++e) {
+        T h[VPL];
+        load_vec<T, VPL>(patch + (int64_t)ent[e] * bs + v0, h);
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) acc[v] += h[v];
+    }
+    store_vec<T, VPL>(grid + cell * bg + v0, acc);
+    if (bg > bs && blockIdx.y == 0)
+        for (int v = bs; v < bg; ++v) grid[cell * bg + v] = T(0);
 }
 
 // Gather: one thread per (grid cell, vector group): sum over the bins whose
@@ -564,6 +635,239 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, int SB, int nsb,
         for (int v = bs; v < bg; ++v) grid[cell * bg + v] = T(0);
 }
 
+// ------------------------------------------------------------------------------
+// FP32 matrix-core variants (16 vectors per workgroup).  Within one task the
+// spreading is the dense product  patch (PD x 16) = Wt (PD x pts) Z (pts x 16)
+// and the interpolation  F (pts x 16) = Wt^T (pts x PD) H (PD x 16), with
+// Wt[c][p] the window weight of point p at patch cell c: both run on
+// v_mfma_f32_16x16x4_f32 (FP32 inputs, FP32 accumulation).
+// Operand layout of that instruction (one wavefront): A[i][k] in lane i+16k,
+// B[k][j] in lane j+16k, D[i][j] in register i%4 of lane j+16*(i/4).
+// ------------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Per-point window weights in LDS: wx[P] | wy[P] | wz[P] | wyz[P*P] (D = 3),
+// wx[P] | wy[P] (D = 2), wx[P] (D = 1), then one zero slot; zero outside the
+// point's footprint.  Records of absent points are all zero, so the inner
+// loops need no branches.
+template <int D>
+__host__ __device__ inline int wstride_of(int P) {
+    return (D == 3 ? 3 * P + P * P : D * P) + 1;
+}
+
+template <int D>
+__device__ inline void stage_point_weights(const Geom &g, const int *__restrict__ c32,
+                                           const float *__restrict__ f32, int64_t p,
+                                           const int org[3], float beta, float *__restrict__ wp) {
+    const int P = g.P;
+    const float two_over_w = 2.0f / (float)g.w;
+    for (int t = 0; t < D; ++t) {
+        const int cell = c32[(int64_t)t * g.n + p];
+        const float frac = f32[(int64_t)t * g.n + p];
+        const int s0 = cell - g.w / 2 + 1;
+        for (int q = 0; q < P; ++q) {
+            const int k = org[t] + q;
+            float val = 0.0f;
+            if (k >= s0 && k < s0 + g.w) val = es_psi<float>((float)(cell - k) + frac, two_over_w, beta);
+            wp[t * P + q] = val;
+        }
+    }
+    if (D == 3)
+        for (int qz = 0; qz < P; ++qz)
+            for (int qy = 0; qy < P; ++qy) wp[3 * P + qy + P * qz] = wp[P + qy] * wp[2 * P + qz];
+    wp[wstride_of<D>(P) - 1] = 0.0f;
+}
+
+__device__ inline void zero_record(int ws, float *__restrict__ wp) {
+    for (int q = 0; q < ws; ++q) wp[q] = 0.0f;
+}
+
+// Offsets of a patch cell's two weight factors inside a point's record; cells
+// beyond the patch point at the zero slot.
+template <int D>
+__device__ inline void cell_offsets(int c, int P, int PD, int &ia, int &ib) {
+    const int zs = wstride_of<D>(P) - 1;
+    if (c >= PD) { ia = zs; ib = zs; return; }
+    ia = c % P;
+    ib = D == 3 ? 3 * P + c / P : (D == 2 ? P + c / P : zs);
+}
+
+// NT tiles of 16 patch cells (16*NT >= PD).
+template <int D, int NT>
+__global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restrict__ tasks,
+                                                    const int *__restrict__ c32,
+                                                    const float *__restrict__ f32,
+                                                    const float *__restrict__ Zs, float beta,
+                                                    float *__restrict__ patch) {
+    extern __shared__ unsigned char smem_raw[];
+    const int P = g.P, PD = g.PD, bs = g.bs;
+    const int ws = wstride_of<D>(P);
+    float *wts = reinterpret_cast<float *>(smem_raw);   // [64][ws]
+    float *zv = wts + 64 * ws;                          // [64][16]
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int4 tk = tasks[blockIdx.x];
+    const int v0 = blockIdx.y * 16;
+    int org[3] = {0, 0, 0};
+    {
+        unsigned key = (unsigned)tk.x;
+        for (int t = 0; t < D; ++t) {
+            org[t] = (int)(key % (unsigned)g.nb) * g.B - g.w / 2 + 1;
+            key /= (unsigned)g.nb;
+        }
+    }
+    int ia[NT], ib[NT];
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        cell_offsets<D>(16 * t + li, P, PD, ia[t], ib[t]);
+        acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int c0 = 0; c0 < tk.z; c0 += 64) {
+        const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
+        const int64_t first = (int64_t)tk.y + c0;
+        __syncthreads();
+        float *myw = wts + lane * ws;
+        if (lane < cnt) {
+            stage_point_weights<D>(g, c32, f32, first + lane, org, beta, myw);
+            const float *zp = Zs + (first + lane) * bs + v0;
+#pragma unroll
+            for (int j = 0; j < 16; j += 4) {
+                float4 q = *reinterpret_cast<const float4 *>(zp + j);
+                zv[lane * 16 + j] = q.x; zv[lane * 16 + j + 1] = q.y;
+                zv[lane * 16 + j + 2] = q.z; zv[lane * 16 + j + 3] = q.w;
+            }
+        } else {
+            zero_record(ws, myw);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) zv[lane * 16 + j] = 0.0f;
+        }
+        __syncthreads();
+        for (int pt0 = 0; pt0 < cnt; pt0 += 4) {
+            const int pk = pt0 + lk;                 // point of this lane's k slot (< 64)
+            const float b = zv[pk * 16 + li];
+            const float *wp = wts + pk * ws;
+            float a[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) a[t] = D > 1 ? wp[ia[t]] * wp[ib[t]] : wp[ia[t]];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b, acc[t], 0, 0, 0);
+        }
+    }
+    float *out = patch + (int64_t)tk.w * PD * bs + v0 + li;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 16 * t + 4 * lk + r;
+            if (c < PD) out[(int64_t)c * bs] = acc[t][r];
+        }
+    }
+}
+
+// KS = 4*NT cell steps; four groups of 16 points share each B fragment.
+template <int D, int NT>
+__global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restrict__ tasks,
+                                                    const int *__restrict__ c32,
+                                                    const float *__restrict__ f32,
+                                                    const float *__restrict__ grid, int bg,
+                                                    float beta, float *__restrict__ Fs) {
+    constexpr int KS = 4 * NT;
+    extern __shared__ unsigned char smem_raw[];
+    const int P = g.P, PD = g.PD, bs = g.bs;
+    const int ws = wstride_of<D>(P);
+    float *wts = reinterpret_cast<float *>(smem_raw);          // [64][ws]
+    int *tab = reinterpret_cast<int *>(wts + 64 * ws);         // [2][16*NT]
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int4 tk = tasks[blockIdx.x];
+    const int v0 = blockIdx.y * 16;
+    int org[3] = {0, 0, 0};
+    {
+        unsigned key = (unsigned)tk.x;
+        for (int t = 0; t < D; ++t) {
+            org[t] = (int)(key % (unsigned)g.nb) * g.B - g.w / 2 + 1;
+            key /= (unsigned)g.nb;
+        }
+    }
+    for (int c = lane; c < 16 * NT; c += 64) {
+        int a, b;
+        cell_offsets<D>(c, P, PD, a, b);
+        tab[c] = a;
+        tab[16 * NT + c] = b;
+    }
+    // B fragments: the task's patch of the grid, cell 4s + lk, vector li
+    float hb[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        float h = 0.0f;
+        const int c = 4 * s + lk;
+        if (c < PD) {
+            const int qx = c % P, qy = (c / P) % P, qz = c / (P * P);
+            int64_t cell = org[0] + qx;
+            if (D > 1) cell += (int64_t)(org[1] + qy) * g.nos;
+            if (D > 2) cell += (int64_t)(org[2] + qz) * g.nos * g.nos;
+            h = grid[cell * bg + v0 + li];
+        }
+        hb[s] = h;
+    }
+    for (int c0 = 0; c0 < tk.z; c0 += 64) {
+        const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
+        const int64_t first = (int64_t)tk.y + c0;
+        __syncthreads();
+        if (lane < cnt) stage_point_weights<D>(g, c32, f32, first + lane, org, beta, wts + lane * ws);
+        else zero_record(ws, wts + lane * ws);
+        __syncthreads();
+        floatx4 acc[4];
+        const float *wp[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+            wp[q] = wts + (16 * q + li) * ws;        // A row: point 16q + li
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int c = 4 * s + lk;
+            const int ca = tab[c], cb = tab[16 * NT + c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float a = D > 1 ? wp[q][ca] * wp[q][cb] : wp[q][ca];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hb[s], acc[q], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pt = 16 * q + 4 * lk + r;
+                if (pt < cnt) Fs[(first + pt) * bs + v0 + li] = acc[q][r];
+            }
+    }
+}
+
+// Tile counts with a compiled matrix-core variant; a patch uses the first
+// one that covers it (extra cells carry zero weight).
+static const int kNtiles[] = {1, 2, 3, 4, 6, 8, 10, 12, 14, 16};
+
+static int mfma_ntiles(int PD) {
+    for (int nt : kNtiles)
+        if (16 * nt >= PD) return nt;
+    return 0;
+}
+
+#define MLG_NT_SWITCH(nt, CALL)                                                    \
+    switch (nt) {                                                                  \
+        case 1: CALL(1); break;                                                    \
+        case 2: CALL(2); break;                                                    \
+        case 3: CALL(3); break;                                                    \
+        case 4: CALL(4); break;                                                    \
+        case 6: CALL(6); break;                                                    \
+        case 8: CALL(8); break;                                                    \
+        case 10: CALL(10); break;                                                  \
+        case 12: CALL(12); break;                                                  \
+        case 14: CALL(14); break;                                                  \
+        case 16: CALL(16); break;                                                  \
+        default: throw Error(MLG_ERR_ARG, "unsupported tile count");               \
+    }
+
 template <class T>
 struct Cplx;
 template <>
@@ -572,74 +876,114 @@ template <>
 struct Cplx<double> { using type = double2; };
 
 // Batched radix-2 FFT of length L along lines of a [outer][L][inner] complex
-// array.  A workgroup handles LB outers x IC inner columns.
-template <class T>
-__global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict__ data, int L,
-                                             int logL, int64_t outer_cnt, int64_t inner, int IC,
-                                             int LB, int sign,
-                                             const typename Cplx<T>::type *__restrict__ tw) {
-    using C2 = typename Cplx<T>::type;
-    extern __shared__ unsigned char smem_raw[];
-    C2 *buf = reinterpret_cast<C2 *>(smem_raw);
-    const int tid = threadIdx.x;
-    const int64_t nchunk = inner / IC;
-    const int64_t c0 = ((int64_t)blockIdx.x % nchunk) * IC;
-    const int64_t o0 = ((int64_t)blockIdx.x / nchunk) * LB;
-    const int lines = IC * LB;
-    for (int e = tid; e < L * lines; e += 256) {
-        int ln = e % lines, k = e / lines;
-        int oo = ln / IC, cc = ln - oo * IC;
-        int64_t o = o0 + oo;
-        C2 val;
-        val.x = T(0);
-        val.y = T(0);
-        if (o < outer_cnt) val = data[(o * L + k) * inner + c0 + cc];
-        int rk = __brev((unsigned)k) >> (32 - logL);
-        buf[rk * lines + ln] = val;
-    }
-    __syncthreads();
+// array; a workgroup handles LB outers x IC inner columns.  Only frequency
+// lines that can reach the band |l_t| <= N/2 are touched:
+//   cols = 0: every inner column;
+//   cols = 1: inner = [x][q], x frequency in the band;
+//   cols = 2: inner = [y][x][q], x and y frequencies in the band.
+// mode 0: forward; mode 1: inverse, entries whose line index is outside the
+// band read as zero (they were never multiplied); mode 2: forward, times the
+// multiplier M, inverse (the last axis of Algorithm 1 in one pass).
+__device__ inline int band_index(int i, int N, int nos) { return i <= N / 2 ? i : nos - (N + 1) + i; }
+
+__device__ inline bool in_band(int k, int N, int nos) { return k <= N / 2 || k >= nos - N / 2; }
+
+template <class C2>
+__device__ inline void fft_stages(C2 *buf, int L, int logL, int lines, bool inverse,
+                                  const C2 *__restrict__ tw) {
     for (int s = 0; s < logL; ++s) {
         const int half = 1 << s;
         const int tstride = L >> (s + 1);
-        for (int e = tid; e < (L / 2) * lines; e += 256) {
-            int ln = e % lines, bf = e / lines;
-            int grp = bf >> s, pos = bf & (half - 1);
-            int i0 = (grp << (s + 1)) + pos, i1 = i0 + half;
+        for (int e = threadIdx.x; e < (L / 2) * lines; e += blockDim.x) {
+            const int ln = e % lines, bf = e / lines;
+            const int grp = bf >> s, pos = bf & (half - 1);
+            const int i0 = (grp << (s + 1)) + pos, i1 = i0 + half;
             C2 w = tw[pos * tstride];
-            if (sign > 0) w.y = -w.y;
-            C2 a = buf[i0 * lines + ln], b = buf[i1 * lines + ln];
-            C2 bw;
+            if (inverse) w.y = -w.y;
+            const C2 a = buf[i0 * lines + ln], b = buf[i1 * lines + ln];
+            C2 bw, r0, r1;
             bw.x = b.x * w.x - b.y * w.y;
             bw.y = b.x * w.y + b.y * w.x;
-            C2 r0, r1;
-            r0.x = a.x + bw.x;
-            r0.y = a.y + bw.y;
-            r1.x = a.x - bw.x;
-            r1.y = a.y - bw.y;
+            r0.x = a.x + bw.x; r0.y = a.y + bw.y;
+            r1.x = a.x - bw.x; r1.y = a.y - bw.y;
             buf[i0 * lines + ln] = r0;
             buf[i1 * lines + ln] = r1;
         }
         __syncthreads();
     }
-    for (int e = tid; e < L * lines; e += 256) {
-        int ln = e % lines, k = e / lines;
-        int oo = ln / IC, cc = ln - oo * IC;
-        int64_t o = o0 + oo;
-        if (o < outer_cnt) data[(o * L + k) * inner + c0 + cc] = buf[k * lines + ln];
-    }
 }
 
 template <class T>
-__global__ void k_mul(typename Cplx<T>::type *__restrict__ grid, const T *__restrict__ M,
-                      int64_t cells, int nq) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= cells * nq) return;
-    const T m = M[e / nq];
-    auto g = grid[e];
-    g.x *= m;
-    g.y *= m;
-    grid[e] = g;
+__global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict__ data, int L,
+                                             int logL, int64_t outer_cnt, int64_t inner,
+                                             int64_t nact, int IC, int LB, int mode, int cols,
+                                             int N, int nq, const typename Cplx<T>::type *__restrict__ tw,
+                                             const T *__restrict__ M) {
+    using C2 = typename Cplx<T>::type;
+    extern __shared__ unsigned char smem_raw[];
+    C2 *buf = reinterpret_cast<C2 *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int64_t nchunk = (nact + IC - 1) / IC;
+    const int64_t a0 = ((int64_t)blockIdx.x % nchunk) * IC;
+    const int64_t o0 = ((int64_t)blockIdx.x / nchunk) * LB;
+    const int lines = IC * LB;
+    auto column = [&](int64_t a) -> int64_t {
+        if (cols == 0) return a;
+        const int q = (int)(a % nq);
+        const int64_t r = a / nq;
+        if (cols == 1) return (int64_t)band_index((int)r, N, L) * nq + q;
+        const int kx = band_index((int)(r % (N + 1)), N, L), ky = band_index((int)(r / (N + 1)), N, L);
+        return ((int64_t)ky * L + kx) * nq + q;
+    };
+    for (int e = tid; e < L * lines; e += 256) {
+        const int ln = e % lines, k = e / lines;
+        const int oo = ln / IC, cc = ln - oo * IC;
+        const int64_t o = o0 + oo, a = a0 + cc;
+        C2 val;
+        val.x = T(0);
+        val.y = T(0);
+        if (o < outer_cnt && a < nact && (mode != 1 || in_band(k, N, L)))
+            val = data[(o * L + k) * inner + column(a)];
+        const int rk = __brev((unsigned)k) >> (32 - logL);
+        buf[rk * lines + ln] = val;
+    }
+    __syncthreads();
+    fft_stages<C2>(buf, L, logL, lines, mode == 1, tw);
+    if (mode == 2) {
+        // multiply by M (cell = line index * inner extent / nq + column / nq),
+        // then put the line back into bit-reversed order for the inverse
+        for (int e = tid; e < L * lines; e += 256) {
+            const int ln = e % lines, k = e / lines;
+            const int cc = ln % IC;
+            const int64_t a = a0 + cc;
+            T m = T(0);
+            if (a < nact) m = M[(int64_t)k * (inner / nq) + column(a) / nq];
+            C2 v = buf[k * lines + ln];
+            v.x *= m;
+            v.y *= m;
+            buf[k * lines + ln] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < L * lines; e += 256) {
+            const int ln = e % lines, k = e / lines;
+            const int rk = __brev((unsigned)k) >> (32 - logL);
+            if (k < rk) {
+                const C2 t0 = buf[k * lines + ln];
+                buf[k * lines + ln] = buf[rk * lines + ln];
+                buf[rk * lines + ln] = t0;
+            }
+        }
+        __syncthreads();
+        fft_stages<C2>(buf, L, logL, lines, true, tw);
+    }
+    for (int e = tid; e < L * lines; e += 256) {
+        const int ln = e % lines, k = e / lines;
+        const int oo = ln / IC, cc = ln - oo * IC;
+        const int64_t o = o0 + oo, a = a0 + cc;
+        if (o < outer_cnt && a < nact) data[(o * L + k) * inner + column(a)] = buf[k * lines + ln];
+    }
 }
+
 
 // Interpolation: one thread per (point, vector group); window weights in
 // registers, the footprint read from the grid.
@@ -932,6 +1276,8 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     MLG_HIP(hipMemcpyAsync(&tot[2], multi_idx.p + runs, 4, hipMemcpyDeviceToHost, s));
     MLG_HIP(hipStreamSynchronize(s));
     P.nruns = (int)runs;
+    P.run_key.alloc(runs > 0 ? runs : 1);
+    MLG_HIP(hipMemcpyAsync(P.run_key.p, ukeys.p, sizeof(unsigned) * runs, hipMemcpyDeviceToDevice, s));
     P.ntasks = (int)tot[0];
     P.nscratch = (int)tot[1];
     P.nmulti = (int)tot[2];
@@ -943,6 +1289,23 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
                        counts.p, run_start.p, task_first.p, scr_first.p, multi_idx.p, kMaxTaskPoints,
                        P.tasks.p, P.bin_run.p, P.multi.p);
     MLG_LAUNCH_CHECK();
+    // fixed two-level reduction order for runs cut into several tasks
+    if (P.nmulti > 0) {
+        std::vector<int4> hm(P.nmulti);
+        MLG_HIP(hipMemcpyAsync(hm.data(), P.multi.p, sizeof(int4) * P.nmulti, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        std::vector<int2> g1;
+        std::vector<int4> g2;
+        for (const int4 &m : hm) {
+            const int ng = (m.z + 31) / 32;
+            for (int q = 0; q < ng; ++q) g1.push_back(make_int2(m.y + 32 * q, std::min(32, m.z - 32 * q)));
+            g2.push_back(make_int4(m.x, m.y, ng, 0));
+        }
+        P.nred1 = (int)g1.size();
+        P.nred2 = (int)g2.size();
+        upload(P.red1, g1.data(), g1.size(), false, s);
+        upload(P.red2, g2.data(), g2.size(), false, s);
+    }
     P.SB = std::min(8, P.nb);
     P.nsb = (P.nb + P.SB - 1) / P.SB;
     int64_t nsbd = 1;
@@ -1008,6 +1371,52 @@ void nfft_make_window(const Layer &L, NfftWindow &W, int w, int prec, int bs, hi
                            P.bhat.p, ph.p, W.M32.p);
     }
     MLG_LAUNCH_CHECK();
+    // grid cell -> patch entry table
+    W.csr = false;
+    const int Pside = P.B + w - 1;
+    int64_t PDw = 1;
+    for (int t = 0; t < P.d; ++t) PDw *= Pside;
+    const int64_t total = (int64_t)P.nruns * PDw;
+    if (total > 0 && total <= ((int64_t)1 << 28) && G < ((int64_t)1 << 31)) {
+        DevBuf<unsigned> keys(total), skeys(total);
+        DevBuf<int> vals(total);
+        W.cell_ent.alloc(total);
+        hipLaunchKernelGGL(k_csr_keys, dim3(ceil_div(total, 256)), dim3(256), 0, s, total, P.d, (int)PDw,
+                           Pside, P.nos, P.B, P.nb, w, P.run_key.p, keys.p, vals.p);
+        MLG_LAUNCH_CHECK();
+        unsigned endbit = 1;
+        while (((int64_t)1 << endbit) < G) ++endbit;
+        DevBuf<char> tmp;
+        size_t tb = 0;
+        MLG_HIP(rocprim::radix_sort_pairs(nullptr, tb, keys.p, skeys.p, vals.p, W.cell_ent.p,
+                                          (unsigned)total, 0u, endbit, s));
+        tmp.ensure(tb + 1);
+        MLG_HIP(rocprim::radix_sort_pairs(tmp.p, tb, keys.p, skeys.p, vals.p, W.cell_ent.p,
+                                          (unsigned)total, 0u, endbit, s));
+        DevBuf<unsigned> ucell(total), ucnt(total), nu_d(1);
+        tb = 0;
+        MLG_HIP(rocprim::run_length_encode(nullptr, tb, skeys.p, (unsigned)total, ucell.p, ucnt.p,
+                                           nu_d.p, s));
+        tmp.ensure(tb + 1);
+        MLG_HIP(rocprim::run_length_encode(tmp.p, tb, skeys.p, (unsigned)total, ucell.p, ucnt.p,
+                                           nu_d.p, s));
+        unsigned nu = 0;
+        MLG_HIP(hipMemcpyAsync(&nu, nu_d.p, 4, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        DevBuf<int> dense(G + 1);
+        MLG_HIP(hipMemsetAsync(dense.p, 0, sizeof(int) * (G + 1), s));
+        hipLaunchKernelGGL(k_scatter_counts, dim3(ceil_div(nu, 256)), dim3(256), 0, s, (int)nu, ucell.p,
+                           ucnt.p, dense.p);
+        MLG_LAUNCH_CHECK();
+        W.cell_ptr.alloc(G + 1);
+        tb = 0;
+        MLG_HIP(rocprim::exclusive_scan(nullptr, tb, dense.p, W.cell_ptr.p, 0, (size_t)G + 1,
+                                        rocprim::plus<int>(), s));
+        tmp.ensure(tb + 1);
+        MLG_HIP(rocprim::exclusive_scan(tmp.p, tb, dense.p, W.cell_ptr.p, 0, (size_t)G + 1,
+                                        rocprim::plus<int>(), s));
+        W.csr = true;
+    }
     MLG_HIP(hipStreamSynchronize(s));
 }
 
@@ -1042,30 +1451,43 @@ const float2 *tw_of<float>(const NfftPlan &P) { return P.tw32.p; }
 template <>
 const double2 *tw_of<double>(const NfftPlan &P) { return P.tw64.p; }
 
+// One FFT pass along axis `ax`; see k_fft for `mode` and `cols`.
 template <class T>
-static void fft_all(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, int sign,
-                    hipStream_t s) {
+static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, int ax, int mode,
+                     int cols, const T *M, hipStream_t s) {
     const int L = P.nos;
     int logL = 0;
     while ((1 << logL) < L) ++logL;
-    const int64_t nq = bg / 2;
-    // axis 0 is fastest; line stride for axis t is nos^t * nq
-    for (int ax = 0; ax < P.d; ++ax) {
-        int64_t inner = nq;
-        for (int t = 0; t < ax; ++t) inner *= P.nos;
-        int64_t outer = 1;
-        for (int t = ax + 1; t < P.d; ++t) outer *= P.nos;
-        const int maxlines = std::max(1, 4096 / L);
-        int IC = (int)std::min<int64_t>(inner, maxlines);
-        while (inner % IC) --IC;
-        int LB = std::max(1, maxlines / IC);
-        if (LB > outer) LB = (int)outer;
-        const size_t lds = (size_t)L * IC * LB * sizeof(typename Cplx<T>::type);
-        dim3 grd((unsigned)((inner / IC) * ((outer + LB - 1) / LB)));
-        hipLaunchKernelGGL(k_fft<T>, grd, dim3(256), lds, s, grid, L, logL, outer, inner, IC, LB,
-                           sign, tw_of<T>(P));
-        MLG_LAUNCH_CHECK();
-    }
+    const int nq = bg / 2;
+    int64_t inner = nq;
+    for (int t = 0; t < ax; ++t) inner *= P.nos;
+    int64_t outer = 1;
+    for (int t = ax + 1; t < P.d; ++t) outer *= P.nos;
+    int64_t nact = inner;
+    if (cols == 1) nact = (int64_t)(P.N + 1) * nq;
+    if (cols == 2) nact = (int64_t)(P.N + 1) * (P.N + 1) * nq;
+    const int maxlines = std::max(1, 4096 / L);
+    int IC = (int)std::min<int64_t>(nact, maxlines);
+    int LB = std::max(1, maxlines / IC);
+    if (LB > outer) LB = (int)outer;
+    const size_t lds = (size_t)L * IC * LB * sizeof(typename Cplx<T>::type);
+    const int64_t nblk = ((nact + IC - 1) / IC) * ((outer + LB - 1) / LB);
+    hipLaunchKernelGGL(k_fft<T>, dim3((unsigned)nblk), dim3(256), lds, s, grid, L, logL, outer, inner,
+                       nact, IC, LB, mode, cols, P.N, nq, tw_of<T>(P), M);
+    MLG_LAUNCH_CHECK();
+}
+
+// Forward FFT, multiplication by M and inverse FFT with band pruning: axes
+// below the last are transformed forward (later axes only on band columns),
+// the last axis does forward * M * inverse in one pass, and the inverse
+// passes read out-of-band entries as zero.
+template <class T>
+static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, const T *M,
+                         hipStream_t s) {
+    const int d = P.d;
+    for (int ax = 0; ax < d - 1; ++ax) fft_pass<T>(P, bg, grid, ax, 0, ax, nullptr, s);
+    fft_pass<T>(P, bg, grid, d - 1, 2, d - 1, M, s);
+    for (int ax = d - 2; ax >= 0; --ax) fft_pass<T>(P, bg, grid, ax, 1, ax, nullptr, s);
 }
 
 // Widest vector group (power of two <= min(bs, 16)) whose patch slots fit the
@@ -1130,14 +1552,35 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
                 "patch too large for one task (reduce window or bin)");
     const int bg = bs < 2 ? 2 : bs;
     const T beta = (T)W.beta;
+    // FP32 blocks of 16 vectors with patches of <= 256 cells use the matrix
+    // cores; everything else the vector-ALU kernels.
+    const bool mf = std::is_same<T, float>::value && bs % 16 == 0 && g.PD <= 256;
+    const int ws = D == 3 ? 3 * g.P + g.P * g.P + 1 : D * g.P + 1;
+    const int ntl = mfma_ntiles(g.PD);
     if (P.ntasks > 0) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (mf) {
+                const size_t lds = (size_t)64 * (ws + 16) * sizeof(float);
+#define SPREADM_CALL(NT)                                                                        \
+    hipLaunchKernelGGL((k_spread_mfma<D, NT>), dim3(P.ntasks, bs / 16), dim3(64), lds, s, g, P.tasks.p, \
+                       P.c32.p, P.f32.p, Zs, beta, patch)
+                MLG_NT_SWITCH(ntl, SPREADM_CALL)
+#undef SPREADM_CALL
+                MLG_LAUNCH_CHECK();
+            }
+        }
+        if (!mf) {
 #define SPREAD_CALL(V) launch_spread<T, D, V>(g, P, Zs, beta, patch, s)
-        MLG_VPL_SWITCH(vs, SPREAD_CALL)
+            MLG_VPL_SWITCH(vs, SPREAD_CALL)
 #undef SPREAD_CALL
-        if (P.nmulti > 0) {
+        }
+        if (P.nred1 > 0) {
             const int64_t elems = (int64_t)g.PD * bs;
-            hipLaunchKernelGGL(k_binreduce<T>, dim3(P.nmulti, ceil_div(elems, 256)), dim3(256), 0, s,
-                               elems, P.multi.p, patch);
+            hipLaunchKernelGGL(k_reduce1<T>, dim3(P.nred1, ceil_div(elems, 256)), dim3(256), 0, s, elems,
+                               P.red1.p, patch);
+            MLG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_reduce2<T>, dim3(P.nred2, ceil_div(elems, 256)), dim3(256), 0, s, elems,
+                               P.red2.p, patch);
             MLG_LAUNCH_CHECK();
         }
     }
@@ -1145,21 +1588,39 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     int64_t G = 1;
     for (int t = 0; t < D; ++t) G *= P.nos;
     const int vgat = std::min(bs, 16);
+    if (W.csr) {
+#define GATHERC_CALL(V)                                                                           \
+    hipLaunchKernelGGL((k_gather_csr<T, V>), dim3(ceil_div(G, 256), bs / V), dim3(256), 0, s, G, bs, bg, \
+                       W.cell_ptr.p, W.cell_ent.p, patch, grid)
+        MLG_VPL_SWITCH(vgat, GATHERC_CALL)
+#undef GATHERC_CALL
+        MLG_LAUNCH_CHECK();
+    } else {
 #define GATHER_CALL(V) launch_gather<T, D, V>(g, P, patch, bg, grid, G, s)
-    MLG_VPL_SWITCH(vgat, GATHER_CALL)
+        MLG_VPL_SWITCH(vgat, GATHER_CALL)
 #undef GATHER_CALL
+    }
     if (ev) MLG_HIP(hipEventRecord(ev[2], s));
     using C2 = typename Cplx<T>::type;
-    fft_all<T>(P, bg, reinterpret_cast<C2 *>(grid), -1, s);
-    hipLaunchKernelGGL(k_mul<T>, dim3(ceil_div(G * (bg / 2), 256)), dim3(256), 0, s,
-                       reinterpret_cast<C2 *>(grid), mult_of<T>(W), G, bg / 2);
-    MLG_LAUNCH_CHECK();
-    fft_all<T>(P, bg, reinterpret_cast<C2 *>(grid), +1, s);
+    fft_convolve<T>(P, bg, reinterpret_cast<C2 *>(grid), mult_of<T>(W), s);
     if (ev) MLG_HIP(hipEventRecord(ev[3], s));
-    const int vint = std::min(bs, 16);
+    if constexpr (std::is_same<T, float>::value) {
+        if (mf && P.ntasks > 0) {
+            const size_t lds = (size_t)64 * ws * sizeof(float) + 32 * ntl * sizeof(int);
+#define INTERPM_CALL(NT)                                                                          \
+    hipLaunchKernelGGL((k_interp_mfma<D, NT>), dim3(P.ntasks, bs / 16), dim3(64), lds, s, g, P.tasks.p, \
+                       P.c32.p, P.f32.p, grid, bg, beta, Fs)
+            MLG_NT_SWITCH(ntl, INTERPM_CALL)
+#undef INTERPM_CALL
+            MLG_LAUNCH_CHECK();
+        }
+    }
+    if (!mf) {
+        const int vint = std::min(bs, 16);
 #define INTERP_CALL(V) launch_interp<T, D, V>(g, P, grid, bg, beta, Fs, s)
-    MLG_VPL_SWITCH(vint, INTERP_CALL)
+        MLG_VPL_SWITCH(vint, INTERP_CALL)
 #undef INTERP_CALL
+    }
     if (ev) MLG_HIP(hipEventRecord(ev[4], s));
 }
 

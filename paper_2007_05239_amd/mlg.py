@@ -31,7 +31,7 @@ MLG_OP_NADJ = 0
 MLG_OP_LSYM = 1
 MLG_OP_W = 2
 
-STAGES = ["pre", "spread", "gather", "fft", "interp", "post", "direct", "io"]
+STAGES = ["scatter_in", "spread", "gather", "fft", "interp", "gather_out", "direct", "unused"]
 
 EXPORTED = ["mlg_last_error", "mlg_version", "mlg_graph_create", "mlg_graph_destroy",
             "mlg_graph_degrees", "mlg_kernel_matvec", "mlg_laplacian_matvec",

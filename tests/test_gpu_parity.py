@@ -236,3 +236,18 @@ def test_allen_cahn_on_gpu_eigenpairs_end_to_end(mlg):
     U, pred, it = mlg.allen_cahn_ssl(lam, V, lab, c["m"], tol=0.0, max_iter=300)
     assert np.array_equal(pred, po) and np.array_equal(U, Uo)
     assert (pred == c["classes"]).mean() > 0.95
+
+
+def test_nfft_fp32_heavy_bin_two_level_reduction(mlg):
+    """A bin holding > 32 tasks of points exercises both reduction levels."""
+    g = gen.rng(97)
+    n = 24007
+    core = 0.0005 * g.standard_normal((18000, 3))       # one very dense cell
+    rest = gen.uniform_ball(n - 18000, 3, 1.0, 98)
+    pts = np.ascontiguousarray(np.vstack([core, rest]))
+    X = gen.test_vectors(n, 16, 99)
+    case_id("nfft fp32 heavy bin n=%d b=16" % n)
+    Y = mlg.kernel_matvec(pts, 0.3, X, mlg.kparams("nfft", 32, N=64, window=6))
+    assert rel_err(Y, oracle.kernel_matvec(pts, 0.3, X)) <= 1e-4
+    Y64 = mlg.kernel_matvec(pts, 0.3, X[:, :2], mlg.kparams("nfft", 64, N=64, window=12))
+    assert rel_err(Y64, oracle.kernel_matvec(pts, 0.3, X[:, :2])) <= 1e-6
