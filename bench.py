@@ -78,12 +78,14 @@ def main():
     plan_s = time.time() - t0
     infos = [g.layer_info(t) for t in range(T)]
     X = torch.from_numpy(np.ascontiguousarray(gen.test_vectors(n, b, c["base_seed"] + 300))).to(dev)
+    Xc = X.t().contiguous()                 # column-major n x b block, resident in HBM
+    Yc = torch.empty_like(Xc)
     for _ in range(a.warmup):
-        Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, X)
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, X)
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = el / a.steps * 1e3

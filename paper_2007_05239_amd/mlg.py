@@ -212,6 +212,16 @@ class Graph:
         _check(_lib.mlg_laplacian_matvec(self._h, layer, op, b, _ptr(Xc)[0], n, _ptr(Y)[0], n, 0))
         return Y
 
+    def laplacian_matvec_into(self, layer, op, Xc, Yc, sync=True):
+        """Device-only form: Xc, Yc are b x n contiguous CUDA tensors, i.e. the
+        column-major n x b blocks the C ABI takes; no copies are made."""
+        b, n = Xc.shape
+        if sync:
+            _sync()
+        _check(_lib.mlg_laplacian_matvec(self._h, layer, op, b, _ptr(Xc)[0], n, _ptr(Yc)[0], n,
+                                         MLG_DEVICE_PTRS))
+        return Yc
+
     def profile_stages(self, layer, op, X, reps=5):
         """Average ms per matvec in each stage (dict), device tensors only."""
         import torch
