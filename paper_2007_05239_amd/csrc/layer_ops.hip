@@ -5,43 +5,82 @@
 //   gather-out   y = coef sum_t D_t^-1/2 (F_t - K(0) z_t) in FP64, with the
 //                self term of W = W~ - K(0) I (Sec. 4) and the layer mean
 //                (1/T) sum_t (Sec. 3); y = x - that for L_sym / L_1.
-// Both move 64 rows of the column-major block through LDS so that the
-// column-major side and the point-major side are both coalesced.  The layer
-// sum runs in layer order.
+// Both move 256 rows of the column-major block through LDS so that the
+// column-major side and the point-major side are both coalesced; one thread
+// owns one row (its permutation entry and D^-1/2 are read once per layer).
+// The layer sum runs in layer order.
 #include "internal.h"
 
 namespace mlg {
 
+// Thread per row; vectors in groups of VG = 16 (or bs if smaller).  The
+// column-major block moves through an LDS tile of 256 rows x VG columns.
+constexpr int kIoRows = 256;
+constexpr int kIoVG = 16;
+
 template <class T>
-__device__ inline void store_z(void *Z, int64_t idx, double v) {
-    reinterpret_cast<T *>(Z)[idx] = (T)v;
+__device__ inline void store_row(void *Zbase, int64_t off, const double (&z)[kIoVG], int cnt) {
+    T *dst = reinterpret_cast<T *>(Zbase) + off;
+    if constexpr (sizeof(T) == 4) {
+        if (cnt == 16) {
+#pragma unroll
+            for (int j = 0; j < 16; j += 4)
+                *reinterpret_cast<float4 *>(dst + j) =
+                    make_float4((float)z[j], (float)z[j + 1], (float)z[j + 2], (float)z[j + 3]);
+            return;
+        }
+    }
+    for (int j = 0; j < cnt; ++j) dst[j] = (T)z[j];
+}
+
+template <class T>
+__device__ inline void load_row(const void *Fbase, int64_t off, double (&f)[kIoVG], int cnt) {
+    const T *src = reinterpret_cast<const T *>(Fbase) + off;
+    if constexpr (sizeof(T) == 4) {
+        if (cnt == 16) {
+#pragma unroll
+            for (int j = 0; j < 16; j += 4) {
+                const float4 q = *reinterpret_cast<const float4 *>(src + j);
+                f[j] = q.x; f[j + 1] = q.y; f[j + 2] = q.z; f[j + 3] = q.w;
+            }
+            return;
+        }
+    }
+    for (int j = 0; j < cnt; ++j) f[j] = (double)src[j];
 }
 
 __global__ __launch_bounds__(256) void k_scatter_in(int64_t n, int b, int bs,
                                                     const double *__restrict__ X, int64_t ldx,
                                                     const LayerIO *__restrict__ L, int nl,
                                                     int use_dinv) {
-    __shared__ double tile[64 * 65];
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int rows = (int)((n - i0) < 64 ? (n - i0) : 64);
-    for (int e = threadIdx.x; e < 64 * b; e += blockDim.x) {
-        const int r = e & 63, v = e >> 6;
-        if (r < rows) tile[v * 65 + r] = X[i0 + r + (int64_t)v * ldx];
-    }
-    __syncthreads();
-    for (int t = 0; t < nl; ++t) {
-        const LayerIO d = L[t];
-        for (int e = threadIdx.x; e < rows * bs; e += blockDim.x) {
-            const int r = e / bs, v = e - r * bs;
-            const int64_t i = i0 + r;
+    __shared__ double tile[kIoVG * (kIoRows + 1)];
+    const int64_t i0 = (int64_t)blockIdx.x * kIoRows;
+    const int rows = (int)((n - i0) < kIoRows ? (n - i0) : kIoRows);
+    const int r = threadIdx.x;
+    const int64_t i = i0 + r;
+    const int vgw = bs < kIoVG ? bs : kIoVG;
+    for (int v0 = 0; v0 < bs; v0 += vgw) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kIoRows * vgw; e += blockDim.x) {
+            const int rr = e % kIoRows, v = e / kIoRows;
+            double x = 0.0;
+            if (rr < rows && v0 + v < b) x = X[i0 + rr + (int64_t)(v0 + v) * ldx];
+            tile[v * (kIoRows + 1) + rr] = x;
+        }
+        __syncthreads();
+        if (r >= rows) continue;
+        double x[kIoVG];
+#pragma unroll
+        for (int j = 0; j < kIoVG; ++j) x[j] = j < vgw ? tile[j * (kIoRows + 1) + r] : 0.0;
+        for (int t = 0; t < nl; ++t) {
+            const LayerIO d = L[t];
             const int64_t p = d.invperm ? d.invperm[i] : i;
-            double z = 0.0;
-            if (v < b) {
-                z = tile[v * 65 + r];
-                if (use_dinv) z *= d.dinv[i];
-            }
-            if (d.is64) store_z<double>(d.Z, p * bs + v, z);
-            else store_z<float>(d.Z, p * bs + v, z);
+            const double di = use_dinv ? d.dinv[i] : 1.0;
+            double z[kIoVG];
+#pragma unroll
+            for (int j = 0; j < kIoVG; ++j) z[j] = use_dinv ? x[j] * di : x[j];
+            if (d.is64) store_row<double>(d.Z, p * bs + v0, z, vgw);
+            else store_row<float>(d.Z, p * bs + v0, z, vgw);
         }
     }
 }
@@ -51,45 +90,61 @@ __global__ __launch_bounds__(256) void k_gather_out(int64_t n, int b, int bs,
                                                     double *__restrict__ Y, int64_t ldy,
                                                     const LayerIO *__restrict__ L, int nl,
                                                     int use_dinv, int lsym, double coef) {
-    __shared__ double tile[64 * 65];
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int rows = (int)((n - i0) < 64 ? (n - i0) : 64);
-    for (int e = threadIdx.x; e < 64 * b; e += blockDim.x) {
-        const int r = e & 63, v = e >> 6;
-        if (r < rows) tile[v * 65 + r] = X[i0 + r + (int64_t)v * ldx];
-    }
-    __syncthreads();
-    // each (row, vector) element is read and rewritten by one thread only
-    for (int e = threadIdx.x; e < rows * b; e += blockDim.x) {
-        const int r = e / b, v = e - r * b;
-        const int64_t i = i0 + r;
-        const double x = tile[v * 65 + r];
-        double acc = 0.0;
-        for (int t = 0; t < nl; ++t) {
-            const LayerIO d = L[t];
-            const int64_t p = d.invperm ? d.invperm[i] : i;
-            const double di = use_dinv ? d.dinv[i] : 1.0;
-            double zx = use_dinv ? x * di : x;
-            double f, z;
-            if (d.is64) {
-                f = reinterpret_cast<const double *>(d.F)[p * bs + v];
-                z = zx;
-            } else {
-                f = (double)reinterpret_cast<const float *>(d.F)[p * bs + v];
-                z = (double)(float)zx;       // the value the FP32 summation saw
-            }
-            double w = f - d.K0 * z;
-            if (use_dinv) w *= di;
-            acc += w;
+    __shared__ double tile[kIoVG * (kIoRows + 1)];
+    const int64_t i0 = (int64_t)blockIdx.x * kIoRows;
+    const int rows = (int)((n - i0) < kIoRows ? (n - i0) : kIoRows);
+    const int r = threadIdx.x;
+    const int64_t i = i0 + r;
+    const int vgw = bs < kIoVG ? bs : kIoVG;
+    for (int v0 = 0; v0 < b; v0 += vgw) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < kIoRows * vgw; e += blockDim.x) {
+            const int rr = e % kIoRows, v = e / kIoRows;
+            double x = 0.0;
+            if (rr < rows && v0 + v < b) x = X[i0 + rr + (int64_t)(v0 + v) * ldx];
+            tile[v * (kIoRows + 1) + rr] = x;
         }
-        double y = coef * acc;
-        if (lsym) y = x - y;
-        tile[v * 65 + r] = y;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * b; e += blockDim.x) {
-        const int r = e & 63, v = e >> 6;
-        if (r < rows) Y[i0 + r + (int64_t)v * ldy] = tile[v * 65 + r];
+        __syncthreads();
+        if (r < rows) {
+            double x[kIoVG], acc[kIoVG];
+#pragma unroll
+            for (int j = 0; j < kIoVG; ++j) {
+                x[j] = j < vgw ? tile[j * (kIoRows + 1) + r] : 0.0;
+                acc[j] = 0.0;
+            }
+            for (int t = 0; t < nl; ++t) {
+                const LayerIO d = L[t];
+                const int64_t p = d.invperm ? d.invperm[i] : i;
+                const double di = use_dinv ? d.dinv[i] : 1.0;
+                double f[kIoVG];
+                if (d.is64) load_row<double>(d.F, p * bs + v0, f, vgw);
+                else load_row<float>(d.F, p * bs + v0, f, vgw);
+#pragma unroll
+                for (int j = 0; j < kIoVG; ++j) {
+                    if (j < vgw) {
+                        const double zx = use_dinv ? x[j] * di : x[j];
+                        // the value the summation saw (FP32 layers round it)
+                        const double z = d.is64 ? zx : (double)(float)zx;
+                        double w = f[j] - d.K0 * z;
+                        if (use_dinv) w *= di;
+                        acc[j] += w;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kIoVG; ++j) {
+                if (j < vgw) {
+                    double y = coef * acc[j];
+                    if (lsym) y = x[j] - y;
+                    tile[j * (kIoRows + 1) + r] = y;
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kIoRows * vgw; e += blockDim.x) {
+            const int rr = e % kIoRows, v = e / kIoRows;
+            if (rr < rows && v0 + v < b) Y[i0 + rr + (int64_t)(v0 + v) * ldy] = tile[v * (kIoRows + 1) + rr];
+        }
     }
 }
 
@@ -123,8 +178,8 @@ static inline unsigned blocks_for(int64_t work, int threads) {
 void launch_scatter_in(int64_t n, int b, int bs, const double *X, int64_t ldx, const LayerIO *L,
                        int nl, int use_dinv, hipStream_t s) {
     MLG_REQUIRE(bs <= 64 && b <= bs, MLG_ERR_ARG, "block too wide");
-    hipLaunchKernelGGL(k_scatter_in, dim3(blocks_for(n, 64)), dim3(256), 0, s, n, b, bs, X, ldx, L, nl,
-                       use_dinv);
+    hipLaunchKernelGGL(k_scatter_in, dim3(blocks_for(n, kIoRows)), dim3(256), 0, s, n, b, bs, X, ldx, L,
+                       nl, use_dinv);
     MLG_LAUNCH_CHECK();
 }
 
@@ -132,8 +187,8 @@ void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, d
                        int64_t ldy, const LayerIO *L, int nl, int use_dinv, int lsym, double coef,
                        hipStream_t s) {
     MLG_REQUIRE(bs <= 64 && b <= bs, MLG_ERR_ARG, "block too wide");
-    hipLaunchKernelGGL(k_gather_out, dim3(blocks_for(n, 64)), dim3(256), 0, s, n, b, bs, X, ldx, Y, ldy,
-                       L, nl, use_dinv, lsym, coef);
+    hipLaunchKernelGGL(k_gather_out, dim3(blocks_for(n, kIoRows)), dim3(256), 0, s, n, b, bs, X, ldx, Y,
+                       ldy, L, nl, use_dinv, lsym, coef);
     MLG_LAUNCH_CHECK();
 }
 

@@ -935,7 +935,7 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
         const int kx = band_index((int)(r % (N + 1)), N, L), ky = band_index((int)(r / (N + 1)), N, L);
         return ((int64_t)ky * L + kx) * nq + q;
     };
-    for (int e = tid; e < L * lines; e += 256) {
+    for (int e = tid; e < L * lines; e += blockDim.x) {
         const int ln = e % lines, k = e / lines;
         const int oo = ln / IC, cc = ln - oo * IC;
         const int64_t o = o0 + oo, a = a0 + cc;
@@ -952,7 +952,7 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
     if (mode == 2) {
         // multiply by M (cell = line index * inner extent / nq + column / nq),
         // then put the line back into bit-reversed order for the inverse
-        for (int e = tid; e < L * lines; e += 256) {
+        for (int e = tid; e < L * lines; e += blockDim.x) {
             const int ln = e % lines, k = e / lines;
             const int cc = ln % IC;
             const int64_t a = a0 + cc;
@@ -964,7 +964,7 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
             buf[k * lines + ln] = v;
         }
         __syncthreads();
-        for (int e = tid; e < L * lines; e += 256) {
+        for (int e = tid; e < L * lines; e += blockDim.x) {
             const int ln = e % lines, k = e / lines;
             const int rk = __brev((unsigned)k) >> (32 - logL);
             if (k < rk) {
@@ -976,7 +976,7 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
         __syncthreads();
         fft_stages<C2>(buf, L, logL, lines, true, tw);
     }
-    for (int e = tid; e < L * lines; e += 256) {
+    for (int e = tid; e < L * lines; e += blockDim.x) {
         const int ln = e % lines, k = e / lines;
         const int oo = ln / IC, cc = ln - oo * IC;
         const int64_t o = o0 + oo, a = a0 + cc;
@@ -1466,13 +1466,18 @@ static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, in
     int64_t nact = inner;
     if (cols == 1) nact = (int64_t)(P.N + 1) * nq;
     if (cols == 2) nact = (int64_t)(P.N + 1) * (P.N + 1) * nq;
-    const int maxlines = std::max(1, 4096 / L);
+    // lines per workgroup: enough workgroups to fill the chip (>= ~2048),
+    // at most 4096 points of LDS per workgroup
+    const int64_t lines_total = nact * outer;
+    int maxlines = std::max(1, 4096 / L);
+    while (maxlines > 1 && lines_total / maxlines < 2048) maxlines >>= 1;
     int IC = (int)std::min<int64_t>(nact, maxlines);
     int LB = std::max(1, maxlines / IC);
     if (LB > outer) LB = (int)outer;
+    const int threads = (int)std::min<int64_t>(256, std::max<int64_t>(64, (int64_t)IC * LB * L / 2));
     const size_t lds = (size_t)L * IC * LB * sizeof(typename Cplx<T>::type);
     const int64_t nblk = ((nact + IC - 1) / IC) * ((outer + LB - 1) / LB);
-    hipLaunchKernelGGL(k_fft<T>, dim3((unsigned)nblk), dim3(256), lds, s, grid, L, logL, outer, inner,
+    hipLaunchKernelGGL(k_fft<T>, dim3((unsigned)nblk), dim3(threads), lds, s, grid, L, logL, outer, inner,
                        nact, IC, LB, mode, cols, P.N, nq, tw_of<T>(P), M);
     MLG_LAUNCH_CHECK();
 }
