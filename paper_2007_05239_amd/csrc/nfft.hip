@@ -408,14 +408,13 @@ __device__ inline void store_vec(T *__restrict__ p, const T (&v)[V]) {
 // cells l, l+64, ... and VPL vectors of each; points are staged 64 at a time
 // (their 1D window weights at the P patch positions per dimension, and their
 // values) and accumulated in the task's point order.
-template <class T, int D, int VPL>
+template <class T, int D, int VPL, int CMAX>
 __global__ __launch_bounds__(64) void k_spread(Geom g, const int4 *__restrict__ tasks,
                                                const double *__restrict__ u64,
                                                const int *__restrict__ c32,
                                                const float *__restrict__ f32,
                                                const T *__restrict__ Zs, T beta,
                                                T *__restrict__ patch) {
-    constexpr int CMAX = 64 / VPL;
     extern __shared__ unsigned char smem_raw[];
     const int P = g.P, PD = g.PD, bs = g.bs;
     T *wts = reinterpret_cast<T *>(smem_raw);       // [64][D][P]
@@ -1503,12 +1502,23 @@ static int spread_vpl(int PD, int bs) {
     return v;
 }
 
+// Cell slots per lane: the smallest compiled count covering the patch.
 template <class T, int D, int VPL>
 static void launch_spread(const Geom &g, const NfftPlan &P, const T *Zs, T beta, T *patch,
                           hipStream_t s) {
     const size_t lds = (size_t)64 * (D * g.P + VPL) * sizeof(T);
-    hipLaunchKernelGGL((k_spread<T, D, VPL>), dim3(P.ntasks, g.bs / VPL), dim3(64), lds, s, g,
-                       P.tasks.p, P.u64.p, P.c32.p, P.f32.p, Zs, beta, patch);
+    const int cpl = ceil_div(g.PD, 64);
+    constexpr int CFULL = 64 / VPL;
+    dim3 grd(P.ntasks, g.bs / VPL);
+    if (cpl <= 4 && CFULL >= 4)
+        hipLaunchKernelGGL((k_spread<T, D, VPL, (CFULL < 4 ? CFULL : 4)>), grd, dim3(64), lds, s, g,
+                           P.tasks.p, P.u64.p, P.c32.p, P.f32.p, Zs, beta, patch);
+    else if (cpl <= 16 && CFULL >= 16)
+        hipLaunchKernelGGL((k_spread<T, D, VPL, (CFULL < 16 ? CFULL : 16)>), grd, dim3(64), lds, s, g,
+                           P.tasks.p, P.u64.p, P.c32.p, P.f32.p, Zs, beta, patch);
+    else
+        hipLaunchKernelGGL((k_spread<T, D, VPL, CFULL>), grd, dim3(64), lds, s, g, P.tasks.p, P.u64.p,
+                           P.c32.p, P.f32.p, Zs, beta, patch);
     MLG_LAUNCH_CHECK();
 }
 
@@ -1579,6 +1589,9 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
             MLG_VPL_SWITCH(vs, SPREAD_CALL)
 #undef SPREAD_CALL
         }
+    }
+    if (ev) MLG_HIP(hipEventRecord(ev[1], s));   // spreading kernel alone
+    if (P.ntasks > 0) {
         if (P.nred1 > 0) {
             const int64_t elems = (int64_t)g.PD * bs;
             hipLaunchKernelGGL(k_reduce1<T>, dim3(P.nred1, ceil_div(elems, 256)), dim3(256), 0, s, elems,
@@ -1589,7 +1602,6 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
             MLG_LAUNCH_CHECK();
         }
     }
-    if (ev) MLG_HIP(hipEventRecord(ev[1], s));
     int64_t G = 1;
     for (int t = 0; t < D; ++t) G *= P.nos;
     const int vgat = std::min(bs, 16);
