@@ -24,17 +24,6 @@ Graph::~Graph() {
     caps.clear();
 }
 
-__global__ void k_points_soa(int64_t n, int d, const double *__restrict__ pts,
-                             double *__restrict__ x64, float *__restrict__ x32) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int t = 0; t < d; ++t) {
-        double v = pts[i * d + t];
-        x64[(int64_t)t * n + i] = v;
-        x32[(int64_t)t * n + i] = (float)v;
-    }
-}
-
 static int block_stride(int b) {
     int bs = 1;
     while (bs < b) bs <<= 1;
@@ -123,7 +112,7 @@ static void layer_core(Graph &g, int t, int bs, StageTimer *tm) {
     } else {
         const T *x = nullptr;
         if constexpr (sizeof(T) == 8) x = L.x64.p; else x = L.x32.p;
-        launch_direct<T>(g.n, L.d, x, 1.0 / (L.sigma * L.sigma), bs, Zs, Fs,
+        launch_direct<T>(g.n, L.d, x, bs, Zs, Fs,
                          reinterpret_cast<T *>(g.part.p), g.part.n / sizeof(T), s);
         if (tm) MLG_HIP(hipEventRecord(tm->ev[4], s));
     }
@@ -249,7 +238,7 @@ static void compute_degrees(Graph &g, Layer &L) {
         MLG_HIP(hipMemcpyAsync(dio.p, &io, sizeof(io), hipMemcpyHostToDevice, s));
         launch_scatter_in(n, 1, 1, ones.p, n, dio.p, 1, 0, s);
         DevBuf<double> part(direct_part_size<double>(n, 1));
-        launch_direct<double>(n, L.d, L.x64.p, 1.0 / (L.sigma * L.sigma), 1, Z.p, F.p, part.p,
+        launch_direct<double>(n, L.d, L.x64.p, 1, Z.p, F.p, part.p,
                               part.n, s);
         launch_gather_out(n, 1, 1, ones.p, n, L.deg.p, n, dio.p, 1, 0, 0, 1.0, s);
         MLG_HIP(hipStreamSynchronize(s));
@@ -277,11 +266,7 @@ static void build_layer(Graph &g, Layer &L, const double *pts, bool dev, bool de
         p = pd.p;
     }
     L.n = n;
-    L.x64.alloc((size_t)n * L.d);
-    L.x32.alloc((size_t)n * L.d);
-    hipLaunchKernelGGL(k_points_soa, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, L.d, p, L.x64.p,
-                       L.x32.p);
-    MLG_LAUNCH_CHECK();
+    if (L.kp.method == MLG_METHOD_DIRECT) direct_coords(n, L.d, p, L.sigma, L.x64, L.x32, s);
     if (L.kp.method == MLG_METHOD_NFFT) {
         nfft_plan_layer(L, p, s);
         L.sorted = 1;

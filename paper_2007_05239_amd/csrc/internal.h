@@ -59,10 +59,10 @@ struct Layer {
     double sigma = 0;
     mlg_kparams kp{};
     int64_t n = 0;
-    // direct path: centred coordinates, SoA d x n
+    // direct path: coordinates centred on the bounding box and scaled by
+    // 1/sigma (x64) or sqrt(log2 e)/sigma (x32), SoA d x n
     DevBuf<double> x64;
     DevBuf<float> x32;
-    double center[64];
     NfftPlan nf;
     NfftWindow win;          // matvec window
     DevBuf<double> deg;      // degrees, original order
@@ -94,9 +94,15 @@ void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s);
 void launch_invperm(int64_t n, const int *perm, int *inv, hipStream_t s);
 
 // ---- direct.hip ---------------------------------------------------------------
+// Scaled, centred coordinates of a direct layer (d x n SoA): x64 for the
+// FP64 kernels, x32 for the FP32 kernels.
+void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, DevBuf<double> &x64,
+                   DevBuf<float> &x32, hipStream_t s);
+// Fs = W Zs (zero diagonal) for n points with coordinates from direct_coords;
+// part: S x n x bs column-split partials (direct_part_size elements).
 template <class T>
-void launch_direct(int64_t n, int d, const T *x, double inv_s2, int bs, const T *Zs, T *Fs,
-                   T *part, size_t part_cap, hipStream_t s);
+void launch_direct(int64_t n, int d, const T *x, int bs, const T *Zs, T *Fs, T *part,
+                   size_t part_cap, hipStream_t s);
 template <class T>
 size_t direct_part_size(int64_t n, int bs);
 

@@ -642,164 +642,248 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, int SB, int nsb,
 // v_mfma_f32_16x16x4_f32 (FP32 inputs, FP32 accumulation).
 // Operand layout of that instruction (one wavefront): A[i][k] in lane i+16k,
 // B[k][j] in lane j+16k, D[i][j] in register i%4 of lane j+16*(i/4).
+//
+// A task is processed in chunks of 64 points.  Each lane owns one point of a
+// chunk: it evaluates the point's D x P one-dimensional window values (and,
+// for D = 3, the P x P products of the y and z factors) into an LDS record,
+// while the cell/offset coordinates (and for spreading the 16 vector values)
+// of the next chunk are already being fetched into registers.  The patch
+// edge P is a compile-time constant, so the staging is branch-free and every
+// LDS address in the MFMA loops is a per-lane base plus an immediate.
 // ------------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Per-point window weights in LDS: wx[P] | wy[P] | wz[P] | wyz[P*P] (D = 3),
-// wx[P] | wy[P] (D = 2), wx[P] (D = 1), then one zero slot; zero outside the
-// point's footprint.  Records of absent points are all zero, so the inner
-// loops need no branches.
+template <int D, int P>
+struct MfShape {
+    static constexpr int PD = D == 3 ? P * P * P : (D == 2 ? P * P : P);
+    static constexpr int NT = (PD + 15) / 16;                    // 16-cell tiles
+    static constexpr int OB = D == 3 ? 3 * P : P;                 // second factor: wyz (D=3) or wy
+    static constexpr int ZS = D == 3 ? 3 * P + P * P : D * P;     // zero slot
+    static constexpr int WSP = (ZS + 1 + 3) / 4 * 4;             // record stride (floats)
+    static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
+    static constexpr int S16 = P / gcd(P, 16);   // period in tiles of (16t + li) mod P
+    static constexpr int S4 = P / gcd(P, 4);     // period in steps of (4s + lk) mod P
+};
+
+// Coordinates of one point: grid cell and FP32 offset inside it, per dimension.
 template <int D>
-__host__ __device__ inline int wstride_of(int P) {
-    return (D == 3 ? 3 * P + P * P : D * P) + 1;
-}
+struct PtIn {
+    int cell[D];
+    float frac[D];
+};
 
 template <int D>
-__device__ inline void stage_point_weights(const Geom &g, const int *__restrict__ c32,
-                                           const float *__restrict__ f32, int64_t p,
-                                           const int org[3], float beta, float *__restrict__ wp) {
-    const int P = g.P;
-    const float two_over_w = 2.0f / (float)g.w;
+__device__ inline void fetch_point(const int *__restrict__ c32, const float *__restrict__ f32,
+                                   int64_t n, int64_t p, bool ok, PtIn<D> &pi) {
+#pragma unroll
     for (int t = 0; t < D; ++t) {
-        const int cell = c32[(int64_t)t * g.n + p];
-        const float frac = f32[(int64_t)t * g.n + p];
-        const int s0 = cell - g.w / 2 + 1;
+        pi.cell[t] = ok ? c32[(int64_t)t * n + p] : 0;
+        pi.frac[t] = ok ? f32[(int64_t)t * n + p] : 0.0f;
+    }
+}
+
+// The record of one point: wx[P] | wy[P] | wz[P] | wyz[P*P] (D = 3), wx | wy
+// (D = 2) or wx (D = 1), then zeros; weights outside the point's footprint
+// (and all weights of an absent point) are zero.
+template <int D, int P>
+__device__ inline void put_record(const PtIn<D> &pi, bool ok, const int org[3], int w,
+                                  float two_over_w, float beta, float *__restrict__ wp) {
+    using S = MfShape<D, P>;
+    float wv[D][P];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        const int s0 = pi.cell[t] - w / 2 + 1;
+#pragma unroll
         for (int q = 0; q < P; ++q) {
             const int k = org[t] + q;
-            float val = 0.0f;
-            if (k >= s0 && k < s0 + g.w) val = es_psi<float>((float)(cell - k) + frac, two_over_w, beta);
-            wp[t * P + q] = val;
+            const float val = es_psi<float>((float)(pi.cell[t] - k) + pi.frac[t], two_over_w, beta);
+            wv[t][q] = (ok && k >= s0 && k < s0 + w) ? val : 0.0f;
         }
     }
-    if (D == 3)
+    float rec[S::WSP];
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+#pragma unroll
+        for (int q = 0; q < P; ++q) rec[t * P + q] = wv[t][q];
+    if constexpr (D == 3) {
+#pragma unroll
         for (int qz = 0; qz < P; ++qz)
-            for (int qy = 0; qy < P; ++qy) wp[3 * P + qy + P * qz] = wp[P + qy] * wp[2 * P + qz];
-    wp[wstride_of<D>(P) - 1] = 0.0f;
+#pragma unroll
+            for (int qy = 0; qy < P; ++qy) rec[3 * P + qy + P * qz] = wv[1][qy] * wv[2][qz];
+    }
+#pragma unroll
+    for (int e = S::ZS; e < S::WSP; ++e) rec[e] = 0.0f;
+#pragma unroll
+    for (int e = 0; e < S::WSP; e += 4)
+        *reinterpret_cast<float4 *>(wp + e) = make_float4(rec[e], rec[e + 1], rec[e + 2], rec[e + 3]);
 }
 
-__device__ inline void zero_record(int ws, float *__restrict__ wp) {
-    for (int q = 0; q < ws; ++q) wp[q] = 0.0f;
-}
-
-// Offsets of a patch cell's two weight factors inside a point's record; cells
-// beyond the patch point at the zero slot.
 template <int D>
-__device__ inline void cell_offsets(int c, int P, int PD, int &ia, int &ib) {
-    const int zs = wstride_of<D>(P) - 1;
-    if (c >= PD) { ia = zs; ib = zs; return; }
-    ia = c % P;
-    ib = D == 3 ? 3 * P + c / P : (D == 2 ? P + c / P : zs);
+__device__ inline void task_origin(const Geom &g, unsigned key, int org[3]) {
+    org[0] = org[1] = org[2] = 0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        org[t] = (int)(key % (unsigned)g.nb) * g.B - g.w / 2 + 1;
+        key /= (unsigned)g.nb;
+    }
 }
 
-// NT tiles of 16 patch cells (16*NT >= PD).
-template <int D, int NT>
+template <int D, int P>
 __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restrict__ tasks,
                                                     const int *__restrict__ c32,
                                                     const float *__restrict__ f32,
                                                     const float *__restrict__ Zs, float beta,
                                                     float *__restrict__ patch) {
-    extern __shared__ unsigned char smem_raw[];
-    const int P = g.P, PD = g.PD, bs = g.bs;
-    const int ws = wstride_of<D>(P);
-    float *wts = reinterpret_cast<float *>(smem_raw);   // [64][ws]
-    float *zv = wts + 64 * ws;                          // [64][16]
+    using S = MfShape<D, P>;
+    constexpr int NT = S::NT, WSP = S::WSP;
+    __shared__ __attribute__((aligned(16))) float wts[64 * WSP];
+    __shared__ __attribute__((aligned(16))) float zv[64 * 16];
+    const int bs = g.bs;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
     const int4 tk = tasks[blockIdx.x];
     const int v0 = blockIdx.y * 16;
-    int org[3] = {0, 0, 0};
-    {
-        unsigned key = (unsigned)tk.x;
-        for (int t = 0; t < D; ++t) {
-            org[t] = (int)(key % (unsigned)g.nb) * g.B - g.w / 2 + 1;
-            key /= (unsigned)g.nb;
-        }
+    int org[3];
+    task_origin<D>(g, (unsigned)tk.x, org);
+    const float two_over_w = 2.0f / (float)g.w;
+
+    // LDS offsets (floats) of the two factors of tile t's cell 16t + li for the
+    // lane's k slot; periodic in t with period S16, the remainder folded into
+    // immediates.  Cells past the patch (last tile only) read the zero slot.
+    int ra[S::S16], rb[S::S16];
+#pragma unroll
+    for (int tm = 0; tm < S::S16; ++tm) {
+        const int c = 16 * tm + li;
+        ra[tm] = lk * WSP + c % P;
+        rb[tm] = lk * WSP + S::OB + c / P;
     }
-    int ia[NT], ib[NT];
+    int la, lb;
+    {
+        const int c = 16 * (NT - 1) + li;
+        la = c < S::PD ? lk * WSP + c % P : lk * WSP + S::ZS;
+        lb = c < S::PD ? lk * WSP + S::OB + c / P : lk * WSP + S::ZS;
+    }
     floatx4 acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        cell_offsets<D>(16 * t + li, P, PD, ia[t], ib[t]);
-        acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    PtIn<D> pin;
+    float4 zin[4];
+    {
+        const bool ok = lane < tk.z;
+        const int64_t p = (int64_t)tk.y + lane;
+        fetch_point<D>(c32, f32, g.n, p, ok, pin);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + p * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
-        const int64_t first = (int64_t)tk.y + c0;
         __syncthreads();
-        float *myw = wts + lane * ws;
-        if (lane < cnt) {
-            stage_point_weights<D>(g, c32, f32, first + lane, org, beta, myw);
-            const float *zp = Zs + (first + lane) * bs + v0;
+        put_record<D, P>(pin, lane < cnt, org, g.w, two_over_w, beta, wts + lane * WSP);
 #pragma unroll
-            for (int j = 0; j < 16; j += 4) {
-                float4 q = *reinterpret_cast<const float4 *>(zp + j);
-                zv[lane * 16 + j] = q.x; zv[lane * 16 + j + 1] = q.y;
-                zv[lane * 16 + j + 2] = q.z; zv[lane * 16 + j + 3] = q.w;
-            }
-        } else {
-            zero_record(ws, myw);
+        for (int j = 0; j < 4; ++j) *reinterpret_cast<float4 *>(zv + lane * 16 + 4 * j) = zin[j];
+        __syncthreads();
+        const int c1 = c0 + 64;
+        if (c1 < tk.z) {   // prefetch the next chunk while this one is multiplied
+            const bool ok = lane < tk.z - c1;
+            const int64_t p = (int64_t)tk.y + c1 + lane;
+            fetch_point<D>(c32, f32, g.n, p, ok, pin);
 #pragma unroll
-            for (int j = 0; j < 16; ++j) zv[lane * 16 + j] = 0.0f;
+            for (int j = 0; j < 4; ++j)
+                zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + p * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        __syncthreads();
-        for (int pt0 = 0; pt0 < cnt; pt0 += 4) {
-            const int pk = pt0 + lk;                 // point of this lane's k slot (< 64)
-            const float b = zv[pk * 16 + li];
-            const float *wp = wts + pk * ws;
-            float a[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) a[t] = D > 1 ? wp[ia[t]] * wp[ib[t]] : wp[ia[t]];
+        for (int gi = 0; gi < 16; ++gi) {
+            if (4 * gi < cnt) {
+                const float b = zv[(4 * gi + lk) * 16 + li];
+                float a[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b, acc[t], 0, 0, 0);
+                for (int t = 0; t < NT; ++t) {
+                    const int tm = t % S::S16, tq = t / S::S16;
+                    const int oa = (t == NT - 1 ? la : ra[tm]) + 4 * gi * WSP;
+                    const int ob = (t == NT - 1 ? lb : rb[tm] + tq * (16 * S::S16 / P)) + 4 * gi * WSP;
+                    a[t] = D > 1 ? wts[oa] * wts[ob] : wts[oa];
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b, acc[t], 0, 0, 0);
+            }
         }
     }
-    float *out = patch + (int64_t)tk.w * PD * bs + v0 + li;
+    float *out = patch + (int64_t)tk.w * S::PD * bs + v0 + li;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int c = 16 * t + 4 * lk + r;
-            if (c < PD) out[(int64_t)c * bs] = acc[t][r];
+            if (c < S::PD) out[(int64_t)c * bs] = acc[t][r];
         }
     }
 }
 
-// KS = 4*NT cell steps; four groups of 16 points share each B fragment.
-template <int D, int NT>
+// Chunk body of the interpolation for NQ groups of 16 points: KSV steps of 4
+// patch cells; the four point groups give four independent accumulators.
+template <int D, int P, int NQ>
+__device__ inline void interp_chunk(const float *__restrict__ wts, const int (&qa)[MfShape<D, P>::S4],
+                                    const int (&qb)[MfShape<D, P>::S4], int li, int lk,
+                                    const float *hb, int cnt, int64_t first, int bs, int v0,
+                                    float *__restrict__ Fs) {
+    using S = MfShape<D, P>;
+    constexpr int WSP = S::WSP;
+    constexpr int KSV = (S::PD + 3) / 4;
+    floatx4 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KSV; ++s) {
+        const int sm = s % S::S4, sq = s / S::S4;
+        int oa = qa[sm], ob = qb[sm] + sq * (4 * S::S4 / P);
+        if (4 * s + 3 >= S::PD) {      // partial last step: cells past the patch
+            const bool in = 4 * s + lk < S::PD;
+            oa = in ? oa : li * WSP + S::ZS;
+            ob = in ? ob : li * WSP + S::ZS;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const float a = D > 1 ? wts[oa + 16 * q * WSP] * wts[ob + 16 * q * WSP] : wts[oa + 16 * q * WSP];
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hb[s], acc[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pt = 16 * q + 4 * lk + r;
+            if (pt < cnt) Fs[(first + pt) * bs + v0 + li] = acc[q][r];
+        }
+}
+
+template <int D, int P>
 __global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restrict__ tasks,
                                                     const int *__restrict__ c32,
                                                     const float *__restrict__ f32,
                                                     const float *__restrict__ grid, int bg,
                                                     float beta, float *__restrict__ Fs) {
-    constexpr int KS = 4 * NT;
-    extern __shared__ unsigned char smem_raw[];
-    const int P = g.P, PD = g.PD, bs = g.bs;
-    const int ws = wstride_of<D>(P);
-    float *wts = reinterpret_cast<float *>(smem_raw);          // [64][ws]
-    int *tab = reinterpret_cast<int *>(wts + 64 * ws);         // [2][16*NT]
+    using S = MfShape<D, P>;
+    constexpr int WSP = S::WSP;
+    constexpr int KSV = (S::PD + 3) / 4;
+    __shared__ __attribute__((aligned(16))) float wts[64 * WSP];
+    const int bs = g.bs;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
     const int4 tk = tasks[blockIdx.x];
     const int v0 = blockIdx.y * 16;
-    int org[3] = {0, 0, 0};
-    {
-        unsigned key = (unsigned)tk.x;
-        for (int t = 0; t < D; ++t) {
-            org[t] = (int)(key % (unsigned)g.nb) * g.B - g.w / 2 + 1;
-            key /= (unsigned)g.nb;
-        }
-    }
-    for (int c = lane; c < 16 * NT; c += 64) {
-        int a, b;
-        cell_offsets<D>(c, P, PD, a, b);
-        tab[c] = a;
-        tab[16 * NT + c] = b;
-    }
+    int org[3];
+    task_origin<D>(g, (unsigned)tk.x, org);
+    const float two_over_w = 2.0f / (float)g.w;
+
+    PtIn<D> pin;
+    fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + lane, lane < tk.z, pin);
     // B fragments: the task's patch of the grid, cell 4s + lk, vector li
-    float hb[KS];
+    float hb[KSV];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        float h = 0.0f;
+    for (int s = 0; s < KSV; ++s) {
         const int c = 4 * s + lk;
-        if (c < PD) {
+        float h = 0.0f;
+        if (c < S::PD) {
             const int qx = c % P, qy = (c / P) % P, qz = c / (P * P);
             int64_t cell = org[0] + qx;
             if (D > 1) cell += (int64_t)(org[1] + qy) * g.nos;
@@ -808,63 +892,71 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restri
         }
         hb[s] = h;
     }
+    // LDS offsets of the factors of cell 4s + lk for point 16q + li: periodic
+    // in s with period S4; q and the remainder of s are immediates.
+    int qa[S::S4], qb[S::S4];
+#pragma unroll
+    for (int sm = 0; sm < S::S4; ++sm) {
+        const int c = 4 * sm + lk;
+        qa[sm] = li * WSP + c % P;
+        qb[sm] = li * WSP + S::OB + c / P;
+    }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
         const int64_t first = (int64_t)tk.y + c0;
         __syncthreads();
-        if (lane < cnt) stage_point_weights<D>(g, c32, f32, first + lane, org, beta, wts + lane * ws);
-        else zero_record(ws, wts + lane * ws);
+        put_record<D, P>(pin, lane < cnt, org, g.w, two_over_w, beta, wts + lane * WSP);
         __syncthreads();
-        floatx4 acc[4];
-        const float *wp[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-            wp[q] = wts + (16 * q + li) * ws;        // A row: point 16q + li
-        }
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int c = 4 * s + lk;
-            const int ca = tab[c], cb = tab[16 * NT + c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float a = D > 1 ? wp[q][ca] * wp[q][cb] : wp[q][ca];
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hb[s], acc[q], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int pt = 16 * q + 4 * lk + r;
-                if (pt < cnt) Fs[(first + pt) * bs + v0 + li] = acc[q][r];
-            }
+        const int c1 = c0 + 64;
+        if (c1 < tk.z) fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
+        const int nq = (cnt + 15) >> 4;
+        if (nq == 4) interp_chunk<D, P, 4>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
+        else if (nq == 3) interp_chunk<D, P, 3>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
+        else if (nq == 2) interp_chunk<D, P, 2>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
+        else interp_chunk<D, P, 1>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
     }
 }
 
-// Tile counts with a compiled matrix-core variant; a patch uses the first
-// one that covers it (extra cells carry zero weight).
-static const int kNtiles[] = {1, 2, 3, 4, 6, 8, 10, 12, 14, 16};
-
-static int mfma_ntiles(int PD) {
-    for (int nt : kNtiles)
-        if (16 * nt >= PD) return nt;
-    return 0;
+// Patch edges with a compiled matrix-core variant, per dimension.
+static bool mfma_patch_ok(int D, int P) {
+    if (P < 2) return false;
+    if (D == 3) return P <= 6;
+    if (D == 2) return P <= 12;
+    return P <= 16;
 }
 
-#define MLG_NT_SWITCH(nt, CALL)                                                    \
-    switch (nt) {                                                                  \
-        case 1: CALL(1); break;                                                    \
-        case 2: CALL(2); break;                                                    \
-        case 3: CALL(3); break;                                                    \
-        case 4: CALL(4); break;                                                    \
-        case 6: CALL(6); break;                                                    \
-        case 8: CALL(8); break;                                                    \
-        case 10: CALL(10); break;                                                  \
-        case 12: CALL(12); break;                                                  \
-        case 14: CALL(14); break;                                                  \
-        case 16: CALL(16); break;                                                  \
-        default: throw Error(MLG_ERR_ARG, "unsupported tile count");               \
+#define MLG_P_SWITCH(D, p, CALL)                                                   \
+    switch (p) {                                                                   \
+        case 2: CALL(D, 2); break;                                                 \
+        case 3: CALL(D, 3); break;                                                 \
+        case 4: CALL(D, 4); break;                                                 \
+        case 5: CALL(D, 5); break;                                                 \
+        case 6: CALL(D, 6); break;                                                 \
+        default:                                                                   \
+            if constexpr (D < 3) {                                                 \
+                switch (p) {                                                       \
+                    case 7: CALL(D, 7); break;                                     \
+                    case 8: CALL(D, 8); break;                                     \
+                    case 9: CALL(D, 9); break;                                     \
+                    case 10: CALL(D, 10); break;                                   \
+                    case 11: CALL(D, 11); break;                                   \
+                    case 12: CALL(D, 12); break;                                   \
+                    default:                                                       \
+                        if constexpr (D < 2) {                                     \
+                            switch (p) {                                           \
+                                case 13: CALL(D, 13); break;                       \
+                                case 14: CALL(D, 14); break;                       \
+                                case 15: CALL(D, 15); break;                       \
+                                case 16: CALL(D, 16); break;                       \
+                                default: throw Error(MLG_ERR_ARG, "unsupported patch edge"); \
+                            }                                                      \
+                        } else {                                                   \
+                            throw Error(MLG_ERR_ARG, "unsupported patch edge");    \
+                        }                                                          \
+                }                                                                  \
+            } else {                                                               \
+                throw Error(MLG_ERR_ARG, "unsupported patch edge");                \
+            }                                                                      \
     }
 
 template <class T>
@@ -1569,17 +1661,14 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     const T beta = (T)W.beta;
     // FP32 blocks of 16 vectors with patches of <= 256 cells use the matrix
     // cores; everything else the vector-ALU kernels.
-    const bool mf = std::is_same<T, float>::value && bs % 16 == 0 && g.PD <= 256;
-    const int ws = D == 3 ? 3 * g.P + g.P * g.P + 1 : D * g.P + 1;
-    const int ntl = mfma_ntiles(g.PD);
+    const bool mf = std::is_same<T, float>::value && bs % 16 == 0 && mfma_patch_ok(D, g.P);
     if (P.ntasks > 0) {
         if constexpr (std::is_same<T, float>::value) {
             if (mf) {
-                const size_t lds = (size_t)64 * (ws + 16) * sizeof(float);
-#define SPREADM_CALL(NT)                                                                        \
-    hipLaunchKernelGGL((k_spread_mfma<D, NT>), dim3(P.ntasks, bs / 16), dim3(64), lds, s, g, P.tasks.p, \
+#define SPREADM_CALL(DD, PP)                                                                      \
+    hipLaunchKernelGGL((k_spread_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
                        P.c32.p, P.f32.p, Zs, beta, patch)
-                MLG_NT_SWITCH(ntl, SPREADM_CALL)
+                MLG_P_SWITCH(D, g.P, SPREADM_CALL)
 #undef SPREADM_CALL
                 MLG_LAUNCH_CHECK();
             }
@@ -1623,11 +1712,10 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     if (ev) MLG_HIP(hipEventRecord(ev[3], s));
     if constexpr (std::is_same<T, float>::value) {
         if (mf && P.ntasks > 0) {
-            const size_t lds = (size_t)64 * ws * sizeof(float) + 32 * ntl * sizeof(int);
-#define INTERPM_CALL(NT)                                                                          \
-    hipLaunchKernelGGL((k_interp_mfma<D, NT>), dim3(P.ntasks, bs / 16), dim3(64), lds, s, g, P.tasks.p, \
+#define INTERPM_CALL(DD, PP)                                                                      \
+    hipLaunchKernelGGL((k_interp_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
                        P.c32.p, P.f32.p, grid, bg, beta, Fs)
-            MLG_NT_SWITCH(ntl, INTERPM_CALL)
+            MLG_P_SWITCH(D, g.P, INTERPM_CALL)
 #undef INTERPM_CALL
             MLG_LAUNCH_CHECK();
         }
