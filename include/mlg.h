@@ -27,9 +27,10 @@
  *  - The caller owns every array it passes.  The library never frees a
  *    caller pointer and keeps none past the call.  A graph handle owns its
  *    own device memory (points, plans, degrees, workspaces, HIP graphs).
- *  - Work is enqueued on the HIP stream given at creation (NULL = the null
- *    stream) and the call returns after that stream has drained, so device
- *    outputs are ready when it returns.
+ *  - Work is enqueued on the HIP stream given at creation (NULL = a
+ *    non-blocking stream the handle creates and owns) and the call returns
+ *    after that stream has drained, so device outputs are ready when it
+ *    returns.
  *  - One handle must not be used from two threads at once.
  *  - Same inputs and same parameters give bit-identical outputs: no kernel
  *    accumulates floating point through atomics.
@@ -56,6 +57,10 @@ typedef enum {
 } mlg_status;
 
 #define MLG_DEVICE_PTRS 1
+/* mlg_graph_create: skip the degree pass; the graph then serves MLG_OP_W
+ * products only (degree-normalised operators, degrees and Lanczos return
+ * MLG_ERR_ARG). */
+#define MLG_SKIP_DEGREES 2
 
 /* summation method */
 #define MLG_METHOD_DIRECT 0 /* O(n^2) tiled direct sum (Sec. 2 case (i))       */
@@ -114,11 +119,13 @@ const char *mlg_version(void);
  *            per flags; only read during the call).
  *   sigma    T kernel widths, > 0.
  *   kp       T parameter records.
- *   flags    MLG_DEVICE_PTRS or 0.
- *   stream   hipStream_t for all work on this graph (NULL = null stream).
+ *   flags    MLG_DEVICE_PTRS and/or MLG_SKIP_DEGREES, or 0.
+ *   stream   hipStream_t for all work on this graph (NULL = a non-blocking
+ *            stream owned by the handle).
  * Plans every layer (torus scaling, kernel Fourier coefficients, bin sort)
- * and computes each layer's degrees in FP64.  Returns MLG_ERR_ISOLATED if a
- * degree is not positive (below 1e-9 for NFFT layers).
+ * and, unless MLG_SKIP_DEGREES is given, computes each layer's degrees in
+ * FP64.  Returns MLG_ERR_ISOLATED if a degree is not positive (below 1e-9
+ * for NFFT layers).
  */
 mlg_status mlg_graph_create(mlg_graph **out, int64_t n, int T, const int *d,
                             const double *const *points, const double *sigma,

@@ -5,20 +5,19 @@
 // sigma (FP64), or multiplied by sqrt(log2 e)/sigma (FP32), so that a weight
 // is exp(-r^2) or exp2(-r^2) of the scaled squared distance.
 //
-// Blocks of 8 or more vectors run the exp tile x vector block contraction on
-// the matrix cores: per wavefront, 16 target rows against 16 source points,
-// the 16 x 16 weight tile E is formed on the vector ALUs (four entries per
-// lane, in the A-operand layout of the 16x16x4 MFMA) and multiplied by the
-// 16 x 16 vector tile of Z with four MFMAs.  Narrower blocks accumulate on
-// the vector ALUs.  Rows are split over workgroups and the column range over
-// a second grid dimension; the column partials are summed in a fixed order,
-// so results are reproducible bit for bit.
+// The exp tile x vector block contraction runs on the matrix cores: per
+// wavefront, 16 target rows against 16 source points, the 16 x 16 weight
+// tile E is formed on the vector ALUs (four entries per lane, in the
+// A-operand layout of the 16x16x4 MFMA) and multiplied by the 16 x 16 vector
+// tile of Z with four MFMAs (blocks narrower than 16 vectors pad the tile
+// with zero columns).  Rows are split over workgroups and the column range
+// over a second grid dimension; the column partials are summed in a fixed
+// order, so results are reproducible bit for bit.
 #include "internal.h"
 
 namespace mlg {
 
 constexpr int kDirectMaxD = 16;
-constexpr int kJT = 64;        // source points per LDS stage (vector-ALU kernel)
 constexpr int kDmRT = 2;       // 16-row target tiles per wavefront (MFMA kernel)
 constexpr int kDmRows = 4 * kDmRT * 16;  // target rows per workgroup (4 wavefronts)
 constexpr int kDmJC = 128;     // source points per LDS stage (MFMA kernel)
@@ -27,59 +26,7 @@ constexpr int kDmJC = 128;     // source points per LDS stage (MFMA kernel)
 __device__ inline float kweight(float r2) { return __builtin_amdgcn_exp2f(-r2); }
 __device__ inline double kweight(double r2) { return exp(-r2); }
 
-// ---- vector-ALU kernel (blocks of 1, 2 or 4 vectors) ---------------------------
-template <class T, int BS>
-__global__ __launch_bounds__(256) void k_direct(int64_t n, int d, const T *__restrict__ x,
-                                                const T *__restrict__ Zs, T *__restrict__ out,
-                                                int64_t jchunk) {
-    __shared__ T sx[kDirectMaxD][kJT];
-    __shared__ T sz[kJT][BS];
-    const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
-    const bool valid = i < n;
-    T xi[kDirectMaxD];
-#pragma unroll
-    for (int k = 0; k < kDirectMaxD; ++k) xi[k] = (k < d && valid) ? x[(int64_t)k * n + i] : T(0);
-    T acc[BS];
-#pragma unroll
-    for (int v = 0; v < BS; ++v) acc[v] = T(0);
-    const int64_t j0 = (int64_t)blockIdx.y * jchunk;
-    const int64_t j1 = (j0 + jchunk < n) ? j0 + jchunk : n;
-    for (int64_t jb = j0; jb < j1; jb += kJT) {
-        const int cnt = (int)((j1 - jb) < kJT ? (j1 - jb) : kJT);
-        __syncthreads();
-        for (int e = tid; e < d * kJT; e += 256) {
-            int k = e / kJT, jj = e - k * kJT;
-            sx[k][jj] = jj < cnt ? x[(int64_t)k * n + jb + jj] : T(0);
-        }
-        for (int e = tid; e < kJT * BS; e += 256) {
-            int jj = e / BS, v = e - jj * BS;
-            sz[jj][v] = jj < cnt ? Zs[(jb + jj) * BS + v] : T(0);
-        }
-        __syncthreads();
-        for (int jj = 0; jj < cnt; ++jj) {
-            T r2 = T(0);
-#pragma unroll
-            for (int k = 0; k < kDirectMaxD; ++k) {
-                if (k < d) {
-                    T dk = xi[k] - sx[k][jj];
-                    r2 += dk * dk;
-                }
-            }
-            T e = kweight(r2);
-            if (jb + jj == i) e = T(0);
-#pragma unroll
-            for (int v = 0; v < BS; ++v) acc[v] += e * sz[jj][v];
-        }
-    }
-    if (valid) {
-        T *o = out + ((int64_t)blockIdx.y * n + i) * BS;
-#pragma unroll
-        for (int v = 0; v < BS; ++v) o[v] = acc[v];
-    }
-}
-
-// ---- MFMA kernel (blocks of 8 to 64 vectors) -----------------------------------
+// ---- MFMA kernel ------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -111,18 +58,21 @@ struct Mfma16<double> {
 // B = Z[4q + r][v].  The LDS stage keeps Z in exactly that order
 // (sz[tile][vtile][lane][r]) so each lane reads its four values at once.
 //
-// DMAX bounds d (3 or 16); VT = vector tiles of 16 (bs = 8 uses one tile with
-// lanes v >= 8 reading zeros).
-template <class T, int DMAX, int VT>
+// DK = d for d <= 3 (compile time), or 0 for a runtime d <= 16; VT = vector
+// tiles of 16 (bs < 16 uses one tile with lanes v >= bs reading zeros).
+template <class T, int DK, int VT>
 __global__ __launch_bounds__(256) void k_direct_mfma(int64_t n, int d, int bs,
                                                      const T *__restrict__ x,
                                                      const T *__restrict__ Zs,
                                                      T *__restrict__ out, int64_t jchunk) {
     typedef typename Mfma16<T>::acc acc_t;
+    constexpr int DMAX = DK > 0 ? DK : kDirectMaxD;
+    if (DK > 0) d = DK;
     __shared__ T sc[kDmJC / 16][DMAX][16];
     __shared__ T sz[kDmJC / 16][VT][64][4];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, q = lane >> 4;
     const int64_t row0 = (int64_t)blockIdx.x * kDmRows + wave * (kDmRT * 16);
     T yi[kDmRT][DMAX];
@@ -283,12 +233,10 @@ static int direct_splits(int64_t n, int rows_per_wg, int stage) {
     return S < 1 ? 1 : S;
 }
 
-static bool use_mfma(int bs) { return bs >= 8; }
-
 static void split_plan(int64_t n, int bs, int &S, int64_t &jchunk) {
-    const int rows = use_mfma(bs) ? kDmRows : 256;
-    const int stage = use_mfma(bs) ? kDmJC : kJT;
-    S = direct_splits(n, rows, stage);
+    (void)bs;
+    const int stage = kDmJC;
+    S = direct_splits(n, kDmRows, stage);
     jchunk = (n + S - 1) / S;
     jchunk = (jchunk + stage - 1) / stage * stage;
     S = (int)((n + jchunk - 1) / jchunk);
@@ -302,28 +250,23 @@ size_t direct_part_size(int64_t n, int bs) {
     return S > 1 ? (size_t)S * n * bs : 0;
 }
 
-template <class T, int BS>
-static void launch_valu(int64_t n, int d, const T *x, const T *Zs, T *dst, int S, int64_t jchunk,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((k_direct<T, BS>), dim3(ceil_div(n, 256), S), dim3(256), 0, s, n, d, x, Zs, dst,
-                       jchunk);
-    MLG_LAUNCH_CHECK();
-}
-
-template <class T, int DMAX>
+template <class T, int DK>
 static void launch_mfma_d(int64_t n, int d, int bs, const T *x, const T *Zs, T *dst, int S,
                           int64_t jchunk, hipStream_t s) {
     const dim3 grid(ceil_div(n, kDmRows), S);
     switch (bs) {
+        case 1:
+        case 2:
+        case 4:
         case 8:
         case 16:
-            hipLaunchKernelGGL((k_direct_mfma<T, DMAX, 1>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
+            hipLaunchKernelGGL((k_direct_mfma<T, DK, 1>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
             break;
         case 32:
-            hipLaunchKernelGGL((k_direct_mfma<T, DMAX, 2>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
+            hipLaunchKernelGGL((k_direct_mfma<T, DK, 2>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
             break;
         case 64:
-            hipLaunchKernelGGL((k_direct_mfma<T, DMAX, 4>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
+            hipLaunchKernelGGL((k_direct_mfma<T, DK, 4>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
             break;
         default: throw Error(MLG_ERR_ARG, "direct: unsupported block stride");
     }
@@ -342,16 +285,11 @@ void launch_direct(int64_t n, int d, const T *x, int bs, const T *Zs, T *Fs, T *
         MLG_REQUIRE(part && part_cap >= (size_t)S * n * bs, MLG_ERR_ARG, "direct: workspace too small");
         dst = part;
     }
-    if (use_mfma(bs)) {
-        if (d <= 3) launch_mfma_d<T, 3>(n, d, bs, x, Zs, dst, S, jchunk, s);
-        else launch_mfma_d<T, kDirectMaxD>(n, d, bs, x, Zs, dst, S, jchunk, s);
-    } else {
-        switch (bs) {
-            case 1: launch_valu<T, 1>(n, d, x, Zs, dst, S, jchunk, s); break;
-            case 2: launch_valu<T, 2>(n, d, x, Zs, dst, S, jchunk, s); break;
-            case 4: launch_valu<T, 4>(n, d, x, Zs, dst, S, jchunk, s); break;
-            default: throw Error(MLG_ERR_ARG, "direct: unsupported block stride");
-        }
+    switch (d) {
+        case 1: launch_mfma_d<T, 1>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
+        case 2: launch_mfma_d<T, 2>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
+        case 3: launch_mfma_d<T, 3>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
+        default: launch_mfma_d<T, 0>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
     }
     if (S > 1) {
         const int64_t total = n * bs;

@@ -147,6 +147,8 @@ static void core(Graph &g, int layer, int bs, StageTimer *tm) {
 static void check_op(const Graph &g, int layer, int op, int b) {
     MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
     MLG_REQUIRE(op == MLG_OP_NADJ || op == MLG_OP_LSYM || op == MLG_OP_W, MLG_ERR_ARG, "bad op");
+    MLG_REQUIRE(op == MLG_OP_W || g.has_degrees, MLG_ERR_ARG,
+                "graph created with MLG_SKIP_DEGREES serves MLG_OP_W only");
     MLG_REQUIRE(!(op == MLG_OP_W && layer < 0), MLG_ERR_ARG, "MLG_OP_W needs one layer");
     MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
 }
@@ -341,6 +343,7 @@ static mlg_status create_graph(mlg_graph **out, int64_t n, int T, const int *d,
         h->g.stream = make_stream(stream);
         h->g.n = n;
         h->g.T = T;
+        h->g.has_degrees = degrees;
         h->g.layers.resize(T);
         try {
             for (int t = 0; t < T; ++t) {
@@ -364,7 +367,8 @@ static mlg_status create_graph(mlg_graph **out, int64_t n, int T, const int *d,
 mlg_status mlg_graph_create(mlg_graph **out, int64_t n, int T, const int *d,
                             const double *const *points, const double *sigma,
                             const mlg_kparams *kp, int flags, void *stream) {
-    return create_graph(out, n, T, d, points, sigma, kp, flags, stream, true);
+    return create_graph(out, n, T, d, points, sigma, kp, flags, stream,
+                        (flags & MLG_SKIP_DEGREES) == 0);
 }
 
 mlg_status mlg_graph_destroy(mlg_graph *g) {
@@ -383,6 +387,7 @@ mlg_status mlg_graph_degrees(mlg_graph *h, int layer, double *deg, int flags) {
         MLG_REQUIRE(h && deg, MLG_ERR_ARG, "null argument");
         Graph &g = h->g;
         MLG_REQUIRE(layer >= 0 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+        MLG_REQUIRE(g.has_degrees, MLG_ERR_ARG, "graph created with MLG_SKIP_DEGREES has no degrees");
         MLG_HIP(hipMemcpyAsync(deg, g.layers[layer].deg.p, sizeof(double) * g.n,
                                (flags & MLG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice
                                                          : hipMemcpyDeviceToHost,
@@ -470,6 +475,7 @@ mlg_status mlg_lanczos_eigs(mlg_graph *h, int layer, double p, int k, int block,
         MLG_REQUIRE(h && evals && evecs, MLG_ERR_ARG, "null argument");
         Graph &g = h->g;
         MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+        MLG_REQUIRE(g.has_degrees, MLG_ERR_ARG, "graph created with MLG_SKIP_DEGREES has no Laplacian");
         MLG_REQUIRE(p == 1.0, MLG_ERR_NOT_IMPL, "only the p = 1 power mean is implemented");
         MLG_REQUIRE(k >= 1 && 2 * (int64_t)k <= g.n, MLG_ERR_ARG, "k must be in 1..n/2");
         MLG_REQUIRE(block >= 1 && block <= 32, MLG_ERR_ARG, "block must be in 1..32");

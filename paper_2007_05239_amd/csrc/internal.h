@@ -131,6 +131,7 @@ void ac_run(int64_t n, int k, int m, const double *evals_dev, const double *evec
 struct Graph {
     int64_t n = 0;
     int T = 0;
+    bool has_degrees = true;
     hipStream_t stream = nullptr;
     std::vector<Layer> layers;
     // workspaces: per-layer slices of Zs/Fs (n x bs, the layer's precision)

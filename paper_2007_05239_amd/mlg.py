@@ -25,6 +25,7 @@ MLG_ERR_HIP = -5
 MLG_ERR_NOT_IMPL = -6
 
 MLG_DEVICE_PTRS = 1
+MLG_SKIP_DEGREES = 2
 MLG_METHOD_DIRECT = 0
 MLG_METHOD_NFFT = 1
 MLG_OP_NADJ = 0
@@ -145,7 +146,7 @@ def _colmajor(X):
 class Graph:
     """A multilayer graph (mlg_graph_create); one layer per point set."""
 
-    def __init__(self, layers, sigmas, params=None, device=False):
+    def __init__(self, layers, sigmas, params=None, device=False, degrees=True):
         self.n = int(layers[0].shape[0])
         self.T = len(layers)
         if params is None:
@@ -170,8 +171,9 @@ class Graph:
         sarr = (ctypes.c_double * self.T)(*[float(s) for s in sigmas])
         karr = (KParams * self.T)(*params)
         h = ctypes.c_void_p()
+        flags = (MLG_DEVICE_PTRS if dev else 0) | (0 if degrees else MLG_SKIP_DEGREES)
         _check(_lib.mlg_graph_create(ctypes.byref(h), self.n, self.T, ds, parr, sarr, karr,
-                                     MLG_DEVICE_PTRS if dev else 0, None))
+                                     flags, None))
         self._h = h
         self._keep = []
 
