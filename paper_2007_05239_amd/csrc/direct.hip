@@ -92,16 +92,34 @@ __global__ __launch_bounds__(256) void k_direct_mfma(int64_t n, int d, int bs,
     const int64_t j1 = (j0 + jchunk < n) ? j0 + jchunk : n;
     for (int64_t jb = j0; jb < j1; jb += kDmJC) {
         const int cnt = (int)((j1 - jb) < kDmJC ? (j1 - jb) : kDmJC);
-        __syncthreads();
-        for (int e = tid; e < d * kDmJC; e += 256) {
+        // every global load of the stage issued before the first LDS write
+        constexpr int CI = (DMAX * kDmJC + 255) / 256, ZI = kDmJC * VT * 16 / 256;
+        T cv[CI], zv[ZI];
+#pragma unroll
+        for (int it = 0; it < CI; ++it) {
+            const int e = tid + 256 * it;
             const int k = e / kDmJC, jj = e - k * kDmJC;
-            sc[jj >> 4][k][jj & 15] = jj < cnt ? x[(int64_t)k * n + jb + jj] : T(0);
+            cv[it] = (k < d && jj < cnt) ? x[(int64_t)k * n + jb + jj] : T(0);
         }
-        for (int e = tid; e < kDmJC * VT * 16; e += 256) {
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const int e = tid + 256 * it;
             const int jj = e / (VT * 16), v = e - jj * (VT * 16);
-            const T val = (jj < cnt && v < bs) ? Zs[(jb + jj) * bs + v] : T(0);
+            zv[it] = (jj < cnt && v < bs) ? Zs[(jb + jj) * bs + v] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < CI; ++it) {
+            const int e = tid + 256 * it;
+            const int k = e / kDmJC, jj = e - k * kDmJC;
+            if (k < d) sc[jj >> 4][k][jj & 15] = cv[it];
+        }
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const int e = tid + 256 * it;
+            const int jj = e / (VT * 16), v = e - jj * (VT * 16);
             const int jl = jj & 15;
-            sz[jj >> 4][v >> 4][(v & 15) + 16 * (jl >> 2)][jl & 3] = val;
+            sz[jj >> 4][v >> 4][(v & 15) + 16 * (jl >> 2)][jl & 3] = zv[it];
         }
         __syncthreads();
         const int ntile = (cnt + 15) >> 4;

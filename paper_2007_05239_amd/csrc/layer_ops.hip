@@ -5,17 +5,17 @@
 //   gather-out   y = coef sum_t D_t^-1/2 (F_t - K(0) z_t) in FP64, with the
 //                self term of W = W~ - K(0) I (Sec. 4) and the layer mean
 //                (1/T) sum_t (Sec. 3); y = x - that for L_sym / L_1.
-// Both move 256 rows of the column-major block through LDS so that the
-// column-major side and the point-major side are both coalesced; one thread
-// owns one row (its permutation entry and D^-1/2 are read once per layer).
-// The layer sum runs in layer order.
+// One thread owns one row (its permutation entry and D^-1/2 are read once
+// per layer).  The layer sum runs in layer order.
 #include "internal.h"
 
 namespace mlg {
 
-// Thread per row; vectors in groups of VG = 16 (or bs if smaller).  The
-// column-major block moves through an LDS tile of 256 rows x VG columns.
-constexpr int kIoRows = 256;
+// Thread per row, vectors in groups of VG = 16 (or bs if smaller): a
+// thread reads its row of the column-major block column by column (each
+// column access is contiguous across the workgroup's threads), with every
+// load of the group issued before the first use, and writes or reads the
+// layer's sorted row (bs consecutive values) with vector accesses.
 constexpr int kIoVG = 16;
 
 template <class T>
@@ -49,29 +49,23 @@ __device__ inline void load_row(const void *Fbase, int64_t off, double (&f)[kIoV
     for (int j = 0; j < cnt; ++j) f[j] = (double)src[j];
 }
 
+__device__ inline void load_block_row(const double *__restrict__ X, int64_t ldx, int64_t i, int b,
+                                      int v0, int vgw, double (&x)[kIoVG]) {
+#pragma unroll
+    for (int j = 0; j < kIoVG; ++j)
+        x[j] = (j < vgw && v0 + j < b) ? X[i + (int64_t)(v0 + j) * ldx] : 0.0;
+}
+
 __global__ __launch_bounds__(256) void k_scatter_in(int64_t n, int b, int bs,
                                                     const double *__restrict__ X, int64_t ldx,
                                                     const LayerIO *__restrict__ L, int nl,
                                                     int use_dinv) {
-    __shared__ double tile[kIoVG * (kIoRows + 1)];
-    const int64_t i0 = (int64_t)blockIdx.x * kIoRows;
-    const int rows = (int)((n - i0) < kIoRows ? (n - i0) : kIoRows);
-    const int r = threadIdx.x;
-    const int64_t i = i0 + r;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     const int vgw = bs < kIoVG ? bs : kIoVG;
     for (int v0 = 0; v0 < bs; v0 += vgw) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kIoRows * vgw; e += blockDim.x) {
-            const int rr = e % kIoRows, v = e / kIoRows;
-            double x = 0.0;
-            if (rr < rows && v0 + v < b) x = X[i0 + rr + (int64_t)(v0 + v) * ldx];
-            tile[v * (kIoRows + 1) + rr] = x;
-        }
-        __syncthreads();
-        if (r >= rows) continue;
         double x[kIoVG];
-#pragma unroll
-        for (int j = 0; j < kIoVG; ++j) x[j] = j < vgw ? tile[j * (kIoRows + 1) + r] : 0.0;
+        load_block_row(X, ldx, i, b, v0, vgw, x);
         for (int t = 0; t < nl; ++t) {
             const LayerIO d = L[t];
             const int64_t p = d.invperm ? d.invperm[i] : i;
@@ -90,60 +84,40 @@ __global__ __launch_bounds__(256) void k_gather_out(int64_t n, int b, int bs,
                                                     double *__restrict__ Y, int64_t ldy,
                                                     const LayerIO *__restrict__ L, int nl,
                                                     int use_dinv, int lsym, double coef) {
-    __shared__ double tile[kIoVG * (kIoRows + 1)];
-    const int64_t i0 = (int64_t)blockIdx.x * kIoRows;
-    const int rows = (int)((n - i0) < kIoRows ? (n - i0) : kIoRows);
-    const int r = threadIdx.x;
-    const int64_t i = i0 + r;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     const int vgw = bs < kIoVG ? bs : kIoVG;
     for (int v0 = 0; v0 < b; v0 += vgw) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < kIoRows * vgw; e += blockDim.x) {
-            const int rr = e % kIoRows, v = e / kIoRows;
-            double x = 0.0;
-            if (rr < rows && v0 + v < b) x = X[i0 + rr + (int64_t)(v0 + v) * ldx];
-            tile[v * (kIoRows + 1) + rr] = x;
-        }
-        __syncthreads();
-        if (r < rows) {
-            double x[kIoVG], acc[kIoVG];
+        double x[kIoVG], acc[kIoVG];
+        load_block_row(X, ldx, i, b, v0, vgw, x);
 #pragma unroll
-            for (int j = 0; j < kIoVG; ++j) {
-                x[j] = j < vgw ? tile[j * (kIoRows + 1) + r] : 0.0;
-                acc[j] = 0.0;
-            }
-            for (int t = 0; t < nl; ++t) {
-                const LayerIO d = L[t];
-                const int64_t p = d.invperm ? d.invperm[i] : i;
-                const double di = use_dinv ? d.dinv[i] : 1.0;
-                double f[kIoVG];
-                if (d.is64) load_row<double>(d.F, p * bs + v0, f, vgw);
-                else load_row<float>(d.F, p * bs + v0, f, vgw);
-#pragma unroll
-                for (int j = 0; j < kIoVG; ++j) {
-                    if (j < vgw) {
-                        const double zx = use_dinv ? x[j] * di : x[j];
-                        // the value the summation saw (FP32 layers round it)
-                        const double z = d.is64 ? zx : (double)(float)zx;
-                        double w = f[j] - d.K0 * z;
-                        if (use_dinv) w *= di;
-                        acc[j] += w;
-                    }
-                }
-            }
+        for (int j = 0; j < kIoVG; ++j) acc[j] = 0.0;
+        for (int t = 0; t < nl; ++t) {
+            const LayerIO d = L[t];
+            const int64_t p = d.invperm ? d.invperm[i] : i;
+            const double di = use_dinv ? d.dinv[i] : 1.0;
+            double f[kIoVG];
+            if (d.is64) load_row<double>(d.F, p * bs + v0, f, vgw);
+            else load_row<float>(d.F, p * bs + v0, f, vgw);
 #pragma unroll
             for (int j = 0; j < kIoVG; ++j) {
                 if (j < vgw) {
-                    double y = coef * acc[j];
-                    if (lsym) y = x[j] - y;
-                    tile[j * (kIoRows + 1) + r] = y;
+                    const double zx = use_dinv ? x[j] * di : x[j];
+                    // the value the summation saw (FP32 layers round it)
+                    const double z = d.is64 ? zx : (double)(float)zx;
+                    double w = f[j] - d.K0 * z;
+                    if (use_dinv) w *= di;
+                    acc[j] += w;
                 }
             }
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < kIoRows * vgw; e += blockDim.x) {
-            const int rr = e % kIoRows, v = e / kIoRows;
-            if (rr < rows && v0 + v < b) Y[i0 + rr + (int64_t)(v0 + v) * ldy] = tile[v * (kIoRows + 1) + rr];
+#pragma unroll
+        for (int j = 0; j < kIoVG; ++j) {
+            if (j < vgw && v0 + j < b) {
+                double y = coef * acc[j];
+                if (lsym) y = x[j] - y;
+                Y[i + (int64_t)(v0 + j) * ldy] = y;
+            }
         }
     }
 }
@@ -178,7 +152,7 @@ static inline unsigned blocks_for(int64_t work, int threads) {
 void launch_scatter_in(int64_t n, int b, int bs, const double *X, int64_t ldx, const LayerIO *L,
                        int nl, int use_dinv, hipStream_t s) {
     MLG_REQUIRE(bs <= 64 && b <= bs, MLG_ERR_ARG, "block too wide");
-    hipLaunchKernelGGL(k_scatter_in, dim3(blocks_for(n, kIoRows)), dim3(256), 0, s, n, b, bs, X, ldx, L,
+    hipLaunchKernelGGL(k_scatter_in, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, b, bs, X, ldx, L,
                        nl, use_dinv);
     MLG_LAUNCH_CHECK();
 }
@@ -187,7 +161,7 @@ void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, d
                        int64_t ldy, const LayerIO *L, int nl, int use_dinv, int lsym, double coef,
                        hipStream_t s) {
     MLG_REQUIRE(bs <= 64 && b <= bs, MLG_ERR_ARG, "block too wide");
-    hipLaunchKernelGGL(k_gather_out, dim3(blocks_for(n, kIoRows)), dim3(256), 0, s, n, b, bs, X, ldx, Y,
+    hipLaunchKernelGGL(k_gather_out, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, b, bs, X, ldx, Y,
                        ldy, L, nl, use_dinv, lsym, coef);
     MLG_LAUNCH_CHECK();
 }

@@ -498,8 +498,16 @@ __global__ void k_reduce1(int64_t elems, const int2 *__restrict__ grp, T *__rest
     if (e >= elems) return;
     const int2 gr = grp[blockIdx.x];
     const T *src = patch + (int64_t)gr.x * elems + e;
+    // loads in batches of 8 (all in flight together), sums in task order
     T s = src[0];
-    for (int j = 1; j < gr.y; ++j) s += src[(int64_t)j * elems];
+    for (int j0 = 1; j0 < gr.y; j0 += 8) {
+        T h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h[u] = j0 + u < gr.y ? src[(int64_t)(j0 + u) * elems] : T(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < gr.y) s += h[u];
+    }
     patch[(int64_t)gr.x * elems + e] = s;
 }
 
@@ -512,7 +520,14 @@ __global__ void k_reduce2(int64_t elems, const int4 *__restrict__ runs, T *__res
     const int4 r = runs[blockIdx.x];
     const T *src = patch + (int64_t)r.y * elems + e;
     T s = src[0];
-    for (int j = 1; j < r.z; ++j) s += src[(int64_t)j * 32 * elems];
+    for (int j0 = 1; j0 < r.z; j0 += 8) {
+        T h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h[u] = j0 + u < r.z ? src[(int64_t)(j0 + u) * 32 * elems] : T(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < r.z) s += h[u];
+    }
     patch[(int64_t)r.x * elems + e] = s;
 }
 
@@ -559,11 +574,25 @@ __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
 #pragma unroll
     for (int v = 0; v < VPL; ++v) acc[v] = T(0);
     const int e1 = ptr[cell + 1];
-    for (int e = ptr[cell]; e < e1; ++e) {
-        T h[VPL];
-        load_vec<T, VPL>(patch + (int64_t)ent[e] * bs + v0, h);
+    // entries in batches of 4: indices, then rows, all in flight; summed in
+    // entry order
+    for (int e0 = ptr[cell]; e0 < e1; e0 += 4) {
+        int idx[4];
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) acc[v] += h[v];
+        for (int u = 0; u < 4; ++u) idx[u] = e0 + u < e1 ? ent[e0 + u] : -1;
+        T h[4][VPL];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (idx[u] >= 0) load_vec<T, VPL>(patch + (int64_t)idx[u] * bs + v0, h[u]);
+            else
+#pragma unroll
+                for (int v = 0; v < VPL; ++v) h[u][v] = T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (idx[u] >= 0)
+#pragma unroll
+                for (int v = 0; v < VPL; ++v) acc[v] += h[u][v];
     }
     store_vec<T, VPL>(grid + cell * bg + v0, acc);
     if (bg > bs && blockIdx.y == 0)
@@ -966,112 +995,166 @@ struct Cplx<float> { using type = float2; };
 template <>
 struct Cplx<double> { using type = double2; };
 
-// Batched radix-2 FFT of length L along lines of a [outer][L][inner] complex
-// array; a workgroup handles LB outers x IC inner columns.  Only frequency
-// lines that can reach the band |l_t| <= N/2 are touched:
-//   cols = 0: every inner column;
-//   cols = 1: inner = [x][q], x frequency in the band;
-//   cols = 2: inner = [y][x][q], x and y frequencies in the band.
-// mode 0: forward; mode 1: inverse, entries whose line index is outside the
-// band read as zero (they were never multiplied); mode 2: forward, times the
-// multiplier M, inverse (the last axis of Algorithm 1 in one pass).
+// Batched radix-2 FFT of length L = 2^LOGL along one axis of the
+// [.. axes ..][q] complex grid (q = vector pair, innermost).  A line is
+// addressed as  off(o) + k S + coff(a),  k = 0..L-1 along the axis, with
+//   a in [0, A): the columns below the axis (contiguous in memory, or the
+//                band columns of the next-lower axis: abnd = 1);
+//   o in [0, O): the lines above the axis (plain stride ostr, or the band
+//                rows of the next-higher axis: obnd = 1).
+// Band mapping: index i of the N + 1 band frequencies -> grid index i
+// (i <= N/2) or L - (N + 1) + i.  Only frequency lines that can reach the
+// band |l_t| <= N/2 are touched, which prunes the later axes.
+// mode 0: forward, only the band entries along the axis are stored (the
+// others are never read again); mode 1: inverse, entries whose k is outside
+// the band read as zero (they were never multiplied); mode 2: forward, times
+// the multiplier M (indexed by grid cell = element offset / nq), inverse: the
+// last axis of Algorithm 1 in one pass.
+// A workgroup takes OB consecutive o and C consecutive a (OB * C = LINES
+// lines); loads and stores walk memory order (a fastest, then k, then o), the
+// LDS buffer holds buf[k][line] with the line fastest, so both the global
+// side and the butterflies are conflict-free.
 __device__ inline int band_index(int i, int N, int nos) { return i <= N / 2 ? i : nos - (N + 1) + i; }
 
 __device__ inline bool in_band(int k, int N, int nos) { return k <= N / 2 || k >= nos - N / 2; }
 
-template <class C2>
-__device__ inline void fft_stages(C2 *buf, int L, int logL, int lines, bool inverse,
-                                  const C2 *__restrict__ tw) {
-    for (int s = 0; s < logL; ++s) {
+struct FftPass {
+    int64_t O, A;        // lines: O outer x A columns
+    int64_t S;           // element stride along the axis
+    int64_t ostr;        // element stride of o (before band mapping)
+    int obnd, abnd;      // band-mapped o / a
+    int lognq;           // log2 of complex lanes per cell
+    int N;               // bandwidth
+    int mode;
+    int logC, logOB;     // workgroup tile: C = 2^logC columns, OB = 2^logOB outers
+    int64_t nachunk;     // ceil(A / C)
+};
+
+template <class C2, int LOGL, int LOGLINES>
+__device__ inline void fft_stages2(C2 *buf, const C2 *tw, bool inverse) {
+    constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES;
+#pragma unroll
+    for (int s = 0; s < LOGL; ++s) {
         const int half = 1 << s;
-        const int tstride = L >> (s + 1);
-        for (int e = threadIdx.x; e < (L / 2) * lines; e += blockDim.x) {
-            const int ln = e % lines, bf = e / lines;
+#pragma unroll
+        for (int it = 0; it < (L / 2) * LINES / 256; ++it) {
+            const int e = threadIdx.x + 256 * it;
+            const int ln = e & (LINES - 1), bf = e >> LOGLINES;
             const int grp = bf >> s, pos = bf & (half - 1);
             const int i0 = (grp << (s + 1)) + pos, i1 = i0 + half;
-            C2 w = tw[pos * tstride];
+            C2 w = tw[pos << (LOGL - 1 - s)];
             if (inverse) w.y = -w.y;
-            const C2 a = buf[i0 * lines + ln], b = buf[i1 * lines + ln];
+            const C2 a = buf[i0 * LINES + ln], b = buf[i1 * LINES + ln];
             C2 bw, r0, r1;
             bw.x = b.x * w.x - b.y * w.y;
             bw.y = b.x * w.y + b.y * w.x;
-            r0.x = a.x + bw.x; r0.y = a.y + bw.y;
-            r1.x = a.x - bw.x; r1.y = a.y - bw.y;
-            buf[i0 * lines + ln] = r0;
-            buf[i1 * lines + ln] = r1;
+            r0.x = a.x + bw.x;
+            r0.y = a.y + bw.y;
+            r1.x = a.x - bw.x;
+            r1.y = a.y - bw.y;
+            buf[i0 * LINES + ln] = r0;
+            buf[i1 * LINES + ln] = r1;
         }
         __syncthreads();
     }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict__ data, int L,
-                                             int logL, int64_t outer_cnt, int64_t inner,
-                                             int64_t nact, int IC, int LB, int mode, int cols,
-                                             int N, int nq, const typename Cplx<T>::type *__restrict__ tw,
+template <class T, int LOGL, int LOGLINES>
+__global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict__ data, FftPass p,
+                                             const typename Cplx<T>::type *__restrict__ twg,
                                              const T *__restrict__ M) {
     using C2 = typename Cplx<T>::type;
-    extern __shared__ unsigned char smem_raw[];
-    C2 *buf = reinterpret_cast<C2 *>(smem_raw);
-    const int tid = threadIdx.x;
-    const int64_t nchunk = (nact + IC - 1) / IC;
-    const int64_t a0 = ((int64_t)blockIdx.x % nchunk) * IC;
-    const int64_t o0 = ((int64_t)blockIdx.x / nchunk) * LB;
-    const int lines = IC * LB;
-    auto column = [&](int64_t a) -> int64_t {
-        if (cols == 0) return a;
-        const int q = (int)(a % nq);
-        const int64_t r = a / nq;
-        if (cols == 1) return (int64_t)band_index((int)r, N, L) * nq + q;
-        const int kx = band_index((int)(r % (N + 1)), N, L), ky = band_index((int)(r / (N + 1)), N, L);
-        return ((int64_t)ky * L + kx) * nq + q;
+    constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES;
+    __shared__ C2 buf[L * LINES];
+    __shared__ C2 tw[L / 2];
+    for (int j = threadIdx.x; j < L / 2; j += blockDim.x) tw[j] = twg[j];
+    const int C = 1 << p.logC;
+    const int64_t a0 = ((int64_t)blockIdx.x % p.nachunk) << p.logC;
+    const int64_t o0 = ((int64_t)blockIdx.x / p.nachunk) << p.logOB;
+    const int64_t nq1 = ((int64_t)1 << p.lognq) - 1;
+    // element offset of column a / outer o
+    auto coff = [&](int64_t a) -> int64_t {
+        if (!p.abnd) return a;
+        const int r = (int)(a >> p.lognq);
+        return ((int64_t)band_index(r, p.N, L) << p.lognq) + (a & nq1);
     };
-    for (int e = tid; e < L * lines; e += blockDim.x) {
-        const int ln = e % lines, k = e / lines;
-        const int oo = ln / IC, cc = ln - oo * IC;
-        const int64_t o = o0 + oo, a = a0 + cc;
-        C2 val;
-        val.x = T(0);
-        val.y = T(0);
-        if (o < outer_cnt && a < nact && (mode != 1 || in_band(k, N, L)))
-            val = data[(o * L + k) * inner + column(a)];
-        const int rk = __brev((unsigned)k) >> (32 - logL);
-        buf[rk * lines + ln] = val;
+    auto ooff = [&](int64_t o) -> int64_t {
+        return (p.obnd ? (int64_t)band_index((int)o, p.N, L) : o) * p.ostr;
+    };
+    // all loads of the thread in flight before the first LDS write
+    constexpr int PER = L * LINES / 256;
+    C2 val[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int cc = e & (C - 1);
+        const int k = (e >> p.logC) & (L - 1);
+        const int oo = e >> (p.logC + LOGL);
+        const int64_t a = a0 + cc, o = o0 + oo;
+        val[it].x = T(0);
+        val[it].y = T(0);
+        if (a < p.A && o < p.O && (p.mode != 1 || in_band(k, p.N, L)))
+            val[it] = data[ooff(o) + (int64_t)k * p.S + coff(a)];
+    }
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int cc = e & (C - 1);
+        const int k = (e >> p.logC) & (L - 1);
+        const int oo = e >> (p.logC + LOGL);
+        const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
+        buf[rk * LINES + (oo << p.logC) + cc] = val[it];
     }
     __syncthreads();
-    fft_stages<C2>(buf, L, logL, lines, mode == 1, tw);
-    if (mode == 2) {
-        // multiply by M (cell = line index * inner extent / nq + column / nq),
-        // then put the line back into bit-reversed order for the inverse
-        for (int e = tid; e < L * lines; e += blockDim.x) {
-            const int ln = e % lines, k = e / lines;
-            const int cc = ln % IC;
-            const int64_t a = a0 + cc;
-            T m = T(0);
-            if (a < nact) m = M[(int64_t)k * (inner / nq) + column(a) / nq];
-            C2 v = buf[k * lines + ln];
-            v.x *= m;
-            v.y *= m;
-            buf[k * lines + ln] = v;
+    fft_stages2<C2, LOGL, LOGLINES>(buf, tw, p.mode == 1);
+    if (p.mode == 2) {
+        T m[PER];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int e = threadIdx.x + 256 * it;
+            const int cc = e & (C - 1);
+            const int k = (e >> p.logC) & (L - 1);
+            const int oo = e >> (p.logC + LOGL);
+            const int64_t a = a0 + cc, o = o0 + oo;
+            m[it] = T(0);
+            if (a < p.A && o < p.O) m[it] = M[(ooff(o) + (int64_t)k * p.S + coff(a)) >> p.lognq];
+        }
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int e = threadIdx.x + 256 * it;
+            const int cc = e & (C - 1);
+            const int k = (e >> p.logC) & (L - 1);
+            const int oo = e >> (p.logC + LOGL);
+            const int i = k * LINES + (oo << p.logC) + cc;
+            C2 v = buf[i];
+            v.x *= m[it];
+            v.y *= m[it];
+            buf[i] = v;
         }
         __syncthreads();
-        for (int e = tid; e < L * lines; e += blockDim.x) {
-            const int ln = e % lines, k = e / lines;
-            const int rk = __brev((unsigned)k) >> (32 - logL);
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int e = threadIdx.x + 256 * it;
+            const int ln = e & (LINES - 1), k = e >> LOGLINES;
+            const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
             if (k < rk) {
-                const C2 t0 = buf[k * lines + ln];
-                buf[k * lines + ln] = buf[rk * lines + ln];
-                buf[rk * lines + ln] = t0;
+                const C2 t0 = buf[k * LINES + ln];
+                buf[k * LINES + ln] = buf[rk * LINES + ln];
+                buf[rk * LINES + ln] = t0;
             }
         }
         __syncthreads();
-        fft_stages<C2>(buf, L, logL, lines, true, tw);
+        fft_stages2<C2, LOGL, LOGLINES>(buf, tw, true);
     }
-    for (int e = tid; e < L * lines; e += blockDim.x) {
-        const int ln = e % lines, k = e / lines;
-        const int oo = ln / IC, cc = ln - oo * IC;
-        const int64_t o = o0 + oo, a = a0 + cc;
-        if (o < outer_cnt && a < nact) data[(o * L + k) * inner + column(a)] = buf[k * lines + ln];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int cc = e & (C - 1);
+        const int k = (e >> p.logC) & (L - 1);
+        const int oo = e >> (p.logC + LOGL);
+        const int64_t a = a0 + cc, o = o0 + oo;
+        if (a < p.A && o < p.O && (p.mode != 0 || in_band(k, p.N, L)))
+            data[ooff(o) + (int64_t)k * p.S + coff(a)] = buf[k * LINES + (oo << p.logC) + cc];
     }
 }
 
@@ -1542,48 +1625,126 @@ const float2 *tw_of<float>(const NfftPlan &P) { return P.tw32.p; }
 template <>
 const double2 *tw_of<double>(const NfftPlan &P) { return P.tw64.p; }
 
-// One FFT pass along axis `ax`; see k_fft for `mode` and `cols`.
-template <class T>
-static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, int ax, int mode,
-                     int cols, const T *M, hipStream_t s) {
-    const int L = P.nos;
-    int logL = 0;
-    while ((1 << logL) < L) ++logL;
-    const int nq = bg / 2;
-    int64_t inner = nq;
-    for (int t = 0; t < ax; ++t) inner *= P.nos;
-    int64_t outer = 1;
-    for (int t = ax + 1; t < P.d; ++t) outer *= P.nos;
-    int64_t nact = inner;
-    if (cols == 1) nact = (int64_t)(P.N + 1) * nq;
-    if (cols == 2) nact = (int64_t)(P.N + 1) * (P.N + 1) * nq;
-    // lines per workgroup: enough workgroups to fill the chip (>= ~2048),
-    // at most 4096 points of LDS per workgroup
-    const int64_t lines_total = nact * outer;
-    int maxlines = std::max(1, 4096 / L);
-    while (maxlines > 1 && lines_total / maxlines < 2048) maxlines >>= 1;
-    int IC = (int)std::min<int64_t>(nact, maxlines);
-    int LB = std::max(1, maxlines / IC);
-    if (LB > outer) LB = (int)outer;
-    const int threads = (int)std::min<int64_t>(256, std::max<int64_t>(64, (int64_t)IC * LB * L / 2));
-    const size_t lds = (size_t)L * IC * LB * sizeof(typename Cplx<T>::type);
-    const int64_t nblk = ((nact + IC - 1) / IC) * ((outer + LB - 1) / LB);
-    hipLaunchKernelGGL(k_fft<T>, dim3((unsigned)nblk), dim3(threads), lds, s, grid, L, logL, outer, inner,
-                       nact, IC, LB, mode, cols, P.N, nq, tw_of<T>(P), M);
+static int ilog2(int64_t v) {
+    int l = 0;
+    while (((int64_t)1 << l) < v) ++l;
+    return l;
+}
+
+// Lines per workgroup: 2^LOGLINES with L * LINES = 2048 complex values (at
+// most 64 lines).
+template <class T, int LOGL>
+static void fft_launch(FftPass p, typename Cplx<T>::type *grid, const typename Cplx<T>::type *tw,
+                       const T *M, hipStream_t s) {
+    constexpr int LOGLINES = 11 - LOGL > 6 ? 6 : 11 - LOGL;
+    const int logA = ilog2(p.A);
+    p.logC = std::min(logA, LOGLINES);
+    p.logOB = LOGLINES - p.logC;
+    p.nachunk = (p.A + ((int64_t)1 << p.logC) - 1) >> p.logC;
+    const int64_t nob = (p.O + ((int64_t)1 << p.logOB) - 1) >> p.logOB;
+    const int64_t nblk = p.nachunk * nob;
+    MLG_REQUIRE(nblk < ((int64_t)1 << 31), MLG_ERR_RANGE, "FFT grid too large");
+    hipLaunchKernelGGL((k_fft<T, LOGL, LOGLINES>), dim3((unsigned)nblk), dim3(256), 0, s, grid, p, tw, M);
     MLG_LAUNCH_CHECK();
 }
 
-// Forward FFT, multiplication by M and inverse FFT with band pruning: axes
-// below the last are transformed forward (later axes only on band columns),
-// the last axis does forward * M * inverse in one pass, and the inverse
-// passes read out-of-band entries as zero.
+// One FFT pass along axis `ax` of the nos^d x nq grid over every line above
+// the axis.  `band_lo` (second axis only): the columns below the axis are
+// restricted to the band of the first axis.
+template <class T>
+static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, int ax, int mode,
+                     bool band_lo, const T *M, hipStream_t s) {
+    const int L = P.nos;
+    const int nq = bg / 2;
+    FftPass p{};
+    p.lognq = ilog2(nq);
+    p.N = P.N;
+    p.mode = mode;
+    int64_t below = nq;                       // elements below the axis
+    for (int t = 0; t < ax; ++t) below *= L;
+    p.S = below;
+    p.ostr = below * L;
+    if (band_lo) {
+        // columns: band of axis ax-1 times the (whole) axes below it
+        p.A = (int64_t)(P.N + 1) * (below / L);
+        p.abnd = 1;
+        MLG_REQUIRE(ax == 1, MLG_ERR_ARG, "band columns only below the second axis");
+    } else {
+        p.A = below;
+        p.abnd = 0;
+    }
+    int64_t above = 1;
+    for (int t = ax + 1; t < P.d; ++t) above *= L;
+    p.O = above;
+    p.obnd = 0;
+    const auto *tw = tw_of<T>(P);
+    switch (ilog2(L)) {
+        case 4: fft_launch<T, 4>(p, grid, tw, M, s); break;
+        case 5: fft_launch<T, 5>(p, grid, tw, M, s); break;
+        case 6: fft_launch<T, 6>(p, grid, tw, M, s); break;
+        case 7: fft_launch<T, 7>(p, grid, tw, M, s); break;
+        case 8: fft_launch<T, 8>(p, grid, tw, M, s); break;
+        case 9: fft_launch<T, 9>(p, grid, tw, M, s); break;
+        default: throw Error(MLG_ERR_RANGE, "FFT length must be 16..512");
+    }
+}
+
+// The last axis of a 3-D grid: lines (band y, band x, q), forward * M *
+// inverse along z.
+template <class T>
+static void fft_pass_z(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, const T *M,
+                       hipStream_t s) {
+    const int L = P.nos;
+    const int nq = bg / 2;
+    FftPass p{};
+    p.lognq = ilog2(nq);
+    p.N = P.N;
+    p.mode = 2;
+    p.S = (int64_t)L * L * nq;
+    p.ostr = (int64_t)L * nq;
+    p.O = P.N + 1;
+    p.obnd = 1;
+    p.A = (int64_t)(P.N + 1) * nq;
+    p.abnd = 1;
+    const auto *tw = tw_of<T>(P);
+    switch (ilog2(L)) {
+        case 4: fft_launch<T, 4>(p, grid, tw, M, s); break;
+        case 5: fft_launch<T, 5>(p, grid, tw, M, s); break;
+        case 6: fft_launch<T, 6>(p, grid, tw, M, s); break;
+        case 7: fft_launch<T, 7>(p, grid, tw, M, s); break;
+        case 8: fft_launch<T, 8>(p, grid, tw, M, s); break;
+        case 9: fft_launch<T, 9>(p, grid, tw, M, s); break;
+        default: throw Error(MLG_ERR_RANGE, "FFT length must be 16..512");
+    }
+}
+
+// Forward FFT, multiplication by M and inverse FFT with band pruning.  The
+// grid is [z][y][x][q] (d = 3), [y][x][q] (d = 2) or [x][q] (d = 1).
+//   d = 1: x: forward * M * inverse.
+//   d = 2: x forward (all rows); y forward * M * inverse on the band x
+//          columns; x inverse (all rows, out-of-band x read as zero).
+//   d = 3: x forward (all); y forward on band x columns (all z); z forward *
+//          M * inverse on band x columns of band y rows; y inverse on band
+//          x columns; x inverse (all, out-of-band read as zero).
+// Only entries with every frequency inside the band are ever multiplied;
+// the out-of-band ones are never read again.
 template <class T>
 static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, const T *M,
                          hipStream_t s) {
     const int d = P.d;
-    for (int ax = 0; ax < d - 1; ++ax) fft_pass<T>(P, bg, grid, ax, 0, ax, nullptr, s);
-    fft_pass<T>(P, bg, grid, d - 1, 2, d - 1, M, s);
-    for (int ax = d - 2; ax >= 0; --ax) fft_pass<T>(P, bg, grid, ax, 1, ax, nullptr, s);
+    if (d == 1) {
+        fft_pass<T>(P, bg, grid, 0, 2, false, M, s);
+    } else if (d == 2) {
+        fft_pass<T>(P, bg, grid, 0, 0, false, nullptr, s);
+        fft_pass<T>(P, bg, grid, 1, 2, true, M, s);
+        fft_pass<T>(P, bg, grid, 0, 1, false, nullptr, s);
+    } else {
+        fft_pass<T>(P, bg, grid, 0, 0, false, nullptr, s);
+        fft_pass<T>(P, bg, grid, 1, 0, true, nullptr, s);
+        fft_pass_z<T>(P, bg, grid, M, s);
+        fft_pass<T>(P, bg, grid, 1, 1, true, nullptr, s);
+        fft_pass<T>(P, bg, grid, 0, 1, false, nullptr, s);
+    }
 }
 
 // Widest vector group (power of two <= min(bs, 16)) whose patch slots fit the
