@@ -2,7 +2,7 @@
 //
 // A matvec with the layer mean (Sec. 3, eq. for I - L_1) or one layer's
 // operator (Sec. 2) runs as
-//   scatter-in: z_t = D_t^-1/2 x for every layer, in the layer's sorted order
+//   scatter-in: z_t = D_t^-1/2 x for every layer, in node order
 //               and summation precision;
 //   per layer:  F_t = W~_t z_t (NFFT, Algorithm 1) or W_t z_t (direct);
 //   gather-out: y = coef sum_t D_t^-1/2 (F_t - K(0) z_t) in FP64 (y = x - that
@@ -81,7 +81,6 @@ static void ensure_ws(Graph &g, int bs) {
         const Layer &L = g.layers[t];
         io[t].Z = g.Zs.p + slice[t];
         io[t].F = g.Fs.p + slice[t];
-        io[t].invperm = L.sorted ? L.invperm.p : nullptr;
         io[t].dinv = L.dinv.p;
         io[t].K0 = L.kp.method == MLG_METHOD_NFFT ? 1.0 : 0.0;
         io[t].is64 = L.kp.precision == 64;
@@ -219,7 +218,6 @@ static void compute_degrees(Graph &g, Layer &L) {
     LayerIO io{};
     io.Z = Z.p;
     io.F = F.p;
-    io.invperm = L.sorted ? L.invperm.p : nullptr;
     io.dinv = nullptr;
     io.is64 = 1;
     DevBuf<LayerIO> dio(1);
@@ -271,9 +269,6 @@ static void build_layer(Graph &g, Layer &L, const double *pts, bool dev, bool de
     if (L.kp.method == MLG_METHOD_DIRECT) direct_coords(n, L.d, p, L.sigma, L.x64, L.x32, s);
     if (L.kp.method == MLG_METHOD_NFFT) {
         nfft_plan_layer(L, p, s);
-        L.sorted = 1;
-        L.invperm.alloc(n);
-        launch_invperm(n, L.nf.perm.p, L.invperm.p, s);
         int w = default_window(L);
         nfft_make_window(L, L.win, w, L.kp.precision, 1, s);
     }

@@ -67,15 +67,12 @@ struct Layer {
     NfftWindow win;          // matvec window
     DevBuf<double> deg;      // degrees, original order
     DevBuf<double> dinv;     // D^-1/2, original order
-    DevBuf<int> invperm;     // original index -> sorted position (NFFT layers)
-    int sorted = 0;          // 1 if the layer's points are kept in sorted order
 };
 
 // What the block entry/exit kernels need to know about one layer.
 struct LayerIO {
-    void *Z;                 // n x bs input of the summation (sorted order), float or double
-    const void *F;           // n x bs output of the summation
-    const int *invperm;      // null: identity
+    void *Z;                 // n x bs input of the summation (node order), float or double
+    const void *F;           // n x bs output of the summation (node order)
     const double *dinv;      // D^-1/2, original order
     double K0;               // self term removed after the summation (0 for direct)
     int is64;
@@ -91,7 +88,6 @@ void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, d
 void launch_fill_ones(int64_t n, double *Xr, hipStream_t s);
 void launch_check_degrees(int64_t n, const double *deg, double thresh, int *flag, hipStream_t s);
 void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s);
-void launch_invperm(int64_t n, const int *perm, int *inv, hipStream_t s);
 
 // ---- direct.hip ---------------------------------------------------------------
 // Scaled, centred coordinates of a direct layer (d x n SoA): x64 for the

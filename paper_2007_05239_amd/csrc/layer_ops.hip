@@ -1,7 +1,6 @@
 // Entry and exit of a block matvec, around each layer's summation:
-//   scatter-in   z_t = D_t^-1/2 x for every layer t, written in the layer's
-//                sorted point order and cast to its summation precision
-//                (Sec. 2, L_sym = I - D^-1/2 W D^-1/2);
+//   scatter-in   z_t = D_t^-1/2 x for every layer t, cast to its summation
+//                precision, in node order (Sec. 2, L_sym = I - D^-1/2 W D^-1/2);
 //   gather-out   y = coef sum_t D_t^-1/2 (F_t - K(0) z_t) in FP64, with the
 //                self term of W = W~ - K(0) I (Sec. 4) and the layer mean
 //                (1/T) sum_t (Sec. 3); y = x - that for L_sym / L_1.
@@ -68,13 +67,12 @@ __global__ __launch_bounds__(256) void k_scatter_in(int64_t n, int b, int bs,
         load_block_row(X, ldx, i, b, v0, vgw, x);
         for (int t = 0; t < nl; ++t) {
             const LayerIO d = L[t];
-            const int64_t p = d.invperm ? d.invperm[i] : i;
             const double di = use_dinv ? d.dinv[i] : 1.0;
             double z[kIoVG];
 #pragma unroll
             for (int j = 0; j < kIoVG; ++j) z[j] = use_dinv ? x[j] * di : x[j];
-            if (d.is64) store_row<double>(d.Z, p * bs + v0, z, vgw);
-            else store_row<float>(d.Z, p * bs + v0, z, vgw);
+            if (d.is64) store_row<double>(d.Z, i * bs + v0, z, vgw);
+            else store_row<float>(d.Z, i * bs + v0, z, vgw);
         }
     }
 }
@@ -94,11 +92,10 @@ __global__ __launch_bounds__(256) void k_gather_out(int64_t n, int b, int bs,
         for (int j = 0; j < kIoVG; ++j) acc[j] = 0.0;
         for (int t = 0; t < nl; ++t) {
             const LayerIO d = L[t];
-            const int64_t p = d.invperm ? d.invperm[i] : i;
             const double di = use_dinv ? d.dinv[i] : 1.0;
             double f[kIoVG];
-            if (d.is64) load_row<double>(d.F, p * bs + v0, f, vgw);
-            else load_row<float>(d.F, p * bs + v0, f, vgw);
+            if (d.is64) load_row<double>(d.F, i * bs + v0, f, vgw);
+            else load_row<float>(d.F, i * bs + v0, f, vgw);
 #pragma unroll
             for (int j = 0; j < kIoVG; ++j) {
                 if (j < vgw) {
@@ -139,12 +136,6 @@ __global__ void k_dinv(int64_t n, const double *deg, double *dinv) {
     if (i < n) dinv[i] = 1.0 / sqrt(deg[i]);
 }
 
-// inv[perm[p]] = p.
-__global__ void k_invperm(int64_t n, const int *perm, int *inv) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) inv[perm[p]] = (int)p;
-}
-
 static inline unsigned blocks_for(int64_t work, int threads) {
     return (unsigned)((work + threads - 1) / threads);
 }
@@ -182,9 +173,5 @@ void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s) {
     MLG_LAUNCH_CHECK();
 }
 
-void launch_invperm(int64_t n, const int *perm, int *inv, hipStream_t s) {
-    hipLaunchKernelGGL(k_invperm, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, perm, inv);
-    MLG_LAUNCH_CHECK();
-}
 
 }  // namespace mlg

@@ -18,10 +18,12 @@
 //                   (the real part of the sum over I_N).  psi^ is the window's
 //                   Fourier transform by Gauss-Legendre quadrature.
 //
-// Apply (per block of vectors z, stride bs, sorted order; no atomics):
-//   spread   one wavefront per task: lanes own the cells of the bin's patch
-//            (the union of its points' window footprints) and accumulate
-//            psi(u_p - k) z_p over the task's points in registers;
+// Apply (per block of vectors z, stride bs, in node order; the kernels walk
+// the points in bin order through the permutation; no atomics):
+//   spread   one wavefront per task: the bin's patch (the union of its
+//            points' window footprints) accumulates psi(u_p - k) z_p over the
+//            task's points (matrix cores for FP32 blocks of 16, registers
+//            otherwise);
 //   reduce   bins cut into several tasks: task patches summed in task order;
 //   gather   one thread per grid cell: sum over the bins whose patch covers
 //            the cell (bin order), via a dense bin table and a coarse
@@ -55,13 +57,22 @@ template <>
 __device__ inline double dexp<double>(double a) { return exp(a); }
 
 // Exponential-of-semicircle window in grid units, support |t| <= w/2:
-// psi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1)).
+// psi(t) = exp(beta (sqrt(1 - (2t/w)^2) - 1)).  The FP32 form uses the
+// hardware square root and base-2 exponential (about 1 ulp each): the
+// relative error of a weight stays near 1e-7, far below the FP32 gate.
 template <class T>
 __device__ inline T es_psi(T t, T two_over_w, T beta) {
     T z = t * two_over_w;
     T s = T(1) - z * z;
     s = s > T(0) ? s : T(0);
     return dexp<T>(beta * (sqrt(s) - T(1)));
+}
+template <>
+__device__ inline float es_psi<float>(float t, float two_over_w, float beta) {
+    const float z = t * two_over_w;
+    const float s = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+    const float bl = beta * 1.44269504088896341f;   // beta log2(e)
+    return __builtin_amdgcn_exp2f(fmaf(bl, __builtin_amdgcn_sqrtf(s), -bl));
 }
 
 struct KRParams {
@@ -346,6 +357,9 @@ __global__ void k_twiddles(int L, float2 *__restrict__ t32, double2 *__restrict_
 struct Geom {
     int d, nos, B, nb, w, P, PD, bs;
     int64_t n;
+    // sorted position -> original index: the vector blocks Zs / Fs are kept
+    // in the caller's node order, points in bin order
+    const int *perm;
 };
 
 // (cell, fractional offset) of point p along dimension t.
@@ -401,6 +415,45 @@ __device__ inline void store_vec(T *__restrict__ p, const T (&v)[V]) {
     } else {
 #pragma unroll
         for (int i = 0; i < V; ++i) p[i] = v[i];
+    }
+}
+
+// Grid layout: bg/2 complex planes of G cells each (plane-major); vector v
+// of cell c is component (v & 1) of complex entry (v >> 1) * G + c.  Every
+// plane is a contiguous nos^d array, so each FFT pass streams whole lines.
+template <class T>
+__device__ inline int64_t grid_index(int64_t G, int64_t cell, int v) {
+    return ((int64_t)(v >> 1) * G + cell) * 2 + (v & 1);
+}
+
+template <class T, int V>
+__device__ inline void grid_store(T *__restrict__ grid, int64_t G, int64_t cell, int v0, const T (&v)[V]) {
+    if constexpr (V == 1) {
+        grid[grid_index<T>(G, cell, v0)] = v[0];
+    } else {
+        using C2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            C2 c;
+            c.x = v[i];
+            c.y = v[i + 1];
+            *reinterpret_cast<C2 *>(grid + grid_index<T>(G, cell, v0 + i)) = c;
+        }
+    }
+}
+
+template <class T, int V>
+__device__ inline void grid_load(const T *__restrict__ grid, int64_t G, int64_t cell, int v0, T (&out)[V]) {
+    if constexpr (V == 1) {
+        out[0] = grid[grid_index<T>(G, cell, v0)];
+    } else {
+        using C2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            const C2 c = *reinterpret_cast<const C2 *>(grid + grid_index<T>(G, cell, v0 + i));
+            out[i] = c.x;
+            out[i + 1] = c.y;
+        }
     }
 }
 
@@ -461,7 +514,7 @@ __global__ __launch_bounds__(64) void k_spread(Geom g, const int4 *__restrict__ 
                 }
             }
             T zz[VPL];
-            load_vec<T, VPL>(Zs + p * bs + v0, zz);
+            load_vec<T, VPL>(Zs + (int64_t)g.perm[p] * bs + v0, zz);
 #pragma unroll
             for (int v = 0; v < VPL; ++v) zv[lane * VPL + v] = zz[v];
         }
@@ -594,9 +647,9 @@ __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
 #pragma unroll
                 for (int v = 0; v < VPL; ++v) acc[v] += h[u][v];
     }
-    store_vec<T, VPL>(grid + cell * bg + v0, acc);
+    grid_store<T, VPL>(grid, G, cell, v0, acc);
     if (bg > bs && blockIdx.y == 0)
-        for (int v = bs; v < bg; ++v) grid[cell * bg + v] = T(0);
+        for (int v = bs; v < bg; ++v) grid[grid_index<T>(G, cell, v)] = T(0);
 }
 
 // Gather: one thread per (grid cell, vector group): sum over the bins whose
@@ -658,9 +711,9 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, int SB, int nsb,
             }
         }
     }
-    store_vec<T, VPL>(grid + cell * bg + v0, acc);
+    grid_store<T, VPL>(grid, G, cell, v0, acc);
     if (bg > bs && blockIdx.y == 0)
-        for (int v = bs; v < bg; ++v) grid[cell * bg + v] = T(0);
+        for (int v = bs; v < bg; ++v) grid[grid_index<T>(G, cell, v)] = T(0);
 }
 
 // ------------------------------------------------------------------------------
@@ -711,6 +764,22 @@ __device__ inline void fetch_point(const int *__restrict__ c32, const float *__r
     }
 }
 
+// Window values of one point along one dimension at the patch cells
+// org + q, q = 0..P-1 (zero outside the point's w support cells, and for an
+// absent point).
+template <int P>
+__device__ inline void window_row(int cell, float frac, int org, int w, float two_over_w, float beta,
+                                  bool ok, float (&out)[P]) {
+    const int lo = cell - w / 2 + 1 - org;   // first support cell, relative to org
+    const float bi = (float)(cell - org);    // exact small integer
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        // (cell - (org + q)) + frac: exact integer part, one rounding
+        const float v = es_psi<float>((bi - (float)q) + frac, two_over_w, beta);
+        out[q] = (ok && q >= lo && q < lo + w) ? v : 0.0f;
+    }
+}
+
 // The record of one point: wx[P] | wy[P] | wz[P] | wyz[P*P] (D = 3), wx | wy
 // (D = 2) or wx (D = 1), then zeros; weights outside the point's footprint
 // (and all weights of an absent point) are zero.
@@ -720,15 +789,7 @@ __device__ inline void put_record(const PtIn<D> &pi, bool ok, const int org[3], 
     using S = MfShape<D, P>;
     float wv[D][P];
 #pragma unroll
-    for (int t = 0; t < D; ++t) {
-        const int s0 = pi.cell[t] - w / 2 + 1;
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const int k = org[t] + q;
-            const float val = es_psi<float>((float)(pi.cell[t] - k) + pi.frac[t], two_over_w, beta);
-            wv[t][q] = (ok && k >= s0 && k < s0 + w) ? val : 0.0f;
-        }
-    }
+    for (int t = 0; t < D; ++t) window_row<P>(pi.cell[t], pi.frac[t], org[t], w, two_over_w, beta, ok, wv[t]);
     float rec[S::WSP];
 #pragma unroll
     for (int t = 0; t < D; ++t)
@@ -801,9 +862,10 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
         const bool ok = lane < tk.z;
         const int64_t p = (int64_t)tk.y + lane;
         fetch_point<D>(c32, f32, g.n, p, ok, pin);
+        const int row = ok ? g.perm[p] : 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + p * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+            zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
@@ -817,9 +879,10 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
             const bool ok = lane < tk.z - c1;
             const int64_t p = (int64_t)tk.y + c1 + lane;
             fetch_point<D>(c32, f32, g.n, p, ok, pin);
+            const int row = ok ? g.perm[p] : 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + p * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+                zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
         for (int gi = 0; gi < 16; ++gi) {
@@ -854,7 +917,7 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
 template <int D, int P, int NQ>
 __device__ inline void interp_chunk(const float *__restrict__ wts, const int (&qa)[MfShape<D, P>::S4],
                                     const int (&qb)[MfShape<D, P>::S4], int li, int lk,
-                                    const float *hb, int cnt, int64_t first, int bs, int v0,
+                                    const float *hb, int cnt, const int *wperm, int bs, int v0,
                                     float *__restrict__ Fs) {
     using S = MfShape<D, P>;
     constexpr int WSP = S::WSP;
@@ -882,7 +945,7 @@ __device__ inline void interp_chunk(const float *__restrict__ wts, const int (&q
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int pt = 16 * q + 4 * lk + r;
-            if (pt < cnt) Fs[(first + pt) * bs + v0 + li] = acc[q][r];
+            if (pt < cnt) Fs[(int64_t)wperm[pt] * bs + v0 + li] = acc[q][r];
         }
 }
 
@@ -896,6 +959,9 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restri
     constexpr int WSP = S::WSP;
     constexpr int KSV = (S::PD + 3) / 4;
     __shared__ __attribute__((aligned(16))) float wts[64 * WSP];
+    int64_t G = g.nos;
+    if (D > 1) G *= g.nos;
+    if (D > 2) G *= g.nos;
     const int bs = g.bs;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
     const int4 tk = tasks[blockIdx.x];
@@ -904,8 +970,10 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restri
     task_origin<D>(g, (unsigned)tk.x, org);
     const float two_over_w = 2.0f / (float)g.w;
 
+    __shared__ int wperm[64];
     PtIn<D> pin;
     fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + lane, lane < tk.z, pin);
+    int prow = lane < tk.z ? g.perm[(int64_t)tk.y + lane] : 0;
     // B fragments: the task's patch of the grid, cell 4s + lk, vector li
     float hb[KSV];
 #pragma unroll
@@ -917,7 +985,7 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restri
             int64_t cell = org[0] + qx;
             if (D > 1) cell += (int64_t)(org[1] + qy) * g.nos;
             if (D > 2) cell += (int64_t)(org[2] + qz) * g.nos * g.nos;
-            h = grid[cell * bg + v0 + li];
+            h = grid[grid_index<float>(G, cell, v0 + li)];
         }
         hb[s] = h;
     }
@@ -932,17 +1000,242 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restri
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
-        const int64_t first = (int64_t)tk.y + c0;
         __syncthreads();
         put_record<D, P>(pin, lane < cnt, org, g.w, two_over_w, beta, wts + lane * WSP);
+        wperm[lane] = prow;
         __syncthreads();
         const int c1 = c0 + 64;
-        if (c1 < tk.z) fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
+        if (c1 < tk.z) {
+            fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
+            prow = lane < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + lane] : 0;
+        }
         const int nq = (cnt + 15) >> 4;
-        if (nq == 4) interp_chunk<D, P, 4>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
-        else if (nq == 3) interp_chunk<D, P, 3>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
-        else if (nq == 2) interp_chunk<D, P, 2>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
-        else interp_chunk<D, P, 1>(wts, qa, qb, li, lk, hb, cnt, first, bs, v0, Fs);
+        if (nq == 4) interp_chunk<D, P, 4>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
+        else if (nq == 3) interp_chunk<D, P, 3>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
+        else if (nq == 2) interp_chunk<D, P, 2>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
+        else interp_chunk<D, P, 1>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
+    }
+}
+
+// ------------------------------------------------------------------------------
+// d = 3 matrix-core variants built on the tensor structure of the window:
+// the weight of a point at patch cell (cx, cy, cz) is wxy[cx + P cy] wz[cz].
+//   spreading:      patch[(cx,cy), cz] = sum_p wxy_p[(cx,cy)] (wz_p[cz] z_p)
+//     one A fragment (16 (cx,cy) rows x 4 points) serves all P values of cz,
+//     B = wz_p[cz] z_p (one multiply per lane per cz);
+//   interpolation:  f_p = sum_cz wz_p[cz] sum_(cx,cy) wxy_p[(cx,cy)] H[(cx,cy), cz]
+//     one A fragment (16 points x 4 (cx,cy) cells) serves all P values of cz;
+//     the P partial sums are combined per point on the vector ALUs.
+// Per matrix instruction this needs a fraction of an LDS read instead of two
+// reads and a multiply.
+// ------------------------------------------------------------------------------
+template <int P>
+struct MfShape3 {
+    static constexpr int C2 = P * P;                 // (cx, cy) cells
+    static constexpr int T2 = (C2 + 15) / 16;        // 16-row tiles of (cx, cy)
+    // spreading record stride, = 16 mod 32 so that the four k slots of a
+    // wavefront read disjoint LDS banks
+    static constexpr int RS = (T2 % 2 == 1) ? 16 * T2 : 16 * T2 + 16;
+    static constexpr int KS2 = (C2 + 3) / 4;         // 4-cell steps of (cx, cy)
+    static constexpr int NE = 4 * KS2 + P;           // interpolation entries per point
+    static constexpr int ES = 80;                    // entry stride (64 points + 16)
+};
+
+// Window factors of one point: wx, wy, wz over the patch (zero outside the
+// footprint and for an absent point).
+template <int P>
+__device__ inline void window_factors(const PtIn<3> &pi, bool ok, const int org[3], int w,
+                                      float two_over_w, float beta, float (&wv)[3][P]) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t) window_row<P>(pi.cell[t], pi.frac[t], org[t], w, two_over_w, beta, ok, wv[t]);
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_spread_mfma3(Geom g, const int4 *__restrict__ tasks,
+                                                     const int *__restrict__ c32,
+                                                     const float *__restrict__ f32,
+                                                     const float *__restrict__ Zs, float beta,
+                                                     float *__restrict__ patch) {
+    using S = MfShape3<P>;
+    constexpr int T2 = S::T2, RS = S::RS, C2 = S::C2;
+    __shared__ __attribute__((aligned(16))) float wxy[64 * RS];
+    __shared__ __attribute__((aligned(16))) float wzs[64 * 8];
+    __shared__ __attribute__((aligned(16))) float zv[64 * 16];
+    const int bs = g.bs;
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int4 tk = tasks[blockIdx.x];
+    const int v0 = blockIdx.y * 16;
+    int org[3];
+    task_origin<3>(g, (unsigned)tk.x, org);
+    const float two_over_w = 2.0f / (float)g.w;
+    floatx4 acc[T2][P];
+#pragma unroll
+    for (int t = 0; t < T2; ++t)
+#pragma unroll
+        for (int cz = 0; cz < P; ++cz) acc[t][cz] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    PtIn<3> pin;
+    float4 zin[4];
+    {
+        const bool ok = lane < tk.z;
+        const int64_t p = (int64_t)tk.y + lane;
+        fetch_point<3>(c32, f32, g.n, p, ok, pin);
+        const int row = ok ? g.perm[p] : 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int c0 = 0; c0 < tk.z; c0 += 64) {
+        const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
+        __syncthreads();
+        {
+            float wv[3][P];
+            window_factors<P>(pin, lane < cnt, org, g.w, two_over_w, beta, wv);
+            float rec[RS];
+#pragma unroll
+            for (int e = 0; e < RS; ++e) rec[e] = 0.0f;
+#pragma unroll
+            for (int cy = 0; cy < P; ++cy)
+#pragma unroll
+                for (int cx = 0; cx < P; ++cx) rec[cx + P * cy] = wv[0][cx] * wv[1][cy];
+            float *wp = wxy + lane * RS;
+#pragma unroll
+            for (int e = 0; e < RS; e += 4)
+                *reinterpret_cast<float4 *>(wp + e) = make_float4(rec[e], rec[e + 1], rec[e + 2], rec[e + 3]);
+            float zr[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) zr[e] = e < P ? wv[2][e] : 0.0f;
+            *reinterpret_cast<float4 *>(wzs + lane * 8) = make_float4(zr[0], zr[1], zr[2], zr[3]);
+            *reinterpret_cast<float4 *>(wzs + lane * 8 + 4) = make_float4(zr[4], zr[5], zr[6], zr[7]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) *reinterpret_cast<float4 *>(zv + lane * 16 + 4 * j) = zin[j];
+        __syncthreads();
+        const int c1 = c0 + 64;
+        if (c1 < tk.z) {   // prefetch the next chunk while this one is multiplied
+            const bool ok = lane < tk.z - c1;
+            const int64_t p = (int64_t)tk.y + c1 + lane;
+            fetch_point<3>(c32, f32, g.n, p, ok, pin);
+            const int row = ok ? g.perm[p] : 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int gi = 0; gi < 16; ++gi) {
+            if (4 * gi < cnt) {
+                const int pp = 4 * gi + lk;
+                const float z = zv[pp * 16 + li];
+                float a[T2];
+#pragma unroll
+                for (int t = 0; t < T2; ++t) a[t] = wxy[pp * RS + 16 * t + li];
+                const float4 wz0 = *reinterpret_cast<const float4 *>(wzs + pp * 8);
+                const float4 wz1 = *reinterpret_cast<const float4 *>(wzs + pp * 8 + 4);
+                const float wz[8] = {wz0.x, wz0.y, wz0.z, wz0.w, wz1.x, wz1.y, wz1.z, wz1.w};
+#pragma unroll
+                for (int cz = 0; cz < P; ++cz) {
+                    const float b = z * wz[cz];
+#pragma unroll
+                    for (int t = 0; t < T2; ++t)
+                        acc[t][cz] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b, acc[t][cz], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *out = patch + (int64_t)tk.w * (C2 * P) * bs + v0 + li;
+#pragma unroll
+    for (int t = 0; t < T2; ++t)
+#pragma unroll
+        for (int cz = 0; cz < P; ++cz)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int cxy = 16 * t + 4 * lk + r;
+                if (cxy < C2) out[(int64_t)(cxy + C2 * cz) * bs] = acc[t][cz][r];
+            }
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_interp_mfma3(Geom g, const int4 *__restrict__ tasks,
+                                                     const int *__restrict__ c32,
+                                                     const float *__restrict__ f32,
+                                                     const float *__restrict__ grid, int bg,
+                                                     float beta, float *__restrict__ Fs) {
+    using S = MfShape3<P>;
+    constexpr int KS2 = S::KS2, ES = S::ES, NE = S::NE, C2 = S::C2;
+    // entry-major weights: entry e of point p at wt[e * ES + p]; entries
+    // 0..4 KS2-1: wxy (zero past C2), then wz[0..P-1]
+    __shared__ __attribute__((aligned(16))) float wt[NE * ES];
+    const int64_t G = (int64_t)g.nos * g.nos * g.nos;
+    const int bs = g.bs;
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int4 tk = tasks[blockIdx.x];
+    const int v0 = blockIdx.y * 16;
+    int org[3];
+    task_origin<3>(g, (unsigned)tk.x, org);
+    const float two_over_w = 2.0f / (float)g.w;
+
+    __shared__ int wperm[64];
+    PtIn<3> pin;
+    fetch_point<3>(c32, f32, g.n, (int64_t)tk.y + lane, lane < tk.z, pin);
+    int prow = lane < tk.z ? g.perm[(int64_t)tk.y + lane] : 0;
+    // B fragments: grid at (cx, cy) = 4s + lk, cz, vector li
+    float hb[P][KS2];
+#pragma unroll
+    for (int cz = 0; cz < P; ++cz)
+#pragma unroll
+        for (int s = 0; s < KS2; ++s) {
+            const int cxy = 4 * s + lk;
+            float h = 0.0f;
+            if (cxy < C2) {
+                const int64_t cell = (int64_t)(org[0] + cxy % P) +
+                                     (int64_t)(org[1] + cxy / P) * g.nos +
+                                     (int64_t)(org[2] + cz) * g.nos * g.nos;
+                h = grid[grid_index<float>(G, cell, v0 + li)];
+            }
+            hb[cz][s] = h;
+        }
+    for (int c0 = 0; c0 < tk.z; c0 += 64) {
+        const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
+        __syncthreads();
+        {
+            float wv[3][P];
+            window_factors<P>(pin, lane < cnt, org, g.w, two_over_w, beta, wv);
+#pragma unroll
+            for (int e = 0; e < 4 * KS2; ++e) {
+                const float v = e < C2 ? wv[0][e % P] * wv[1][e / P] : 0.0f;
+                wt[e * ES + lane] = v;
+            }
+#pragma unroll
+            for (int cz = 0; cz < P; ++cz) wt[(4 * KS2 + cz) * ES + lane] = wv[2][cz];
+        }
+        wperm[lane] = prow;
+        __syncthreads();
+        const int c1 = c0 + 64;
+        if (c1 < tk.z) {
+            fetch_point<3>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
+            prow = lane < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + lane] : 0;
+        }
+        const int nq = (cnt + 15) >> 4;
+        for (int q = 0; q < nq; ++q) {
+            floatx4 gz[P];
+#pragma unroll
+            for (int cz = 0; cz < P; ++cz) gz[cz] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS2; ++s) {
+                const float a = wt[(4 * s + lk) * ES + 16 * q + li];
+#pragma unroll
+                for (int cz = 0; cz < P; ++cz)
+                    gz[cz] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hb[cz][s], gz[cz], 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pt = 16 * q + 4 * lk + r;
+                float f = 0.0f;
+#pragma unroll
+                for (int cz = 0; cz < P; ++cz) f += wt[(4 * KS2 + cz) * ES + pt] * gz[cz][r];
+                if (pt < cnt) Fs[(int64_t)wperm[pt] * bs + v0 + li] = f;
+            }
+        }
     }
 }
 
@@ -995,25 +1288,26 @@ struct Cplx<float> { using type = float2; };
 template <>
 struct Cplx<double> { using type = double2; };
 
-// Batched radix-2 FFT of length L = 2^LOGL along one axis of the
-// [.. axes ..][q] complex grid (q = vector pair, innermost).  A line is
-// addressed as  off(o) + k S + coff(a),  k = 0..L-1 along the axis, with
-//   a in [0, A): the columns below the axis (contiguous in memory, or the
-//                band columns of the next-lower axis: abnd = 1);
-//   o in [0, O): the lines above the axis (plain stride ostr, or the band
-//                rows of the next-higher axis: obnd = 1).
+// Batched radix-2 FFT of length L = 2^LOGL along one axis of each complex
+// plane of the grid (plane-major layout: plane q = blockIdx.y, qstr complex
+// entries apart; inside a plane the cells are [z][y][x], x contiguous).  A
+// line is addressed as  off(o) + k S + coff(a),  k = 0..L-1 along the axis:
+//   a in [0, A): the columns below the axis (contiguous), or the band
+//                columns of the x axis (abnd = 1);
+//   o in [0, O): the lines above the axis (stride ostr), or the band rows of
+//                the y axis (obnd = 1).
 // Band mapping: index i of the N + 1 band frequencies -> grid index i
 // (i <= N/2) or L - (N + 1) + i.  Only frequency lines that can reach the
 // band |l_t| <= N/2 are touched, which prunes the later axes.
 // mode 0: forward, only the band entries along the axis are stored (the
 // others are never read again); mode 1: inverse, entries whose k is outside
 // the band read as zero (they were never multiplied); mode 2: forward, times
-// the multiplier M (indexed by grid cell = element offset / nq), inverse: the
-// last axis of Algorithm 1 in one pass.
+// the multiplier M (indexed by the in-plane cell), inverse: the last axis of
+// Algorithm 1 in one pass.
 // A workgroup takes OB consecutive o and C consecutive a (OB * C = LINES
-// lines); loads and stores walk memory order (a fastest, then k, then o), the
-// LDS buffer holds buf[k][line] with the line fastest, so both the global
-// side and the butterflies are conflict-free.
+// lines); loads and stores walk memory order (a fastest, then k, then o).
+// The LDS buffer holds buf[k][line] with a padded row (LINES + 1) so that
+// both the load pattern and the butterflies are free of bank conflicts.
 __device__ inline int band_index(int i, int N, int nos) { return i <= N / 2 ? i : nos - (N + 1) + i; }
 
 __device__ inline bool in_band(int k, int N, int nos) { return k <= N / 2 || k >= nos - N / 2; }
@@ -1022,29 +1316,30 @@ struct FftPass {
     int64_t O, A;        // lines: O outer x A columns
     int64_t S;           // element stride along the axis
     int64_t ostr;        // element stride of o (before band mapping)
+    int64_t qstr;        // complex entries per plane
     int obnd, abnd;      // band-mapped o / a
-    int lognq;           // log2 of complex lanes per cell
     int N;               // bandwidth
     int mode;
     int logC, logOB;     // workgroup tile: C = 2^logC columns, OB = 2^logOB outers
     int64_t nachunk;     // ceil(A / C)
 };
 
-template <class C2, int LOGL, int LOGLINES>
-__device__ inline void fft_stages2(C2 *buf, const C2 *tw, bool inverse) {
-    constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES;
+template <class C2, int LOGL, int LDL>
+__device__ inline void fft_stages2(C2 *buf, const C2 *tw, bool inverse, int lines_log) {
+    constexpr int L = 1 << LOGL;
+    const int LINES = 1 << lines_log;
 #pragma unroll
     for (int s = 0; s < LOGL; ++s) {
         const int half = 1 << s;
 #pragma unroll
-        for (int it = 0; it < (L / 2) * LINES / 256; ++it) {
+        for (int it = 0; it < (L / 2) * (LDL - 1) / 256; ++it) {
             const int e = threadIdx.x + 256 * it;
-            const int ln = e & (LINES - 1), bf = e >> LOGLINES;
+            const int ln = e & (LINES - 1), bf = e >> lines_log;
             const int grp = bf >> s, pos = bf & (half - 1);
             const int i0 = (grp << (s + 1)) + pos, i1 = i0 + half;
             C2 w = tw[pos << (LOGL - 1 - s)];
             if (inverse) w.y = -w.y;
-            const C2 a = buf[i0 * LINES + ln], b = buf[i1 * LINES + ln];
+            const C2 a = buf[i0 * LDL + ln], b = buf[i1 * LDL + ln];
             C2 bw, r0, r1;
             bw.x = b.x * w.x - b.y * w.y;
             bw.y = b.x * w.y + b.y * w.x;
@@ -1052,8 +1347,8 @@ __device__ inline void fft_stages2(C2 *buf, const C2 *tw, bool inverse) {
             r0.y = a.y + bw.y;
             r1.x = a.x - bw.x;
             r1.y = a.y - bw.y;
-            buf[i0 * LINES + ln] = r0;
-            buf[i1 * LINES + ln] = r1;
+            buf[i0 * LDL + ln] = r0;
+            buf[i1 * LDL + ln] = r1;
         }
         __syncthreads();
     }
@@ -1064,20 +1359,16 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
                                              const typename Cplx<T>::type *__restrict__ twg,
                                              const T *__restrict__ M) {
     using C2 = typename Cplx<T>::type;
-    constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES;
-    __shared__ C2 buf[L * LINES];
+    constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES, LDL = LINES + 1;
+    __shared__ C2 buf[L * LDL];
     __shared__ C2 tw[L / 2];
     for (int j = threadIdx.x; j < L / 2; j += blockDim.x) tw[j] = twg[j];
+    data += (int64_t)blockIdx.y * p.qstr;
     const int C = 1 << p.logC;
     const int64_t a0 = ((int64_t)blockIdx.x % p.nachunk) << p.logC;
     const int64_t o0 = ((int64_t)blockIdx.x / p.nachunk) << p.logOB;
-    const int64_t nq1 = ((int64_t)1 << p.lognq) - 1;
-    // element offset of column a / outer o
-    auto coff = [&](int64_t a) -> int64_t {
-        if (!p.abnd) return a;
-        const int r = (int)(a >> p.lognq);
-        return ((int64_t)band_index(r, p.N, L) << p.lognq) + (a & nq1);
-    };
+    // in-plane offset of column a / outer o
+    auto coff = [&](int64_t a) -> int64_t { return p.abnd ? (int64_t)band_index((int)a, p.N, L) : a; };
     auto ooff = [&](int64_t o) -> int64_t {
         return (p.obnd ? (int64_t)band_index((int)o, p.N, L) : o) * p.ostr;
     };
@@ -1103,10 +1394,10 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
         const int k = (e >> p.logC) & (L - 1);
         const int oo = e >> (p.logC + LOGL);
         const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
-        buf[rk * LINES + (oo << p.logC) + cc] = val[it];
+        buf[rk * LDL + (oo << p.logC) + cc] = val[it];
     }
     __syncthreads();
-    fft_stages2<C2, LOGL, LOGLINES>(buf, tw, p.mode == 1);
+    fft_stages2<C2, LOGL, LDL>(buf, tw, p.mode == 1, LOGLINES);
     if (p.mode == 2) {
         T m[PER];
 #pragma unroll
@@ -1117,7 +1408,7 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
             const int oo = e >> (p.logC + LOGL);
             const int64_t a = a0 + cc, o = o0 + oo;
             m[it] = T(0);
-            if (a < p.A && o < p.O) m[it] = M[(ooff(o) + (int64_t)k * p.S + coff(a)) >> p.lognq];
+            if (a < p.A && o < p.O) m[it] = M[ooff(o) + (int64_t)k * p.S + coff(a)];
         }
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
@@ -1125,7 +1416,7 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
             const int cc = e & (C - 1);
             const int k = (e >> p.logC) & (L - 1);
             const int oo = e >> (p.logC + LOGL);
-            const int i = k * LINES + (oo << p.logC) + cc;
+            const int i = k * LDL + (oo << p.logC) + cc;
             C2 v = buf[i];
             v.x *= m[it];
             v.y *= m[it];
@@ -1138,13 +1429,13 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
             const int ln = e & (LINES - 1), k = e >> LOGLINES;
             const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
             if (k < rk) {
-                const C2 t0 = buf[k * LINES + ln];
-                buf[k * LINES + ln] = buf[rk * LINES + ln];
-                buf[rk * LINES + ln] = t0;
+                const C2 t0 = buf[k * LDL + ln];
+                buf[k * LDL + ln] = buf[rk * LDL + ln];
+                buf[rk * LDL + ln] = t0;
             }
         }
         __syncthreads();
-        fft_stages2<C2, LOGL, LOGLINES>(buf, tw, true);
+        fft_stages2<C2, LOGL, LDL>(buf, tw, true, LOGLINES);
     }
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
@@ -1154,10 +1445,9 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
         const int oo = e >> (p.logC + LOGL);
         const int64_t a = a0 + cc, o = o0 + oo;
         if (a < p.A && o < p.O && (p.mode != 0 || in_band(k, p.N, L)))
-            data[ooff(o) + (int64_t)k * p.S + coff(a)] = buf[k * LINES + (oo << p.logC) + cc];
+            data[ooff(o) + (int64_t)k * p.S + coff(a)] = buf[k * LDL + (oo << p.logC) + cc];
     }
 }
-
 
 // Interpolation: one thread per (point, vector group); window weights in
 // registers, the footprint read from the grid.
@@ -1172,6 +1462,9 @@ __global__ __launch_bounds__(256) void k_interp(Geom g, const double *__restrict
     const int v0 = blockIdx.y * VPL;
     const int w = g.w;
     const T two_over_w = T(2) / (T)w;
+    int64_t G = g.nos;
+    if (D > 1) G *= g.nos;
+    if (D > 2) G *= g.nos;
     // innermost dimension's weights in registers (compile-time indices);
     // the outer dimensions' weights are evaluated in their loops
     T phi0[16];
@@ -1199,20 +1492,19 @@ __global__ __launch_bounds__(256) void k_interp(Geom g, const double *__restrict
                 base += (int64_t)g.nos * (s0[1] + k1);
             }
             if (D > 2) base += (int64_t)g.nos * g.nos * (s0[2] + k2);
-            const T *row = grid + base * bg + v0;
 #pragma unroll
             for (int k0 = 0; k0 < 16; ++k0) {
                 if (k0 < w) {
                     const T wgt = wyz * phi0[k0];
                     T h[VPL];
-                    load_vec<T, VPL>(row + (int64_t)k0 * bg, h);
+                    grid_load<T, VPL>(grid, G, base + k0, v0, h);
 #pragma unroll
                     for (int v = 0; v < VPL; ++v) acc[v] += wgt * h[v];
                 }
             }
         }
     }
-    store_vec<T, VPL>(Fs + p * g.bs + v0, acc);
+    store_vec<T, VPL>(Fs + (int64_t)g.perm[p] * g.bs + v0, acc);
 }
 
 // ------------------------------------------------------------------------------
@@ -1634,8 +1926,8 @@ static int ilog2(int64_t v) {
 // Lines per workgroup: 2^LOGLINES with L * LINES = 2048 complex values (at
 // most 64 lines).
 template <class T, int LOGL>
-static void fft_launch(FftPass p, typename Cplx<T>::type *grid, const typename Cplx<T>::type *tw,
-                       const T *M, hipStream_t s) {
+static void fft_launch(FftPass p, int nq, typename Cplx<T>::type *grid,
+                       const typename Cplx<T>::type *tw, const T *M, hipStream_t s) {
     constexpr int LOGLINES = 11 - LOGL > 6 ? 6 : 11 - LOGL;
     const int logA = ilog2(p.A);
     p.logC = std::min(logA, LOGLINES);
@@ -1643,83 +1935,66 @@ static void fft_launch(FftPass p, typename Cplx<T>::type *grid, const typename C
     p.nachunk = (p.A + ((int64_t)1 << p.logC) - 1) >> p.logC;
     const int64_t nob = (p.O + ((int64_t)1 << p.logOB) - 1) >> p.logOB;
     const int64_t nblk = p.nachunk * nob;
-    MLG_REQUIRE(nblk < ((int64_t)1 << 31), MLG_ERR_RANGE, "FFT grid too large");
-    hipLaunchKernelGGL((k_fft<T, LOGL, LOGLINES>), dim3((unsigned)nblk), dim3(256), 0, s, grid, p, tw, M);
+    MLG_REQUIRE(nblk < ((int64_t)1 << 31) && nq <= 65535, MLG_ERR_RANGE, "FFT grid too large");
+    hipLaunchKernelGGL((k_fft<T, LOGL, LOGLINES>), dim3((unsigned)nblk, nq), dim3(256), 0, s, grid, p, tw, M);
     MLG_LAUNCH_CHECK();
 }
 
-// One FFT pass along axis `ax` of the nos^d x nq grid over every line above
-// the axis.  `band_lo` (second axis only): the columns below the axis are
-// restricted to the band of the first axis.
+template <class T>
+static void fft_dispatch(const NfftPlan &P, const FftPass &p, int nq, typename Cplx<T>::type *grid,
+                         const T *M, hipStream_t s) {
+    const auto *tw = tw_of<T>(P);
+    switch (ilog2(P.nos)) {
+        case 4: fft_launch<T, 4>(p, nq, grid, tw, M, s); break;
+        case 5: fft_launch<T, 5>(p, nq, grid, tw, M, s); break;
+        case 6: fft_launch<T, 6>(p, nq, grid, tw, M, s); break;
+        case 7: fft_launch<T, 7>(p, nq, grid, tw, M, s); break;
+        case 8: fft_launch<T, 8>(p, nq, grid, tw, M, s); break;
+        case 9: fft_launch<T, 9>(p, nq, grid, tw, M, s); break;
+        default: throw Error(MLG_ERR_RANGE, "FFT length must be 16..512");
+    }
+}
+
+// One FFT pass along axis `ax` of every plane of the grid.
+//   x (ax = 0): lines of L contiguous entries, every line of the plane;
+//   y (ax = 1): the band x columns of every z slab;
+//   z (ax = 2): the band x columns of the band y rows.
 template <class T>
 static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, int ax, int mode,
-                     bool band_lo, const T *M, hipStream_t s) {
-    const int L = P.nos;
-    const int nq = bg / 2;
+                     const T *M, hipStream_t s) {
+    const int64_t L = P.nos;
     FftPass p{};
-    p.lognq = ilog2(nq);
     p.N = P.N;
     p.mode = mode;
-    int64_t below = nq;                       // elements below the axis
-    for (int t = 0; t < ax; ++t) below *= L;
-    p.S = below;
-    p.ostr = below * L;
-    if (band_lo) {
-        // columns: band of axis ax-1 times the (whole) axes below it
-        p.A = (int64_t)(P.N + 1) * (below / L);
-        p.abnd = 1;
-        MLG_REQUIRE(ax == 1, MLG_ERR_ARG, "band columns only below the second axis");
-    } else {
-        p.A = below;
+    p.qstr = 1;
+    for (int t = 0; t < P.d; ++t) p.qstr *= L;
+    if (ax == 0) {
+        p.S = 1;
+        p.A = 1;
         p.abnd = 0;
+        p.O = p.qstr / L;
+        p.ostr = L;
+        p.obnd = 0;
+    } else if (ax == 1) {
+        p.S = L;
+        p.A = P.N + 1;
+        p.abnd = 1;
+        p.O = p.qstr / (L * L);
+        p.ostr = L * L;
+        p.obnd = 0;
+    } else {
+        p.S = L * L;
+        p.A = P.N + 1;
+        p.abnd = 1;
+        p.O = P.N + 1;
+        p.ostr = L;
+        p.obnd = 1;
     }
-    int64_t above = 1;
-    for (int t = ax + 1; t < P.d; ++t) above *= L;
-    p.O = above;
-    p.obnd = 0;
-    const auto *tw = tw_of<T>(P);
-    switch (ilog2(L)) {
-        case 4: fft_launch<T, 4>(p, grid, tw, M, s); break;
-        case 5: fft_launch<T, 5>(p, grid, tw, M, s); break;
-        case 6: fft_launch<T, 6>(p, grid, tw, M, s); break;
-        case 7: fft_launch<T, 7>(p, grid, tw, M, s); break;
-        case 8: fft_launch<T, 8>(p, grid, tw, M, s); break;
-        case 9: fft_launch<T, 9>(p, grid, tw, M, s); break;
-        default: throw Error(MLG_ERR_RANGE, "FFT length must be 16..512");
-    }
+    fft_dispatch<T>(P, p, bg / 2, grid, M, s);
 }
 
-// The last axis of a 3-D grid: lines (band y, band x, q), forward * M *
-// inverse along z.
-template <class T>
-static void fft_pass_z(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, const T *M,
-                       hipStream_t s) {
-    const int L = P.nos;
-    const int nq = bg / 2;
-    FftPass p{};
-    p.lognq = ilog2(nq);
-    p.N = P.N;
-    p.mode = 2;
-    p.S = (int64_t)L * L * nq;
-    p.ostr = (int64_t)L * nq;
-    p.O = P.N + 1;
-    p.obnd = 1;
-    p.A = (int64_t)(P.N + 1) * nq;
-    p.abnd = 1;
-    const auto *tw = tw_of<T>(P);
-    switch (ilog2(L)) {
-        case 4: fft_launch<T, 4>(p, grid, tw, M, s); break;
-        case 5: fft_launch<T, 5>(p, grid, tw, M, s); break;
-        case 6: fft_launch<T, 6>(p, grid, tw, M, s); break;
-        case 7: fft_launch<T, 7>(p, grid, tw, M, s); break;
-        case 8: fft_launch<T, 8>(p, grid, tw, M, s); break;
-        case 9: fft_launch<T, 9>(p, grid, tw, M, s); break;
-        default: throw Error(MLG_ERR_RANGE, "FFT length must be 16..512");
-    }
-}
-
-// Forward FFT, multiplication by M and inverse FFT with band pruning.  The
-// grid is [z][y][x][q] (d = 3), [y][x][q] (d = 2) or [x][q] (d = 1).
+// Forward FFT, multiplication by M and inverse FFT with band pruning, plane
+// by plane:
 //   d = 1: x: forward * M * inverse.
 //   d = 2: x forward (all rows); y forward * M * inverse on the band x
 //          columns; x inverse (all rows, out-of-band x read as zero).
@@ -1733,17 +2008,17 @@ static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid
                          hipStream_t s) {
     const int d = P.d;
     if (d == 1) {
-        fft_pass<T>(P, bg, grid, 0, 2, false, M, s);
+        fft_pass<T>(P, bg, grid, 0, 2, M, s);
     } else if (d == 2) {
-        fft_pass<T>(P, bg, grid, 0, 0, false, nullptr, s);
-        fft_pass<T>(P, bg, grid, 1, 2, true, M, s);
-        fft_pass<T>(P, bg, grid, 0, 1, false, nullptr, s);
+        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s);
+        fft_pass<T>(P, bg, grid, 1, 2, M, s);
+        fft_pass<T>(P, bg, grid, 0, 1, nullptr, s);
     } else {
-        fft_pass<T>(P, bg, grid, 0, 0, false, nullptr, s);
-        fft_pass<T>(P, bg, grid, 1, 0, true, nullptr, s);
-        fft_pass_z<T>(P, bg, grid, M, s);
-        fft_pass<T>(P, bg, grid, 1, 1, true, nullptr, s);
-        fft_pass<T>(P, bg, grid, 0, 1, false, nullptr, s);
+        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s);
+        fft_pass<T>(P, bg, grid, 1, 0, nullptr, s);
+        fft_pass<T>(P, bg, grid, 2, 2, M, s);
+        fft_pass<T>(P, bg, grid, 1, 1, nullptr, s);
+        fft_pass<T>(P, bg, grid, 0, 1, nullptr, s);
     }
 }
 
@@ -1814,6 +2089,7 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     g.PD = patch_cells(P, W);
     g.bs = bs;
     g.n = P.n;
+    g.perm = P.perm.p;
     MLG_REQUIRE(bs >= 1 && bs <= 64 && is_pow2(bs), MLG_ERR_ARG, "block stride must be a power of two <= 64");
     const int vs = spread_vpl(g.PD, bs);
     MLG_REQUIRE(ceil_div(g.PD, 64) * vs <= 64, MLG_ERR_RANGE,
@@ -1827,8 +2103,12 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
         if constexpr (std::is_same<T, float>::value) {
             if (mf) {
 #define SPREADM_CALL(DD, PP)                                                                      \
-    hipLaunchKernelGGL((k_spread_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
-                       P.c32.p, P.f32.p, Zs, beta, patch)
+    if constexpr (DD == 3)                                                                        \
+        hipLaunchKernelGGL((k_spread_mfma3<PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
+                           P.c32.p, P.f32.p, Zs, beta, patch);                                   \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_spread_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
+                           P.c32.p, P.f32.p, Zs, beta, patch)
                 MLG_P_SWITCH(D, g.P, SPREADM_CALL)
 #undef SPREADM_CALL
                 MLG_LAUNCH_CHECK();
@@ -1874,8 +2154,12 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     if constexpr (std::is_same<T, float>::value) {
         if (mf && P.ntasks > 0) {
 #define INTERPM_CALL(DD, PP)                                                                      \
-    hipLaunchKernelGGL((k_interp_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
-                       P.c32.p, P.f32.p, grid, bg, beta, Fs)
+    if constexpr (DD == 3)                                                                        \
+        hipLaunchKernelGGL((k_interp_mfma3<PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
+                           P.c32.p, P.f32.p, grid, bg, beta, Fs);                                \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_interp_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
+                           P.c32.p, P.f32.p, grid, bg, beta, Fs)
             MLG_P_SWITCH(D, g.P, INTERPM_CALL)
 #undef INTERPM_CALL
             MLG_LAUNCH_CHECK();
