@@ -858,6 +858,9 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
 
     PtIn<D> pin;
     float4 zin[4];
+    // node rows of the points run one chunk ahead of their coordinates, so
+    // no load waits on another inside the loop
+    int rown;
     {
         const bool ok = lane < tk.z;
         const int64_t p = (int64_t)tk.y + lane;
@@ -866,6 +869,7 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        rown = lane + 64 < tk.z ? g.perm[(int64_t)tk.y + 64 + lane] : 0;
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
@@ -879,14 +883,15 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
             const bool ok = lane < tk.z - c1;
             const int64_t p = (int64_t)tk.y + c1 + lane;
             fetch_point<D>(c32, f32, g.n, p, ok, pin);
-            const int row = ok ? g.perm[p] : 0;
+            const int row = rown;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+            rown = lane + 64 < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
         }
 #pragma unroll
         for (int gi = 0; gi < 16; ++gi) {
-            if (4 * gi < cnt) {
+            {
                 const float b = zv[(4 * gi + lk) * 16 + li];
                 float a[NT];
 #pragma unroll
@@ -1009,11 +1014,7 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restri
             fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
             prow = lane < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + lane] : 0;
         }
-        const int nq = (cnt + 15) >> 4;
-        if (nq == 4) interp_chunk<D, P, 4>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
-        else if (nq == 3) interp_chunk<D, P, 3>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
-        else if (nq == 2) interp_chunk<D, P, 2>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
-        else interp_chunk<D, P, 1>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
+        interp_chunk<D, P, 4>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
     }
 }
 
@@ -1050,14 +1051,28 @@ __device__ inline void window_factors(const PtIn<3> &pi, bool ok, const int org[
     for (int t = 0; t < 3; ++t) window_row<P>(pi.cell[t], pi.frac[t], org[t], w, two_over_w, beta, ok, wv[t]);
 }
 
+// Spreading tiles: TF full tiles of 16 (cx, cy) rows serve every cz with
+// B = wz[cz] z; the RR = C2 mod 16 remaining (cx, cy) cells are packed with
+// cz into TR mixed tiles, rows (r, cz) -> A = wxy[16 TF + r] wz[cz], B = z.
 template <int P>
-__global__ __launch_bounds__(64) void k_spread_mfma3(Geom g, const int4 *__restrict__ tasks,
+struct SpreadTiles3 {
+    static constexpr int C2 = P * P;
+    static constexpr int TF = C2 / 16;
+    static constexpr int RR = C2 % 16;
+    static constexpr int TR = (RR * P + 15) / 16;
+};
+
+// Two wavefronts per SIMD keep one wave's matrix work running while the
+// other stages its records; the register budget is capped to allow that.
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_spread_mfma3(Geom g, const int4 *__restrict__ tasks,
                                                      const int *__restrict__ c32,
                                                      const float *__restrict__ f32,
                                                      const float *__restrict__ Zs, float beta,
                                                      float *__restrict__ patch) {
     using S = MfShape3<P>;
-    constexpr int T2 = S::T2, RS = S::RS, C2 = S::C2;
+    using U = SpreadTiles3<P>;
+    constexpr int RS = S::RS, C2 = S::C2, TF = U::TF, RR = U::RR, TR = U::TR;
     __shared__ __attribute__((aligned(16))) float wxy[64 * RS];
     __shared__ __attribute__((aligned(16))) float wzs[64 * 8];
     __shared__ __attribute__((aligned(16))) float zv[64 * 16];
@@ -1068,14 +1083,30 @@ __global__ __launch_bounds__(64) void k_spread_mfma3(Geom g, const int4 *__restr
     int org[3];
     task_origin<3>(g, (unsigned)tk.x, org);
     const float two_over_w = 2.0f / (float)g.w;
-    floatx4 acc[T2][P];
+    floatx4 acc[TF > 0 ? TF : 1][P];
+    floatx4 accr[TR > 0 ? TR : 1];
 #pragma unroll
-    for (int t = 0; t < T2; ++t)
+    for (int t = 0; t < TF; ++t)
 #pragma unroll
         for (int cz = 0; cz < P; ++cz) acc[t][cz] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < TR; ++u) accr[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // mixed-tile row of this lane: (cx, cy) cell 16 TF + r, z slice cz
+    // (cz < 8 for every P <= 6; slots cz >= P select a zero factor)
+    static_assert(TR == 0 || (16 * TR - 1) / (RR > 0 ? RR : 1) < 8, "mixed tile rows exceed the z slots");
+    int rr_cell[TR > 0 ? TR : 1], rr_cz[TR > 0 ? TR : 1];
+#pragma unroll
+    for (int u = 0; u < TR; ++u) {
+        const int flat = 16 * u + li;
+        rr_cell[u] = 16 * TF + flat % (RR > 0 ? RR : 1);
+        rr_cz[u] = flat / (RR > 0 ? RR : 1);
+    }
 
     PtIn<3> pin;
     float4 zin[4];
+    // node rows of the points run one chunk ahead of their coordinates, so
+    // no load waits on another inside the loop
+    int rown;
     {
         const bool ok = lane < tk.z;
         const int64_t p = (int64_t)tk.y + lane;
@@ -1084,6 +1115,7 @@ __global__ __launch_bounds__(64) void k_spread_mfma3(Geom g, const int4 *__restr
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        rown = lane + 64 < tk.z ? g.perm[(int64_t)tk.y + 64 + lane] : 0;
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
@@ -1116,46 +1148,77 @@ __global__ __launch_bounds__(64) void k_spread_mfma3(Geom g, const int4 *__restr
             const bool ok = lane < tk.z - c1;
             const int64_t p = (int64_t)tk.y + c1 + lane;
             fetch_point<3>(c32, f32, g.n, p, ok, pin);
-            const int row = ok ? g.perm[p] : 0;
+            const int row = rown;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+            rown = lane + 64 < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
         }
+        // all 16 groups in one straight-line block (absent points carry zero
+        // records); the operands of group gi + 1 are read from LDS before the
+        // matrix instructions of group gi are issued
+        struct Ops {
+            float z, a[TF > 0 ? TF : 1], rx[TR > 0 ? TR : 1], rz[TR > 0 ? TR : 1], wz[8];
+        };
+        auto read_ops = [&](int gi, Ops &o) {
+            const int pp = 4 * gi + lk;
+            o.z = zv[pp * 16 + li];
+#pragma unroll
+            for (int t = 0; t < TF; ++t) o.a[t] = wxy[pp * RS + 16 * t + li];
+            // mixed-tile factors; z slots >= P of a record hold zero
+#pragma unroll
+            for (int u = 0; u < TR; ++u) {
+                o.rx[u] = wxy[pp * RS + rr_cell[u]];
+                o.rz[u] = wzs[pp * 8 + rr_cz[u]];
+            }
+            const float4 wz0 = *reinterpret_cast<const float4 *>(wzs + pp * 8);
+            const float4 wz1 = *reinterpret_cast<const float4 *>(wzs + pp * 8 + 4);
+            o.wz[0] = wz0.x; o.wz[1] = wz0.y; o.wz[2] = wz0.z; o.wz[3] = wz0.w;
+            o.wz[4] = wz1.x; o.wz[5] = wz1.y; o.wz[6] = wz1.z; o.wz[7] = wz1.w;
+        };
+        Ops nxt;
+        read_ops(0, nxt);
 #pragma unroll
         for (int gi = 0; gi < 16; ++gi) {
-            if (4 * gi < cnt) {
-                const int pp = 4 * gi + lk;
-                const float z = zv[pp * 16 + li];
-                float a[T2];
+            const Ops cur = nxt;
+            if (gi + 1 < 16) read_ops(gi + 1, nxt);
+            // keep the reads above the matrix instructions that hide them
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int t = 0; t < T2; ++t) a[t] = wxy[pp * RS + 16 * t + li];
-                const float4 wz0 = *reinterpret_cast<const float4 *>(wzs + pp * 8);
-                const float4 wz1 = *reinterpret_cast<const float4 *>(wzs + pp * 8 + 4);
-                const float wz[8] = {wz0.x, wz0.y, wz0.z, wz0.w, wz1.x, wz1.y, wz1.z, wz1.w};
+            for (int cz = 0; cz < P; ++cz) {
+                const float b = cur.z * cur.wz[cz];
 #pragma unroll
-                for (int cz = 0; cz < P; ++cz) {
-                    const float b = z * wz[cz];
-#pragma unroll
-                    for (int t = 0; t < T2; ++t)
-                        acc[t][cz] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b, acc[t][cz], 0, 0, 0);
-                }
+                for (int t = 0; t < TF; ++t)
+                    acc[t][cz] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.a[t], b, acc[t][cz], 0, 0, 0);
             }
+#pragma unroll
+            for (int u = 0; u < TR; ++u)
+                accr[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.rx[u] * cur.rz[u], cur.z, accr[u], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     float *out = patch + (int64_t)tk.w * (C2 * P) * bs + v0 + li;
 #pragma unroll
-    for (int t = 0; t < T2; ++t)
+    for (int t = 0; t < TF; ++t)
 #pragma unroll
         for (int cz = 0; cz < P; ++cz)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int cxy = 16 * t + 4 * lk + r;
-                if (cxy < C2) out[(int64_t)(cxy + C2 * cz) * bs] = acc[t][cz][r];
+            for (int m = 0; m < 4; ++m) {
+                const int cxy = 16 * t + 4 * lk + m;
+                out[(int64_t)(cxy + C2 * cz) * bs] = acc[t][cz][m];
             }
+#pragma unroll
+    for (int u = 0; u < TR; ++u)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int flat = 16 * u + 4 * lk + m;
+            const int cz = flat / (RR > 0 ? RR : 1);
+            if (cz < P) out[(int64_t)(16 * TF + flat % (RR > 0 ? RR : 1) + C2 * cz) * bs] = accr[u][m];
+        }
 }
 
 template <int P>
-__global__ __launch_bounds__(64) void k_interp_mfma3(Geom g, const int4 *__restrict__ tasks,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_interp_mfma3(Geom g, const int4 *__restrict__ tasks,
                                                      const int *__restrict__ c32,
                                                      const float *__restrict__ f32,
                                                      const float *__restrict__ grid, int bg,
@@ -1215,17 +1278,25 @@ __global__ __launch_bounds__(64) void k_interp_mfma3(Geom g, const int4 *__restr
             fetch_point<3>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
             prow = lane < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + lane] : 0;
         }
-        const int nq = (cnt + 15) >> 4;
-        for (int q = 0; q < nq; ++q) {
+        // four point groups of 16 in one straight-line block (absent points
+        // carry zero weights and are not stored)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
             floatx4 gz[P];
 #pragma unroll
             for (int cz = 0; cz < P; ++cz) gz[cz] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // the A operand of step s + 1 is read before the matrix
+            // instructions of step s are issued
+            float an = wt[lk * ES + 16 * q + li];
 #pragma unroll
             for (int s = 0; s < KS2; ++s) {
-                const float a = wt[(4 * s + lk) * ES + 16 * q + li];
+                const float a = an;
+                if (s + 1 < KS2) an = wt[(4 * (s + 1) + lk) * ES + 16 * q + li];
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int cz = 0; cz < P; ++cz)
                     gz[cz] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, hb[cz][s], gz[cz], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
