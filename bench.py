@@ -16,8 +16,10 @@ the FP64 oracle, and the oracle timed on the host cores on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -61,6 +63,34 @@ def copy_calibration(mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
                       "kernels": ["device-to-device copy", "elementwise mul by 1"], "reps": 3}))
+
+
+def kernel_source_hash():
+    """sha256 of the source that holds the NFFT kernels."""
+    path = os.path.join(ROOT, "paper_2007_05239_amd", "csrc", "nfft.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel_prefix):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the
+    factor a plain device copy of known size gives), or None when no summary
+    exists or the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "nfft_hbm_counters_image1000x1000_3layer_b16.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    ff = re.search(r"fetch_factor:\s*([0-9.eE+-]+)", text)
+    wf = re.search(r"write_factor:\s*([0-9.eE+-]+)", text)
+    row = re.search(r"^%s\s+fetch_kib=([0-9.eE+-]+)\s+write_kib=([0-9.eE+-]+)" % re.escape(kernel_prefix),
+                    text, re.M)
+    if not (ff and wf and row):
+        return None
+    return (float(row.group(1)) * float(ff.group(1)) + float(row.group(2)) * float(wf.group(1))) * 1024.0
 
 
 def algorithmic_counts(infos, n, b):
@@ -127,9 +157,11 @@ def main():
     flops = 2.0 * n * w ** 3 * b                     # one multiply-add per (point, window cell, vector)
     achieved = flops / (dur_ms * 1e-3) / 1e12
     pe = w + infos[d3[0]]["bin"] - 1                  # patch edge, the kernel's template argument
-    roof = {"kernel": "k_%s_mfma<3,%d> (d=3 layers, FP32 MFMA 16x16x4)" % (dom, pe),
+    kname = "k_%s_mfma3<%d>" % (dom, pe)
+    roof = {"kernel": kname + " (d=3 layers, FP32 MFMA 16x16x4)",
             "bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+            "traffic": measured_traffic(kname),
             "launch_ms": round(dur_ms, 4),
             "algorithmic": "2*n*w^3*b flop per launch, n=%d w=%d b=%d" % (n, w, b)}
 
