@@ -21,6 +21,13 @@ Pieces (each cites the passage it follows):
 * ``power_mean_dense`` -- L_p for any p != 0 through eigendecompositions,
   with the shift delta for p < 0 (Sec. 2, eqs. (1)-(2); matrix functions via
   eigendecomposition).
+* ``power_mean_power_matvec`` / ``power_mean_eigs`` -- the p-th power
+  L_{p,delta}^p = (1/T) sum_t (L_sym^(t) + delta I)^p applied to a block, and
+  the k smallest eigenpairs of L_{p,delta} taken as the k largest of its p-th
+  power (Sec. 3), through dense eigendecompositions.
+* ``pksm_apply`` -- the polynomial Krylov method of Sec. 3 for one layer:
+  Lanczos on L_sym^(t), then f(T_m) e_1 of the small tridiagonal matrix with
+  f(lambda) = (lambda + delta)^p (Higham, Functions of Matrices, ch. 13).
 * ``allen_cahn`` / ``simplex_project`` / ``potential_grad`` -- Algorithm 2
   steps 2-4 in a fixed FP64 operation order (see ``ac.c``).
 """
@@ -239,6 +246,107 @@ def power_mean_dense(layers, p):
     acc /= len(layers)
     lam, V = np.linalg.eigh(acc)
     return (V * np.clip(lam, 0.0, None) ** (1.0 / p)) @ V.T
+
+
+def shift_delta(p):
+    """delta = log(1 + |p|) for p < 0 and 0 for p > 0 (Sec. 2, shifted power
+    mean)."""
+    if p == 0:
+        raise ValueError("p must be nonzero")
+    return float(np.log1p(abs(p))) if p < 0 else 0.0
+
+
+def lsym_dense(L):
+    """Dense L_sym = I - D^-1/2 W D^-1/2 of one layer (Sec. 2), small n."""
+    W = dense_weight(L.points, L.sigma)
+    s = 1.0 / np.sqrt(W.sum(1))
+    return np.eye(W.shape[0]) - s[:, None] * W * s[None, :]
+
+
+def power_mean_power_dense(layers, p):
+    """Dense L_{p,delta}^p = (1/T) sum_t (L_sym^(t) + delta I)^p (Sec. 3),
+    every power through an eigendecomposition of L_sym^(t); its eigenvalues
+    are clipped at 0 first (they are >= 0 in exact arithmetic)."""
+    delta = shift_delta(p)
+    acc = None
+    for L in layers:
+        lam, V = np.linalg.eigh(lsym_dense(L))
+        lam = np.clip(lam, 0.0, None) + delta
+        M = (V * lam ** p) @ V.T
+        acc = M if acc is None else acc + M
+    return acc / len(layers)
+
+
+def power_mean_power_matvec(layers, p, X):
+    """L_{p,delta}^p X (Sec. 3), small n."""
+    return power_mean_power_dense(layers, p) @ X
+
+
+def power_mean_eigs(layers, p, k):
+    """k smallest eigenpairs of L_{p,delta} (p < 0) or L_p (p > 0): the k
+    largest eigenvalues mu of the p-th power for p < 0 (f = lambda^p reverses
+    the order), the k smallest for p > 0, then lambda = mu^(1/p) (Sec. 3).
+    Eigenvalues ascending; sign convention of ``_fix_signs``."""
+    mu, V = np.linalg.eigh(power_mean_power_dense(layers, p))
+    idx = np.argsort(-mu if p < 0 else mu, kind="stable")[:k]
+    lam = np.clip(mu[idx], 0.0, None) ** (1.0 / p)
+    return lam, _fix_signs(V[:, idx])
+
+
+def pksm_apply(Ls, p, x, tol=1e-12, max_steps=128, check_every=4):
+    """Polynomial Krylov approximation of (Ls + delta I)^p x for a symmetric
+    Ls with spectrum in [0, 2] (Sec. 3, PKSM; Higham, Functions of Matrices,
+    ch. 13).  ``Ls`` is a dense matrix or a function x -> Ls x.
+
+    Lanczos on Ls from v_1 = x / ||x|| (no reorthogonalisation):
+      w = Ls v_j - beta_{j-1} v_{j-1};  alpha_j = v_j^T w;  w -= alpha_j v_j;
+      beta_j = ||w||;  v_{j+1} = w / beta_j  (0 if beta_j = 0).
+    T_m = tridiag(beta, alpha, beta) is the projection of Ls; the shift only
+    moves its eigenvalues.  With T_m = Y diag(theta) Y^T,
+      c_m = Y g(theta) Y^T e_1,  g(theta) = ((max(theta, 0) + delta) / delta)^p,
+    the approximation is y_m = ||x|| delta^p V_m c_m.  g <= 1, so the change
+    ||c_m - c_{m-s}|| (every s = check_every steps) measures the error
+    relative to ||x|| ||f(Ls)||; stop when it is <= tol or at max_steps.
+    Returns (y, steps, converged)."""
+    delta = shift_delta(p)
+    if p >= 0:
+        raise ValueError("pksm_apply is for p < 0")
+    mv = (lambda v: Ls @ v) if not callable(Ls) else Ls
+    x = np.asarray(x, dtype=np.float64)
+    nx = float(np.linalg.norm(x))
+    if nx == 0.0:
+        return np.zeros_like(x), 0, True
+    V = [x / nx]
+    alpha, beta = [], []
+    c_prev = np.zeros(0)
+    c = None
+    converged = False
+    m = 0
+    for j in range(max_steps):
+        w = mv(V[j])
+        if j > 0:
+            w = w - beta[j - 1] * V[j - 1]
+        a = float(V[j] @ w)
+        w = w - a * V[j]
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        beta.append(b)
+        m = j + 1
+        if m % check_every == 0 or m == max_steps:
+            Tm = np.diag(alpha) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+            theta, Y = np.linalg.eigh(Tm)
+            g = ((np.clip(theta, 0.0, None) + delta) / delta) ** p
+            c = Y @ (g * Y[0, :])
+            prev = np.concatenate([c_prev, np.zeros(m - c_prev.size)])
+            change = float(np.linalg.norm(c - prev))
+            c_prev = c
+            if change <= tol:
+                converged = True
+                break
+        if m < max_steps:
+            V.append(w / b if b > 0.0 else np.zeros_like(w))
+    y = (nx * delta ** p) * (np.array(V[:m]).T @ c)
+    return y, m, converged
 
 
 # ---------------------------------------------------------------------------

@@ -141,6 +141,107 @@ def test_power_mean_single_layer_is_that_layer():
     np.testing.assert_allclose(oracle.power_mean_dense([L], -2.0), Ls + delta * np.eye(60), atol=1e-10)
 
 
+def two_small_layers(n=90, seed=61):
+    pts1, _ = gen.gaussian_mixture(n, 2, 3, 0.15, seed)
+    pts2 = gen.uniform_ball(n, 3, 1.0, seed + 1)
+    return oracle.Layer(pts1, 0.3), oracle.Layer(pts2, 0.6)
+
+
+def test_power_mean_power_negative_integer_p_is_inverse():
+    """p = -1 and p = -2: the matrix power is the inverse (LAPACK solve, no
+    eigendecomposition), Sec. 2 shifted power mean with delta = log(1+|p|)."""
+    La, Lb = two_small_layers()
+    X = gen.test_vectors(90, 3, 62)
+    I = np.eye(90)
+    for p in (-1.0, -2.0):
+        delta = math.log(1 + abs(p))
+        ref = 0
+        for L in (La, Lb):
+            A = oracle.lsym_dense(L) + delta * I
+            Y = np.linalg.solve(A, X)
+            if p == -2.0:
+                Y = np.linalg.solve(A, Y)
+            ref = ref + Y
+        ref = ref / 2
+        np.testing.assert_allclose(oracle.power_mean_power_matvec([La, Lb], p, X), ref,
+                                   rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+
+
+def test_power_mean_power_fractional_p_matches_sqrtm():
+    """p = -1/2: (A)^(-1/2) = sqrtm(A)^-1 with scipy's Schur-based sqrtm."""
+    import scipy.linalg
+    La, _ = two_small_layers()
+    p = -0.5
+    A = oracle.lsym_dense(La) + math.log(1.5) * np.eye(90)
+    ref = np.linalg.inv(np.real(scipy.linalg.sqrtm(A)))
+    np.testing.assert_allclose(oracle.power_mean_power_dense([La], p), ref, atol=1e-11)
+
+
+def test_power_mean_eigs_against_inverse_operator():
+    """Two layers, p = -1: eigenpairs of L_{-1,delta} are mu^-1 of the mean of
+    inverses (formed with solve), order reversed (Sec. 3)."""
+    La, Lb = two_small_layers()
+    delta = math.log(2.0)
+    I = np.eye(90)
+    Q = 0.5 * (np.linalg.solve(oracle.lsym_dense(La) + delta * I, I)
+               + np.linalg.solve(oracle.lsym_dense(Lb) + delta * I, I))
+    Q = 0.5 * (Q + Q.T)
+    mu = np.sort(np.linalg.eigvalsh(Q))[::-1][:6]
+    lam, V = oracle.power_mean_eigs([La, Lb], -1.0, 6)
+    np.testing.assert_allclose(lam, 1.0 / mu, rtol=1e-11)
+    assert np.all(np.diff(lam) >= 0) and lam[0] >= delta - 1e-12
+    # eigenvectors of L_{-1,delta} itself
+    Lp = oracle.power_mean_dense([La, Lb], -1.0)
+    np.testing.assert_allclose(Lp @ V, V * lam[None, :], atol=1e-10)
+    # one layer: L_sym + delta I, same vectors as the p = 1 eigensolver
+    lam1, V1 = oracle.power_mean_eigs([La], -10.0, 5)
+    l0, V0 = oracle.eigs_dense([La], 5)
+    np.testing.assert_allclose(lam1, l0 + math.log(11.0), atol=1e-9)
+    np.testing.assert_allclose(np.abs(V1.T @ V0), np.eye(5), atol=1e-6)
+
+
+@pytest.mark.parametrize("p", [-10.0, -1.0, -0.3])
+def test_pksm_converges_to_matrix_power(p):
+    """The Lanczos approximation reaches (L_sym + delta I)^p x within the
+    stopping tolerance (relative to ||x|| ||f(L)||, ||f(L)|| <= delta^p)."""
+    La, _ = two_small_layers(160, 71)
+    Ls = oracle.lsym_dense(La)
+    x = gen.test_vectors(160, 1, 72)[:, 0]
+    ref = oracle.power_mean_power_matvec([La], p, x)
+    y, steps, conv = oracle.pksm_apply(Ls, p, x, tol=1e-12)
+    delta = oracle.shift_delta(p)
+    assert conv and steps < 80
+    assert np.linalg.norm(y - ref) <= 1e-10 * np.linalg.norm(x) * delta ** p
+    # operator given as a function
+    y2, steps2, _ = oracle.pksm_apply(lambda v: Ls @ v, p, x, tol=1e-12)
+    assert steps2 == steps and np.array_equal(y, y2)
+
+
+def test_pksm_special_inputs():
+    La, _ = two_small_layers(120, 81)
+    Ls = oracle.lsym_dense(La)
+    p = -10.0
+    delta = oracle.shift_delta(p)
+    # zero vector
+    y, steps, conv = oracle.pksm_apply(Ls, p, np.zeros(120))
+    assert conv and steps == 0 and not y.any()
+    # the null vector D^1/2 1 of L_sym: f(L) x = delta^p x
+    x = np.sqrt(La.deg)
+    y, steps, conv = oracle.pksm_apply(Ls, p, x)
+    np.testing.assert_allclose(y, delta ** p * x, rtol=1e-12)
+    # an exact invariant subspace of dimension 2: beta_2 = 0, v_3 = 0
+    lam, V = np.linalg.eigh(Ls)
+    x = V[:, 5] + 2 * V[:, 40]
+    y, steps, conv = oracle.pksm_apply(Ls, p, x)
+    ref = (lam[5] + delta) ** p * V[:, 5] + 2 * (lam[40] + delta) ** p * V[:, 40]
+    assert conv
+    np.testing.assert_allclose(y, ref, atol=1e-12 * np.abs(ref).max())
+    # the step limit: no convergence at 4 steps with a tight tolerance
+    x = gen.test_vectors(120, 1, 82)[:, 0]
+    y, steps, conv = oracle.pksm_apply(Ls, -0.1, x, tol=1e-15, max_steps=4)
+    assert steps == 4 and not conv
+
+
 def test_eigs_well_separated_clusters_count():
     pts, _ = gen.gaussian_mixture(200, 2, 4, 0.01, 51, mean_low=0, mean_high=10)
     L = oracle.Layer(pts, 0.05)
