@@ -157,17 +157,48 @@ mlg_status mlg_laplacian_matvec(mlg_graph *g, int layer, int op, int b, const do
 typedef struct {
     int iters;        /* block expansion steps taken                       */
     int restarts;     /* thick restarts                                    */
-    int matvecs;      /* operator applications to single vectors           */
+    int matvecs;      /* p = 1: operator applications to single vectors;  */
+                      /* p < 0: single-vector layer matvecs (all inner     */
+                      /* Krylov steps), saturating at INT32_MAX            */
     int nconv;        /* wanted pairs whose residual is <= tol             */
     double max_resid; /* max residual norm ||A phi - mu phi|| over the k   */
+    int inner_steps;  /* p < 0: longest inner Krylov dimension used        */
+    int inner_unconverged; /* p < 0: inner runs stopped at max_steps       */
 } mlg_eig_info;
 
 /*
- * k smallest eigenpairs of L_sym (layer >= 0) or of L_1 (layer = -1),
- * computed as the k largest of D^-1/2 W D^-1/2 resp. I - L_1 with
- * lambda = 1 - mu (Sec. 3; Algorithm 2 step 1).  FP64 block thick-restart
- * Lanczos with full reorthogonalisation (CGS2).
- *   p            power-mean exponent; only 1.0 is implemented.
+ * Inner iteration of the matrix power for p < 0 (polynomial Krylov method,
+ * Sec. 3).  Per column of a block, the Lanczos coefficient vector
+ * c_m = f(T_m) e_1 (normalised so that |c| <= 1) is recomputed every 4 steps;
+ * the iteration stops when every column changed by <= tol since the last
+ * check, which bounds the error relative to ||x|| delta^p, delta^p being the
+ * norm of (L_sym + delta I)^p.
+ *   tol        <= 0: default (1e-2 x the eigensolver tol; 1e-12 for
+ *              mlg_power_mean_matvec).
+ *   max_steps  Krylov dimension limit, >= 4; 0: default 128.  The device
+ *              caps it where the per-column tridiagonal eigensolve
+ *              (max_steps^2 doubles of LDS) would not fit one workgroup.
+ */
+typedef struct {
+    double tol;
+    int max_steps;
+} mlg_pksm_params;
+
+/*
+ * k smallest eigenpairs of a graph Laplacian by FP64 block thick-restart
+ * Lanczos with full reorthogonalisation (CGS2) (Sec. 3; Algorithm 2 step 1).
+ *   p = 1:  L_sym of one layer (layer >= 0) or L_1 (layer = -1), as the k
+ *           largest eigenpairs of D^-1/2 W D^-1/2 resp. I - L_1,
+ *           lambda = 1 - mu.
+ *   p < 0:  the shifted power mean L_{p,delta}, delta = log(1 + |p|)
+ *           (Sec. 2), as the k largest eigenpairs of its p-th power
+ *           (1/T) sum_t (L_sym^(t) + delta I)^p (order reversed by
+ *           lambda^p), every product through the polynomial Krylov method
+ *           (see mlg_power_mean_matvec); the operator is scaled by delta^-p
+ *           so that its spectrum lies in (0, 1], and lambda = delta mu^(1/p).
+ *           layer >= 0 gives L_sym^(t) + delta I.  The eigenvalues include
+ *           the shift (they are >= delta).
+ *   p            1.0 or < 0; anything else returns MLG_ERR_NOT_IMPL.
  *   k            1..n/2 wanted pairs.
  *   block        vectors per Lanczos block, 1..32.
  *   tol          stop when every residual ||A phi - mu phi||_2 <= tol.
@@ -183,7 +214,31 @@ typedef struct {
  */
 mlg_status mlg_lanczos_eigs(mlg_graph *g, int layer, double p, int k, int block, double tol,
                             int max_restarts, uint64_t seed, const double *V0, double *evals,
-                            double *evecs, int64_t ldv, mlg_eig_info *info, int flags);
+                            double *evecs, int64_t ldv, mlg_eig_info *info,
+                            const mlg_pksm_params *pk, int flags);
+
+/*
+ * Y = (L_sym^(t) + delta I)^p X for layer t >= 0, or
+ * Y = L_{p,delta}^p X = (1/T) sum_t (L_sym^(t) + delta I)^p X for layer = -1,
+ * with p < 0 and delta = log(1 + |p|) (Sec. 2 shifted power mean; Sec. 3 p-th
+ * power), by the polynomial Krylov method of Sec. 3: per layer and column,
+ * Lanczos on L_sym^(t) started from x (no reorthogonalisation), then
+ * y = ||x|| V_m f(T_m + delta I) e_1 with f(lambda) = lambda^p; f(T_m) e_1
+ * comes from an implicit-QL eigensolve of the tridiagonal T_m on the device.
+ * FP64 recurrences over the layers' matvecs (NFFT or direct, each in its own
+ * precision); every reduction has one fixed order, so results are
+ * reproducible bit for bit.
+ *   b      1..64 vectors; X and Y n x b column-major (ldx, ldy >= n), not
+ *          overlapping.  A zero column gives a zero column.
+ *   pk     stopping rule (NULL: defaults, see mlg_pksm_params).
+ *   steps  optional out: longest Krylov dimension used.
+ * Returns MLG_ERR_ARG for p >= 0 and MLG_WARN_NOT_CONVERGED (Y still
+ * written) if some layer stopped at max_steps.  Allocates (max_steps + 1) n b
+ * doubles of device workspace for the call.
+ */
+mlg_status mlg_power_mean_matvec(mlg_graph *g, int layer, double p, int b, const double *X,
+                                 int64_t ldx, double *Y, int64_t ldy, const mlg_pksm_params *pk,
+                                 int *steps, int flags);
 
 /* Allen--Cahn parameters (Algorithm 2): epsilon, omega_0, c, dt, tolerance,
  * max_iter. */

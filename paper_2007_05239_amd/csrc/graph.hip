@@ -462,21 +462,57 @@ mlg_status mlg_kernel_matvec(int64_t n, int d, const double *points, double sigm
     return st;
 }
 
+// Operators of the eigensolver.
+namespace {
+struct NadjOp : LanczosOp {
+    Graph &g;
+    int layer;
+    NadjOp(Graph &g_, int l) : g(g_), layer(l) {}
+    void apply(int b, const double *X, int64_t ldx, double *Y, int64_t ldy) override {
+        graph_matvec_enqueue(g, layer, MLG_OP_NADJ, b, X, ldx, Y, ldy, nullptr);
+    }
+    double lambda(double mu) const override { return 1.0 - mu; }
+};
+
+// delta^-p L_{p,delta}^p, spectrum in (0, 1]; lambda = delta mu^(1/p).
+struct PowerLanczosOp : LanczosOp {
+    PowerMeanOp pw;
+    int layer;
+    PowerLanczosOp(Graph &g, int l, int b, double p, int max_steps) : pw(g, b, p, max_steps), layer(l) {}
+    void apply(int b, const double *X, int64_t ldx, double *Y, int64_t ldy) override {
+        MLG_REQUIRE(b == pw.b, MLG_ERR_ARG, "block size mismatch in the Krylov power");
+        pw.apply(layer, X, ldx, Y, ldy, true);
+    }
+    double lambda(double mu) const override {
+        return pw.delta * std::pow(std::max(mu, 1e-300), 1.0 / pw.p);
+    }
+};
+
+void pksm_defaults(const mlg_pksm_params *pk, double outer_tol, double *tol, int *steps) {
+    *tol = (pk && pk->tol > 0) ? pk->tol : 0.01 * outer_tol;
+    *steps = (pk && pk->max_steps > 0) ? pk->max_steps : kPksmDefaultSteps;
+}
+}  // namespace
+
 mlg_status mlg_lanczos_eigs(mlg_graph *h, int layer, double p, int k, int block, double tol,
                             int max_restarts, uint64_t seed, const double *V0, double *evals,
-                            double *evecs, int64_t ldv, mlg_eig_info *info, int flags) {
+                            double *evecs, int64_t ldv, mlg_eig_info *info,
+                            const mlg_pksm_params *pk, int flags) {
     mlg_status rc = MLG_OK;
     mlg_status st = guard([&] {
         MLG_REQUIRE(h && evals && evecs, MLG_ERR_ARG, "null argument");
         Graph &g = h->g;
         MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
         MLG_REQUIRE(g.has_degrees, MLG_ERR_ARG, "graph created with MLG_SKIP_DEGREES has no Laplacian");
-        MLG_REQUIRE(p == 1.0, MLG_ERR_NOT_IMPL, "only the p = 1 power mean is implemented");
+        MLG_REQUIRE(p == 1.0 || p < 0.0, MLG_ERR_NOT_IMPL,
+                    "power means are implemented for p = 1 and p < 0");
         MLG_REQUIRE(k >= 1 && 2 * (int64_t)k <= g.n, MLG_ERR_ARG, "k must be in 1..n/2");
         MLG_REQUIRE(block >= 1 && block <= 32, MLG_ERR_ARG, "block must be in 1..32");
         MLG_REQUIRE(tol > 0, MLG_ERR_ARG, "tol must be > 0");
         MLG_REQUIRE(max_restarts >= 0, MLG_ERR_ARG, "max_restarts must be >= 0");
         MLG_REQUIRE(ldv >= g.n, MLG_ERR_ARG, "ldv < n");
+        if (pk) MLG_REQUIRE(pk->max_steps == 0 || pk->max_steps >= 4, MLG_ERR_ARG,
+                            "pksm max_steps must be 0 or >= 4");
         const bool dev = (flags & MLG_DEVICE_PTRS) != 0;
         DevBuf<double> dV0, dE;
         const double *v0 = V0;
@@ -492,7 +528,27 @@ mlg_status mlg_lanczos_eigs(mlg_graph *h, int layer, double p, int k, int block,
             lde = g.n;
         }
         std::vector<double> ev(k);
-        rc = lanczos_run(g, layer, k, block, tol, max_restarts, seed, v0, ev.data(), E, lde, info);
+        if (p == 1.0) {
+            NadjOp op(g, layer);
+            rc = lanczos_run(g, op, k, block, tol, max_restarts, seed, v0, ev.data(), E, lde, info);
+            if (info) {
+                info->inner_steps = 0;
+                info->inner_unconverged = 0;
+            }
+        } else {
+            double itol;
+            int isteps;
+            pksm_defaults(pk, tol, &itol, &isteps);
+            PowerLanczosOp op(g, layer, block, p, isteps);
+            op.pw.tol = itol;
+            rc = lanczos_run(g, op, k, block, tol, max_restarts, seed, v0, ev.data(), E, lde, info);
+            if (info) {
+                info->inner_steps = op.pw.max_used;
+                info->inner_unconverged = op.pw.unconverged;
+                info->matvecs = (int)std::min<int64_t>(op.pw.layer_matvecs, INT32_MAX);
+            }
+            if (rc == MLG_OK && op.pw.unconverged) rc = MLG_WARN_NOT_CONVERGED;
+        }
         if (dev) {
             MLG_HIP(hipMemcpyAsync(evals, ev.data(), 8 * k, hipMemcpyHostToDevice, g.stream));
         } else {
@@ -501,6 +557,42 @@ mlg_status mlg_lanczos_eigs(mlg_graph *h, int layer, double p, int k, int block,
                                      g.stream));
         }
         MLG_HIP(hipStreamSynchronize(g.stream));
+    });
+    return st != MLG_OK ? st : rc;
+}
+
+mlg_status mlg_power_mean_matvec(mlg_graph *h, int layer, double p, int b, const double *X,
+                                 int64_t ldx, double *Y, int64_t ldy, const mlg_pksm_params *pk,
+                                 int *steps, int flags) {
+    mlg_status rc = MLG_OK;
+    mlg_status st = guard([&] {
+        MLG_REQUIRE(h && X && Y, MLG_ERR_ARG, "null argument");
+        Graph &g = h->g;
+        MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+        MLG_REQUIRE(g.has_degrees, MLG_ERR_ARG, "graph created with MLG_SKIP_DEGREES has no Laplacian");
+        MLG_REQUIRE(p < 0.0, MLG_ERR_ARG, "p must be negative");
+        MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
+        MLG_REQUIRE(ldx >= g.n && ldy >= g.n, MLG_ERR_ARG, "leading dimension < n");
+        if (pk) MLG_REQUIRE(pk->max_steps == 0 || pk->max_steps >= 4, MLG_ERR_ARG,
+                            "pksm max_steps must be 0 or >= 4");
+        double itol;
+        int isteps;
+        pksm_defaults(pk, 1e-10, &itol, &isteps);
+        PowerMeanOp op(g, b, p, isteps);
+        op.tol = itol;
+        if (flags & MLG_DEVICE_PTRS) {
+            op.apply(layer, X, ldx, Y, ldy, false);
+        } else {
+            DevBuf<double> dX((size_t)g.n * b), dY((size_t)g.n * b);
+            MLG_HIP(hipMemcpy2DAsync(dX.p, g.n * 8, X, ldx * 8, g.n * 8, b, hipMemcpyHostToDevice,
+                                     g.stream));
+            op.apply(layer, dX.p, g.n, dY.p, g.n, false);
+            MLG_HIP(hipMemcpy2DAsync(Y, ldy * 8, dY.p, g.n * 8, g.n * 8, b, hipMemcpyDeviceToHost,
+                                     g.stream));
+        }
+        MLG_HIP(hipStreamSynchronize(g.stream));
+        if (steps) *steps = op.max_used;
+        if (op.unconverged) rc = MLG_WARN_NOT_CONVERGED;
     });
     return st != MLG_OK ? st : rc;
 }

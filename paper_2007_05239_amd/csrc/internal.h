@@ -114,9 +114,48 @@ void nfft_apply(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs, T *
 
 // ---- lanczos.hip ----------------------------------------------------------------
 struct Graph;
-mlg_status lanczos_run(Graph &g, int layer, int k, int block, double tol, int max_restarts,
+// Operator of the block eigensolver: Y = A X for b columns (device pointers,
+// enqueued on the graph's stream), and the map from an eigenvalue mu of A to
+// the Laplacian eigenvalue lambda it stands for.  The solver finds the
+// largest mu.
+struct LanczosOp {
+    virtual ~LanczosOp() = default;
+    virtual void apply(int b, const double *X, int64_t ldx, double *Y, int64_t ldy) = 0;
+    virtual double lambda(double mu) const = 0;
+};
+mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int block, double tol, int max_restarts,
                        uint64_t seed, const double *V0_dev, double *evals_host,
                        double *evecs_dev, int64_t ldv, mlg_eig_info *info);
+
+// ---- pksm.hip -------------------------------------------------------------------
+constexpr int kPksmMaxSteps = 128;      // Krylov dimension limit of the matrix power
+constexpr int kPksmDefaultSteps = 128;
+// Largest Krylov dimension whose tridiagonal eigensolve fits the LDS of one
+// workgroup on the current device (<= kPksmMaxSteps).
+int pksm_max_steps_device();
+// Y = (L_sym^(t) + delta I)^p X (one layer) or the layer mean of these terms,
+// p < 0, delta = log(1+|p|), by the polynomial Krylov method (Sec. 3).
+// Workspace for b columns and up to `max_steps` Krylov vectors is allocated
+// once and reused by every apply.
+struct PowerMeanOp {
+    Graph &g;
+    int b;
+    double p, delta = 0.0;
+    double tol = 1e-12;        // stopping threshold on the change of f(T_m) e_1 / delta^p
+    int mcap = 0;              // Krylov dimension limit
+    int64_t rc = 0;            // rows per reduction block
+    int nblk = 0;
+    DevBuf<double> V, W, part, xn, al, be, C[2], chg;
+    DevBuf<int> fail;
+    int max_used = 0;          // longest Krylov dimension used so far
+    int unconverged = 0;       // layer applications stopped at mcap
+    int64_t layer_matvecs = 0; // single-vector layer matvecs
+    PowerMeanOp(Graph &g, int b, double p, int max_steps);
+    void apply_layer(int t, const double *X, int64_t ldx, double *Y, int64_t ldy, bool accumulate,
+                     double coef);
+    // normalised: f / delta^p (spectrum in (0, 1]) instead of f.
+    void apply(int layer, const double *X, int64_t ldx, double *Y, int64_t ldy, bool normalised);
+};
 
 // ---- ac.hip -------------------------------------------------------------------
 void ac_run(int64_t n, int k, int m, const double *evals_dev, const double *evecs_dev,

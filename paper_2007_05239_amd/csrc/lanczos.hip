@@ -1,8 +1,11 @@
-// FP64 block thick-restart Lanczos for the k largest eigenpairs of
-// A = D^-1/2 W D^-1/2 (one layer) or I - L_1 = (1/T) sum_t D_t^-1/2 W_t D_t^-1/2,
-// returned as the k smallest of L_sym resp. L_1 with lambda = 1 - mu (Sec. 3;
-// Algorithm 2 step 1).  The paper used MATLAB's Krylov-Schur; for a symmetric
-// operator, thick restart with Ritz vectors is the same method.
+// FP64 block thick-restart Lanczos for the k largest eigenpairs of a
+// symmetric operator A given as a LanczosOp (Sec. 3; Algorithm 2 step 1):
+//   p = 1:  A = D^-1/2 W D^-1/2 (one layer) or I - L_1 =
+//           (1/T) sum_t D_t^-1/2 W_t D_t^-1/2, lambda = 1 - mu;
+//   p < 0:  A = delta^-p L_{p,delta}^p through the polynomial Krylov power,
+//           lambda = delta mu^(1/p).
+// The paper used MATLAB's Krylov-Schur; for a symmetric operator, thick
+// restart with Ritz vectors is the same method.
 //
 // State kept between steps:  A V_m = V_m H_m + Q S,  V_m^T Q = 0,
 //   V_m  n x m orthonormal basis, H_m = V_m^T A V_m (m x m),
@@ -463,7 +466,7 @@ struct Lz {
     }
 };
 
-mlg_status lanczos_run(Graph &g, int layer, int k, int b, double tol, int max_restarts,
+mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int max_restarts,
                        uint64_t seed, const double *V0, double *evals, double *evecs, int64_t ldv,
                        mlg_eig_info *info) {
     const int64_t n = g.n;
@@ -518,7 +521,7 @@ mlg_status lanczos_run(Graph &g, int layer, int k, int b, double tol, int max_re
         // ---- expand to mmax columns ----
         while (m + b <= mmax) {
             double *Q = V.p + (int64_t)m * n;
-            graph_matvec_enqueue(g, layer, MLG_OP_NADJ, b, Q, n, W.p, n, nullptr);
+            op.apply(b, Q, n, W.p, n);
             matvecs += b;
             ++iters;
             const int mt = m + b;
@@ -583,7 +586,7 @@ mlg_status lanczos_run(Graph &g, int layer, int k, int b, double tol, int max_re
             z.nn(m, k, V.p, n, Ysel.p, evecs, ldv, 0);
             hipLaunchKernelGGL(k_fix_sign, dim3(k), dim3(256), 0, s, n, evecs, ldv);
             MLG_LAUNCH_CHECK();
-            for (int i = 0; i < k; ++i) evals[i] = 1.0 - th[order[i]];
+            for (int i = 0; i < k; ++i) evals[i] = op.lambda(th[order[i]]);
             st = nconv == k ? MLG_OK : MLG_WARN_NOT_CONVERGED;
             MLG_HIP(hipStreamSynchronize(s));
             break;

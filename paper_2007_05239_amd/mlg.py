@@ -36,8 +36,8 @@ STAGES = ["scatter_in", "spread", "gather", "fft", "interp", "gather_out", "dire
 
 EXPORTED = ["mlg_last_error", "mlg_version", "mlg_graph_create", "mlg_graph_destroy",
             "mlg_graph_degrees", "mlg_kernel_matvec", "mlg_laplacian_matvec",
-            "mlg_lanczos_eigs", "mlg_allen_cahn_ssl", "mlg_profile_stages",
-            "mlg_graph_layer_info"]
+            "mlg_lanczos_eigs", "mlg_power_mean_matvec", "mlg_allen_cahn_ssl",
+            "mlg_profile_stages", "mlg_graph_layer_info"]
 
 
 class MlgError(RuntimeError):
@@ -54,7 +54,12 @@ class KParams(ctypes.Structure):
 
 class EigInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("matvecs", ctypes.c_int),
-                ("nconv", ctypes.c_int), ("max_resid", ctypes.c_double)]
+                ("nconv", ctypes.c_int), ("max_resid", ctypes.c_double),
+                ("inner_steps", ctypes.c_int), ("inner_unconverged", ctypes.c_int)]
+
+
+class PksmParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_steps", ctypes.c_int)]
 
 
 class ACParams(ctypes.Structure):
@@ -82,7 +87,10 @@ def _load():
                                i64, I, P], I),
         "mlg_laplacian_matvec": ([P, I, I, I, P, i64, P, i64, I], I),
         "mlg_lanczos_eigs": ([P, I, ctypes.c_double, I, I, ctypes.c_double, I, ctypes.c_uint64, P,
-                              P, P, i64, ctypes.POINTER(EigInfo), I], I),
+                              P, P, i64, ctypes.POINTER(EigInfo), ctypes.POINTER(PksmParams), I],
+                             I),
+        "mlg_power_mean_matvec": ([P, I, ctypes.c_double, I, P, i64, P, i64,
+                                   ctypes.POINTER(PksmParams), ctypes.POINTER(ctypes.c_int), I], I),
         "mlg_allen_cahn_ssl": ([i64, I, I, P, P, i64, P, ctypes.POINTER(ACParams), P, P,
                                 ctypes.POINTER(ctypes.c_int), I, P], I),
         "mlg_profile_stages": ([P, I, I, I, P, i64, P, i64, I, P, I], I),
@@ -236,9 +244,11 @@ class Graph:
         return dict(zip(STAGES, list(ms)))
 
     def lanczos_eigs(self, layer, k, block=4, tol=1e-10, max_restarts=200, seed=0, p=1.0,
-                     V0=None, device=False):
-        """k smallest eigenpairs (lambda ascending, n x k vectors, info dict)."""
+                     V0=None, device=False, inner_tol=0.0, inner_steps=0):
+        """k smallest eigenpairs (lambda ascending, n x k vectors, info dict);
+        p = 1 (L_sym / L_1) or p < 0 (L_{p,delta} through the Krylov power)."""
         info = EigInfo()
+        pk = ctypes.byref(PksmParams(inner_tol, inner_steps))
         if device:
             import torch
             ev = torch.empty(k, dtype=torch.float64, device="cuda")
@@ -249,7 +259,7 @@ class Graph:
                 v0p = _ptr(V0c)[0]
             _sync()
             rc = _lib.mlg_lanczos_eigs(self._h, layer, p, k, block, tol, max_restarts, seed, v0p,
-                                       _ptr(ev)[0], _ptr(V)[0], self.n, ctypes.byref(info),
+                                       _ptr(ev)[0], _ptr(V)[0], self.n, ctypes.byref(info), pk,
                                        MLG_DEVICE_PTRS)
             _check(rc, allow_warn=True)
             evals, evecs = ev, V.t()
@@ -263,11 +273,34 @@ class Graph:
                 v0p = _ptr(V0c)[0]
             rc = _lib.mlg_lanczos_eigs(self._h, layer, p, k, block, tol, max_restarts, seed, v0p,
                                        _ptr(evals)[0], _ptr(evecs)[0], self.n, ctypes.byref(info),
-                                       0)
+                                       pk, 0)
             _check(rc, allow_warn=True)
         return evals, evecs, dict(iters=info.iters, restarts=info.restarts, matvecs=info.matvecs,
                                   nconv=info.nconv, max_resid=info.max_resid,
+                                  inner_steps=info.inner_steps,
+                                  inner_unconverged=info.inner_unconverged,
                                   converged=(rc == MLG_OK))
+
+    def power_mean_matvec(self, layer, p, X, tol=0.0, max_steps=0):
+        """Y = (L_sym^(t) + delta I)^p X (layer t) or the layer mean of these
+        terms (layer -1), p < 0 (mlg_power_mean_matvec).  Returns (Y, info)
+        with info = dict(steps, converged)."""
+        Xc, n, b = _colmajor(X)
+        pk = ctypes.byref(PksmParams(tol, max_steps))
+        steps = ctypes.c_int(0)
+        if _is_torch(Xc):
+            import torch
+            Y = torch.empty((b, n), dtype=torch.float64, device=Xc.device)
+            _sync()
+            rc = _lib.mlg_power_mean_matvec(self._h, layer, p, b, _ptr(Xc)[0], n, _ptr(Y)[0], n,
+                                            pk, ctypes.byref(steps), MLG_DEVICE_PTRS)
+            Y = Y.t()
+        else:
+            Y = np.zeros((n, b), order="F")
+            rc = _lib.mlg_power_mean_matvec(self._h, layer, p, b, _ptr(Xc)[0], n, _ptr(Y)[0], n,
+                                            pk, ctypes.byref(steps), 0)
+        _check(rc, allow_warn=True)
+        return Y, dict(steps=steps.value, converged=(rc == MLG_OK))
 
 
 def kernel_matvec(points, sigma, X, params=None):
