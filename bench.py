@@ -10,14 +10,17 @@ Metric: n * layers * b / s (node-layer-vector rows per second).
 
 Printed as ONE JSON line with the roofline of the dominant kernel (timed
 with HIP events on the library's stream), the FP64-plain comparison (one
-vector per matvec, FP64 NFFT), the relative error of sampled rows against
-the FP64 oracle, and the oracle timed on the host cores on a bounded sample.
+vector per matvec, FP64 NFFT), the p = -10 power mean (one block product
+with L_{p,delta}^p through the Krylov power, and the eigenpair computation
+for p = -10 and p = 1), the relative error of sampled rows against the FP64
+oracle, and the oracle timed on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -44,6 +47,10 @@ def parse():
     ap.add_argument("--window", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain leg")
+    ap.add_argument("--no-power", action="store_true",
+                    help="skip the p < 0 power-mean leg (Krylov power, eigenpairs)")
+    ap.add_argument("--power-only", action="store_true",
+                    help="run only the power-mean leg and print its JSON object (for profiling)")
     ap.add_argument("--image", type=int, default=1000, help="image edge (n = edge^2)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (HBM counter calibration) and exit")
@@ -103,6 +110,35 @@ def algorithmic_counts(infos, n, b):
     return fl
 
 
+def power_leg(g, X, c, n, T, b):
+    """p = -10 power mean: one block product with L_{p,delta}^p (Krylov power
+    over every layer), and the k smallest eigenpairs for p = -10 and p = 1."""
+    import torch
+    p = -10.0
+    g.power_mean_matvec(-1, p, X, tol=1e-7)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, pinf = g.power_mean_matvec(-1, p, X, tol=1e-7)
+    torch.cuda.synchronize()
+    el_p = (time.perf_counter() - t0) / reps
+    eig = {}
+    for pe, blk in ((p, 16), (1.0, 4)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, einf = g.lanczos_eigs(-1, c["k"], block=blk, tol=1e-5, seed=c["base_seed"] + 201,
+                                    p=pe, device=True)
+        torch.cuda.synchronize()
+        eig["p=%g" % pe] = {"seconds": round(time.perf_counter() - t0, 4), "block": blk,
+                            "outer_iters": einf["iters"], "restarts": einf["restarts"],
+                            "inner_steps": einf["inner_steps"], "converged": einf["converged"]}
+    return {"p": p, "delta": math.log1p(abs(p)), "block": b,
+            "ms_per_power_matvec": round(el_p * 1e3, 3), "inner_steps": pinf["steps"],
+            "inner_tol": 1e-7, "layer_rows_per_s": n * T * b * pinf["steps"] / el_p,
+            "eigs_k%d_tol1e-5" % c["k"]: eig}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -129,6 +165,10 @@ def main():
     plan_s = time.time() - t0
     infos = [g.layer_info(t) for t in range(T)]
     X = torch.from_numpy(np.ascontiguousarray(gen.test_vectors(n, b, c["base_seed"] + 300))).to(dev)
+    if a.power_only:
+        print(json.dumps({"power_mean": power_leg(g, X, c, n, T, b)}))
+        g.close()
+        return
     Xc = X.t().contiguous()                 # column-major n x b block, resident in HBM
     Yc = torch.empty_like(Xc)
     for _ in range(a.warmup):
@@ -184,6 +224,8 @@ def main():
         fp64 = {"value": r64, "ms_per_matvec": el64 / k64 * 1e3, "speedup_fp32_batched": value / r64}
         g64.close()
 
+    power = None if a.no_power else power_leg(g, X, c, n, T, b)
+
     # accuracy on sampled rows and the CPU oracle on the same sample
     acc = None
     cpu = None
@@ -218,7 +260,8 @@ def main():
                       "block": b, "layer_params": infos, "plan_s": round(plan_s, 3),
                       "parallelism": "single GPU"},
            "stages_ms": {k: round(v, 4) for k, v in st.items()},
-           "roofline": roof, "fp64_plain": fp64, "accuracy": acc, "cpu_baseline": cpu}
+           "roofline": roof, "fp64_plain": fp64, "power_mean": power, "accuracy": acc,
+           "cpu_baseline": cpu}
     g.close()
     print(json.dumps(out))
 

@@ -183,6 +183,19 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
         for (auto &e : tm.ev) (void)hipEventDestroy(e);
         return;
     }
+    graph_core_enqueue(g, layer, use_dinv, b, X, ldx);
+    launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
+}
+
+const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
+                                  int64_t ldx) {
+    MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
+    MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
+    const int bs = block_stride(b);
+    ensure_ws(g, bs);
+    hipStream_t s = g.stream;
+    const LayerIO *io = layer >= 0 ? g.io.p + layer : g.io.p;
+    const int nl = layer >= 0 ? 1 : g.T;
     launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
     hipGraphExec_t exec = nullptr;
     for (auto &c : g.caps)
@@ -205,7 +218,7 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
         g.caps.push_back({layer, 0, bs, exec});
     }
     MLG_HIP(hipGraphLaunch(exec, s));
-    launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
+    return io;
 }
 
 // Degrees deg = W 1 in FP64: for NFFT layers a high-accuracy FP64 window.

@@ -145,6 +145,7 @@ struct PowerMeanOp {
     int mcap = 0;              // Krylov dimension limit
     int64_t rc = 0;            // rows per reduction block
     int nblk = 0;
+    int nrow = 0;              // blocks of the row-per-thread kernels
     DevBuf<double> V, W, part, xn, al, be, C[2], chg;
     DevBuf<int> fail;
     int max_used = 0;          // longest Krylov dimension used so far
@@ -188,5 +189,12 @@ struct Graph {
 // records stage events (see mlg_profile_stages).
 void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, int64_t ldx,
                           double *Y, int64_t ldy, double *stage_ms);
+// The entry and summation part of that: scatter-in of X (with D^-1/2 when
+// use_dinv) and the layers' summations, leaving F_t in the workspace slices
+// described by the returned device descriptors (one for layer >= 0, T for
+// -1; block stride = the next power of two >= b).  The caller enqueues its
+// own exit kernel on g.stream.
+const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
+                                  int64_t ldx);
 
 }  // namespace mlg

@@ -14,6 +14,8 @@ Workloads (seeded, synthetic; see workloads/gen.py):
   cube      512 x 512 pixels x 104 bands, 52 two-band layers, N in {32,64,128}
   large     n = 1e7 per layer, 3 layers d = 3, sigma 0.02, N = 128
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -172,6 +174,43 @@ def test_image_lanczos_and_allen_cahn(mlg, image, image_graph):
     Uo, po, ito, _ = oracle.allen_cahn(lam, V, lab, c["m"], tol=0.0, max_iter=12)
     assert it == ito == 12
     assert np.array_equal(U, Uo) and np.array_equal(pred, po)
+
+
+def test_image_power_inverse_rows(mlg, image, image_graph):
+    """p = -1 on one layer: Y = (L_sym + delta I)^-1 X, so (L_sym + delta I) Y
+    = X, checked with the layer operator the Krylov power used (that
+    operator's sampled rows and degrees are checked against the oracle in
+    test_image_weight_and_degree_rows; the oracle cannot form all 10^6
+    degrees, which every row of L_sym Y needs)."""
+    c, g = image, image_graph
+    n, p = c["n"], -1.0
+    delta = math.log(2.0)
+    X = gen.test_vectors(n, 4, c["base_seed"] + 302)
+    Xd = device_block(X)
+    case_id("image (L_sym^(0) + delta I)^-1 x n=%d b=4" % n)
+    Y, info = g.power_mean_matvec(0, p, Xd, tol=1e-9)
+    assert info["converged"], info
+    R = g.laplacian_matvec(0, mlg.MLG_OP_LSYM, Y) + delta * Y - Xd
+    R = R.cpu().numpy()
+    assert (np.linalg.norm(R, axis=0) / np.linalg.norm(X, axis=0)).max() <= 1e-6
+
+
+def test_image_lanczos_negative_p(mlg, image, image_graph):
+    """20 smallest eigenpairs of L_{-10,delta} (three layers) through the
+    Krylov power: residuals of the p-th power, order and bounds."""
+    c, g = image, image_graph
+    n, k, p = c["n"], c["k"], -10.0
+    delta = math.log(11.0)
+    case_id("image lanczos L_{-10,delta} n=%d k=%d block=16" % (n, k))
+    lam, V, info = g.lanczos_eigs(-1, k, block=16, tol=1e-5, seed=c["base_seed"] + 201, p=p)
+    case_id("  %s" % info)
+    assert info["converged"] and info["inner_unconverged"] == 0, info
+    assert np.all(np.diff(lam) >= 0) and lam[0] >= delta - 1e-9 and lam[-1] <= 2.0 + delta
+    np.testing.assert_allclose(V.T @ V, np.eye(k), atol=1e-10)
+    QV, _ = g.power_mean_matvec(-1, p, device_block(V[:, :16]), tol=1e-9)
+    QV = QV.cpu().numpy()
+    res = np.linalg.norm(QV - V[:, :16] * lam[None, :16] ** p, axis=0) / delta ** p
+    assert res.max() <= 2e-5, res
 
 
 # ---------------------------------------------------------------------------
