@@ -22,6 +22,7 @@ namespace mlg {
 
 constexpr int kAcChunk = 256;
 constexpr int kAcMaxM = 64;
+constexpr int kAcFastM = 16;    // class counts with register-resident rows
 
 __global__ void k_ac_Z(int64_t n, int k, const double *__restrict__ evals,
                        const double *__restrict__ evecs, int64_t ldv, double c, double dt,
@@ -47,47 +48,81 @@ __global__ void k_ac_init(int64_t n, int m, const int32_t *__restrict__ labels,
     for (int j = 0; j < m; ++j) U[i * m + j] = (l >= 0) ? (j == l ? 1.0 : 0.0) : inv_m;
 }
 
+// Arrays of compile-time length M hold the m <= M classes, so that the
+// per-row state stays in registers when M = m; the loops run over the first
+// m entries in the documented order.
+template <int M>
 __device__ inline void ac_potential_grad(int m, const double *u, double *T) {
-    double a[kAcMaxM], s[kAcMaxM], term[kAcMaxM];
-    for (int q = 0; q < m; ++q) {
-        double acc = 0.0;
-        for (int c = 0; c < m; ++c) acc = acc + fabs(u[c] - (c == q ? 1.0 : 0.0));
-        a[q] = acc;
-        s[q] = 0.25 * (a[q] * a[q]);
+    double a[M], s[M], term[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        if (q < m) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                if (c < m) acc = acc + fabs(u[c] - (c == q ? 1.0 : 0.0));
+            a[q] = acc;
+            s[q] = 0.25 * (a[q] * a[q]);
+        }
     }
-    for (int q = 0; q < m; ++q) {
-        double prod = 1.0;
-        for (int p = 0; p < m; ++p)
-            if (p != q) prod = prod * s[p];
-        term[q] = (0.5 * a[q]) * prod;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        if (q < m) {
+            double prod = 1.0;
+#pragma unroll
+            for (int p = 0; p < M; ++p)
+                if (p < m && p != q) prod = prod * s[p];
+            term[q] = (0.5 * a[q]) * prod;
+        }
     }
-    for (int j = 0; j < m; ++j) {
-        double t = 0.0;
-        for (int q = 0; q < m; ++q) t = (q == j) ? t - term[q] : t + term[q];
-        T[j] = t;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if (j < m) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+                if (q < m) t = (q == j) ? t - term[q] : t + term[q];
+            T[j] = t;
+        }
     }
 }
 
-__global__ void k_ac_rhs(int64_t n, int m, const double *__restrict__ U,
-                         const int32_t *__restrict__ labels, double onepcdt, double coefT,
-                         double dt, double omega0, double *__restrict__ R) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double u[kAcMaxM], T[kAcMaxM];
-    for (int j = 0; j < m; ++j) u[j] = U[i * m + j];
-    ac_potential_grad(m, u, T);
-    const int l = labels[i];
+// Row i of R = ((1+c dt) U - (dt/(2 eps)) T) - (dt omega_i)(U - F).
+template <int M>
+__device__ inline void ac_rhs_row(int64_t i, int m, const double *u, int l, double onepcdt,
+                                  double coefT, double dt, double omega0,
+                                  double *__restrict__ R) {
+    double T[M];
+    ac_potential_grad<M>(m, u, T);
     const double om = l >= 0 ? omega0 : 0.0;
     const double w = dt * om;
-    for (int j = 0; j < m; ++j) {
-        const double f = (l >= 0 && j == l) ? 1.0 : 0.0;
-        const double r1 = onepcdt * u[j];
-        const double r2 = coefT * T[j];
-        const double r3 = r1 - r2;
-        const double r4 = u[j] - f;
-        const double r5 = w * r4;
-        R[i * m + j] = r3 - r5;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if (j < m) {
+            const double f = (l >= 0 && j == l) ? 1.0 : 0.0;
+            const double r1 = onepcdt * u[j];
+            const double r2 = coefT * T[j];
+            const double r3 = r1 - r2;
+            const double r4 = u[j] - f;
+            const double r5 = w * r4;
+            R[i * m + j] = r3 - r5;
+        }
     }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_ac_rhs(int64_t n, int m_rt, const double *__restrict__ U,
+                                                const int32_t *__restrict__ labels, double onepcdt,
+                                                double coefT, double dt, double omega0,
+                                                double *__restrict__ R) {
+    // the dispatch passes M = m for m <= kAcFastM: fold the class count
+    const int m = (M <= kAcFastM) ? M : m_rt;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double u[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) u[j] = j < m ? U[i * m + j] : 0.0;
+    ac_rhs_row<M>(i, m, u, labels[i], onepcdt, coefT, dt, omega0, R);
 }
 
 // part[ch][r][c] = sum over rows of chunk ch (ascending) of Z[r][i]*R[i][c].
@@ -136,71 +171,104 @@ __global__ void k_ac_tree(int64_t cnt, int len, const double *__restrict__ src,
         dst[e] = src[(cnt - 1) * len + x];
 }
 
+// Chen & Ye projection of y onto the simplex.  The sort is an odd-even
+// transposition network (the sorted values are the same for any correct
+// sort); entries m..M-1 are +inf and sort last.
+template <int M>
 __device__ inline void ac_project(int m, const double *y, double *x) {
-    double srt[kAcMaxM];
-    for (int i = 0; i < m; ++i) {
-        double v = y[i];
-        int j = i - 1;
-        while (j >= 0 && srt[j] > v) {
-            srt[j + 1] = srt[j];
-            --j;
+    double srt[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) srt[i] = i < m ? y[i] : INFINITY;
+#pragma unroll
+    for (int pass = 0; pass < M; ++pass) {
+#pragma unroll
+        for (int i = pass & 1; i + 1 < M; i += 2) {
+            const double a = srt[i], b = srt[i + 1];
+            const bool sw = a > b;
+            srt[i] = sw ? b : a;
+            srt[i + 1] = sw ? a : b;
         }
-        srt[j + 1] = v;
     }
     double s = 0.0, that = 0.0;
     bool found = false;
-    for (int i = m - 1; i >= 1; --i) {
-        s = s + srt[i];
-        const double t = (s - 1.0) / (double)(m - i);
-        if (t >= srt[i - 1]) {
-            that = t;
-            found = true;
-            break;
+#pragma unroll
+    for (int i = M - 1; i >= 1; --i) {
+        if (i <= m - 1 && !found) {
+            s = s + srt[i];
+            const double t = (s - 1.0) / (double)(m - i);
+            if (t >= srt[i - 1]) {
+                that = t;
+                found = true;
+            }
         }
     }
     if (!found) {
         s = s + srt[0];
         that = (s - 1.0) / (double)m;
     }
-    for (int i = 0; i < m; ++i) {
-        const double dlt = y[i] - that;
-        x[i] = dlt > 0.0 ? dlt : 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        if (i < m) {
+            const double dlt = y[i] - that;
+            x[i] = dlt > 0.0 ? dlt : 0.0;
+        }
     }
 }
 
-// U~ = Phi V, projection, per-row squared norms of the change and the new row.
-__global__ void k_ac_update(int64_t n, int k, int m, const double *__restrict__ evecs, int64_t ldv,
-                            const double *__restrict__ V, double *__restrict__ U,
-                            double *__restrict__ rowd, double *__restrict__ rown) {
-    __shared__ double Vs[128 * 16];
-    const bool vs_ok = k * m <= 128 * 16;
-    if (vs_ok)
+// U~ = Phi V, projection, per-row squared norms of the change and the new row,
+// and the next right-hand side row.  Each eigenvector entry is read once and
+// used for all m classes; V sits in LDS when it fits (VLDS), else it is read
+// from global memory.
+template <int M, bool VLDS>
+__global__ __launch_bounds__(256) void k_ac_update(int64_t n, int k, int m_rt,
+                                                   const double *__restrict__ evecs, int64_t ldv,
+                                                   const double *__restrict__ V,
+                                                   double *__restrict__ U,
+                                                   double *__restrict__ rowd,
+                                                   double *__restrict__ rown,
+                                                   const int32_t *__restrict__ labels,
+                                                   double onepcdt, double coefT, double dt,
+                                                   double omega0, double *__restrict__ R) {
+    // the dispatch passes M = m for m <= kAcFastM: fold the class count
+    const int m = (M <= kAcFastM) ? M : m_rt;
+    extern __shared__ double Vs[];
+    if constexpr (VLDS) {
         for (int e = threadIdx.x; e < k * m; e += blockDim.x) Vs[e] = V[e];
-    __syncthreads();
-    const double *Vp = vs_ok ? Vs : V;
+        __syncthreads();
+    }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double ut[kAcMaxM], un[kAcMaxM];
-    for (int j = 0; j < m; ++j) {
-        double acc = 0.0;
-        for (int r = 0; r < k; ++r) {
-            const double pr = evecs[i + (int64_t)r * ldv] * Vp[r * m + j];
-            acc = acc + pr;
+    double ut[M], un[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) ut[j] = 0.0;
+#pragma unroll 8
+    for (int r = 0; r < k; ++r) {
+        const double ph = evecs[i + (int64_t)r * ldv];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (j < m) {
+                const double pr = ph * (VLDS ? Vs[r * m + j] : V[r * m + j]);
+                ut[j] = ut[j] + pr;
+            }
         }
-        ut[j] = acc;
     }
-    ac_project(m, ut, un);
+    ac_project<M>(m, ut, un);
     double dn = 0.0, nn = 0.0;
-    for (int j = 0; j < m; ++j) {
-        const double dl = un[j] - U[i * m + j];
-        const double p1 = dl * dl;
-        dn = dn + p1;
-        const double p2 = un[j] * un[j];
-        nn = nn + p2;
-        U[i * m + j] = un[j];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if (j < m) {
+            const double dl = un[j] - U[i * m + j];
+            const double p1 = dl * dl;
+            dn = dn + p1;
+            const double p2 = un[j] * un[j];
+            nn = nn + p2;
+            U[i * m + j] = un[j];
+        }
     }
     rowd[i] = dn;
     rown[i] = nn;
+    // the next iteration's right-hand side from the new row
+    ac_rhs_row<M>(i, m, un, labels[i], onepcdt, coefT, dt, omega0, R);
 }
 
 // Block maxima (max is exact, so the grouping does not matter).
@@ -248,10 +316,277 @@ __global__ void k_ac_argmax(int64_t n, int m, const double *__restrict__ U,
     pred[i] = best;
 }
 
+// ---- fused iteration (m <= 16): one pass over the eigenvectors per step ----
+// den_r = (1 + c dt) + (eps dt) lambda_r, the divisor of row r of Z.
+__global__ void k_ac_den(int k, const double *__restrict__ evals, double c, double dt, double eps,
+                         double *__restrict__ den) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    double onepcdt = c * dt;
+    onepcdt = 1.0 + onepcdt;
+    const double epsdt = eps * dt;
+    const double ee = epsdt * evals[r];
+    den[r] = onepcdt + ee;
+}
+
+// Chunk-major copies of the eigenvectors and of Z:
+//   Pc[(ch k + r) 256 + ii] = phi_{ch 256 + ii, r},  Zc[...] = that / den_r
+// (0 past n), so that a chunk's k x 256 block is contiguous.
+__global__ void k_ac_pack(int64_t n, int k, int64_t nch, const double *__restrict__ evecs,
+                          int64_t ldv, const double *__restrict__ den, double *__restrict__ Pc,
+                          double *__restrict__ Zc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nch * k * kAcChunk) return;
+    const int ii = (int)(e & (kAcChunk - 1));
+    const int64_t rest = e >> 8;
+    const int r = (int)(rest % k);
+    const int64_t i = (rest / k) * kAcChunk + ii;
+    const double ph = i < n ? evecs[i + (int64_t)r * ldv] : 0.0;
+    Pc[e] = ph;
+    Zc[e] = ph / den[r];
+}
+
+// sum over rows q < cnt in order of z_q R[q][c] (R rows at stride m in LDS,
+// Rc = &R[0][c]); z from the chunk-major Z row in groups of 16 rows, two
+// register buffers in turn: a group's loads are issued one group before it
+// is used.  FULL: cnt = 256.
+template <bool FULL>
+__device__ inline void ac_chain_group(const double2 (&g)[8], const double *Rc, int m, int base,
+                                      int cnt, double &acc) {
+#pragma unroll
+    for (int h = 0; h < 16; ++h) {
+        if (FULL || base + h < cnt) {
+            const double z = (h & 1) ? g[h >> 1].y : g[h >> 1].x;
+            const double p = z * Rc[(base + h) * m];
+            acc = acc + p;
+        }
+    }
+}
+
+template <bool FULL>
+__device__ inline double ac_chain(const double2 *__restrict__ z2, const double *Rc, int m,
+                                  int cnt) {
+    double acc = 0.0;
+    double2 ga[8], gb[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) ga[h] = z2[h];
+    for (int q0 = 0; q0 < cnt; q0 += 32) {
+        if (q0 + 16 < cnt) {
+#pragma unroll
+            for (int h = 0; h < 8; ++h) gb[h] = z2[(q0 + 16) / 2 + h];
+        }
+        ac_chain_group<FULL>(ga, Rc, m, q0, cnt, acc);
+        if (q0 + 32 < cnt) {
+#pragma unroll
+            for (int h = 0; h < 8; ++h) ga[h] = z2[(q0 + 32) / 2 + h];
+        }
+        if (q0 + 16 < cnt) ac_chain_group<FULL>(gb, Rc, m, q0 + 16, cnt, acc);
+    }
+    return acc;
+}
+
+// One step for chunk ch = blockIdx.x (256 rows, thread ii owns row ch 256 + ii):
+//   update (unless FIRST): u~ = sum_r phi_ir V_r (r ascending), projection,
+//     change norms (block maxima), U row written;
+//   the right-hand side row of the new U, kept in LDS;
+//   the chunk's partials of the next V: part[ch][r][c] = sum over the rows in
+//     order of Z_ri R_ic, one thread per (r, c) chain, Z from the chunk-major
+//     copy (consecutive threads share r and read the same Z entries).
+template <int M, bool FIRST>
+__global__ __launch_bounds__(256) void k_ac_iter(int64_t n, int k, int m_rt,
+                                                 const double *__restrict__ Pc,
+                                                 const double *__restrict__ Zc,
+                                                 const double *__restrict__ V,
+                                                 double *__restrict__ U,
+                                                 const int32_t *__restrict__ labels,
+                                                 double onepcdt, double coefT, double dt,
+                                                 double omega0, double *__restrict__ part,
+                                                 double *__restrict__ mxd,
+                                                 double *__restrict__ mxn) {
+    // the dispatch passes M = m for m <= kAcFastM: fold the class count
+    const int m = (M <= kAcFastM) ? M : m_rt;
+    extern __shared__ double lds[];
+    double *Vs = lds;                        // k x m
+    double *Rs = Vs + k * m;                 // 256 x m
+    __shared__ double red[2][4];
+    const int64_t ch = blockIdx.x;
+    const int64_t i0 = ch * kAcChunk;
+    const int cnt = (int)((n - i0) < kAcChunk ? (n - i0) : kAcChunk);
+    const int ii = threadIdx.x;
+    const int64_t i = i0 + ii;
+    const bool live = ii < cnt;
+    const double *P = Pc + ch * (int64_t)k * kAcChunk;
+    if (!FIRST)
+        for (int e = threadIdx.x; e < k * m; e += blockDim.x) Vs[e] = V[e];
+    __syncthreads();
+    double dn = 0.0, nn = 0.0;
+    if (live) {
+        double u[M];
+        if (FIRST) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) u[j] = j < m ? U[i * m + j] : 0.0;
+        } else {
+            double ut[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) ut[j] = 0.0;
+#pragma unroll 8
+            for (int r = 0; r < k; ++r) {
+                const double ph = P[(int64_t)r * kAcChunk + ii];
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    if (j < m) {
+                        const double pr = ph * Vs[r * m + j];
+                        ut[j] = ut[j] + pr;
+                    }
+                }
+            }
+            ac_project<M>(m, ut, u);
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (j < m) {
+                    const double dl = u[j] - U[i * m + j];
+                    const double p1 = dl * dl;
+                    dn = dn + p1;
+                    const double p2 = u[j] * u[j];
+                    nn = nn + p2;
+                    U[i * m + j] = u[j];
+                }
+            }
+        }
+        ac_rhs_row<M>(ii, m, u, labels[i], onepcdt, coefT, dt, omega0, Rs);
+    }
+    if (!FIRST) {
+        // block maxima of the change norms (max is exact in any order)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            dn = fmax(dn, __shfl_xor(dn, off, 64));
+            nn = fmax(nn, __shfl_xor(nn, off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            red[0][threadIdx.x >> 6] = dn;
+            red[1][threadIdx.x >> 6] = nn;
+        }
+    }
+    __syncthreads();
+    if (!FIRST && threadIdx.x == 0) {
+        mxd[ch] = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+        mxn[ch] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+    }
+    const double *Zb = Zc + ch * (int64_t)k * kAcChunk;
+    for (int q = threadIdx.x; q < k * m; q += blockDim.x) {
+        const int r = q / m, c = q - r * m;
+        const double2 *z2 = reinterpret_cast<const double2 *>(Zb + (int64_t)r * kAcChunk);
+        const double acc = cnt == kAcChunk ? ac_chain<true>(z2, Rs + c, m, cnt)
+                                           : ac_chain<false>(z2, Rs + c, m, cnt);
+        part[ch * (int64_t)k * m + q] = acc;
+    }
+}
+
+// Runs CALL with MM = m for 2 <= m <= 16 (register-resident rows), else with
+// MM = kAcMaxM and the runtime m.
+#define AC_M_SWITCH(m, CALL)                 \
+    switch (m) {                             \
+        case 2: { constexpr int MM = 2; CALL; break; }   \
+        case 3: { constexpr int MM = 3; CALL; break; }   \
+        case 4: { constexpr int MM = 4; CALL; break; }   \
+        case 5: { constexpr int MM = 5; CALL; break; }   \
+        case 6: { constexpr int MM = 6; CALL; break; }   \
+        case 7: { constexpr int MM = 7; CALL; break; }   \
+        case 8: { constexpr int MM = 8; CALL; break; }   \
+        case 9: { constexpr int MM = 9; CALL; break; }   \
+        case 10: { constexpr int MM = 10; CALL; break; } \
+        case 11: { constexpr int MM = 11; CALL; break; } \
+        case 12: { constexpr int MM = 12; CALL; break; } \
+        case 13: { constexpr int MM = 13; CALL; break; } \
+        case 14: { constexpr int MM = 14; CALL; break; } \
+        case 15: { constexpr int MM = 15; CALL; break; } \
+        case 16: { constexpr int MM = 16; CALL; break; } \
+        default: { constexpr int MM = kAcMaxM; CALL; break; } \
+    }
+
+static size_t ac_fused_lds(int k, int m) {
+    return (size_t)((int64_t)k * m + (int64_t)kAcChunk * m) * sizeof(double);
+}
+
+// Fused steps on chunk-major copies of the eigenvectors and of Z: each step
+// reads both once; U is read and written once, the right-hand side never
+// leaves the workgroup.
+static void ac_run_fused(int64_t n, int k, int m, const double *evals, const double *evecs,
+                         int64_t ldv, const int32_t *labels, const mlg_ac_params &prm, double *U,
+                         int32_t *pred, int *iters, hipStream_t s) {
+    const int64_t nch = (n + kAcChunk - 1) / kAcChunk;
+    DevBuf<double> Pc((size_t)nch * k * kAcChunk), Zc((size_t)nch * k * kAcChunk), den(k), mxd(nch),
+        mxn(nch);
+    DevBuf<double> pa((size_t)nch * k * m), pb((size_t)((nch + 1) / 2) * k * m + 1), mx(2048),
+        rcd(1);
+    DevBuf<int> bad(1);
+    MLG_HIP(hipMemsetAsync(bad.p, 0, 4, s));
+    hipLaunchKernelGGL(k_ac_den, dim3(ceil_div(k, 256)), dim3(256), 0, s, k, evals, prm.c, prm.dt,
+                       prm.eps, den.p);
+    MLG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ac_pack, dim3(ceil_div(nch * k * kAcChunk, 256)), dim3(256), 0, s, n, k,
+                       nch, evecs, ldv, den.p, Pc.p, Zc.p);
+    MLG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_ac_init, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, m, labels, U, bad.p);
+    MLG_LAUNCH_CHECK();
+    int hb = 0;
+    MLG_HIP(hipMemcpyAsync(&hb, bad.p, 4, hipMemcpyDeviceToHost, s));
+    MLG_HIP(hipStreamSynchronize(s));
+    MLG_REQUIRE(hb == 0, MLG_ERR_ARG, "labels must be -1 or in 0..m-1");
+    double onepcdt = prm.c * prm.dt;
+    onepcdt = 1.0 + onepcdt;
+    const double coefT = prm.dt / (2.0 * prm.eps);
+    const size_t lds = ac_fused_lds(k, m);
+    const int nmx = std::min<int64_t>(1024, ceil_div(nch, 256));
+    AC_M_SWITCH(m, hipLaunchKernelGGL((k_ac_iter<MM, true>), dim3((unsigned)nch), dim3(kAcChunk), lds,
+                                      s, n, k, m, Pc.p, Zc.p, nullptr, U, labels, onepcdt, coefT,
+                                      prm.dt, prm.omega0, pa.p, mxd.p, mxn.p));
+    MLG_LAUNCH_CHECK();
+    int l = 0;
+    double rc = 0.0;
+    do {
+        double *src = pa.p, *dst = pb.p;
+        int64_t cnt = nch;
+        while (cnt > 1) {
+            const int64_t outc = cnt / 2 + (cnt & 1);
+            hipLaunchKernelGGL(k_ac_tree, dim3(ceil_div(outc * k * m, 256)), dim3(256), 0, s, cnt, k * m,
+                               src, dst);
+            MLG_LAUNCH_CHECK();
+            std::swap(src, dst);
+            cnt = outc;
+        }
+        // src holds V; the step overwrites pa with the next partials
+        double *Vd = src;
+        if (src == pa.p) {
+            MLG_HIP(hipMemcpyAsync(pb.p, pa.p, sizeof(double) * k * m, hipMemcpyDeviceToDevice, s));
+            Vd = pb.p;
+        }
+        AC_M_SWITCH(m, hipLaunchKernelGGL((k_ac_iter<MM, false>), dim3((unsigned)nch), dim3(kAcChunk),
+                                          lds, s, n, k, m, Pc.p, Zc.p, Vd, U, labels, onepcdt, coefT,
+                                          prm.dt, prm.omega0, pa.p, mxd.p, mxn.p));
+        MLG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_max2, dim3(nmx), dim3(256), 0, s, nch, mxd.p, mxn.p, mx.p);
+        MLG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_ac_finish_max, dim3(1), dim3(64), 0, s, nmx, mx.p, rcd.p);
+        MLG_LAUNCH_CHECK();
+        MLG_HIP(hipMemcpyAsync(&rc, rcd.p, 8, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        l = l + 1;
+    } while (rc > prm.tol && l < prm.max_iter);
+    hipLaunchKernelGGL(k_ac_argmax, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, m, U, pred);
+    MLG_LAUNCH_CHECK();
+    MLG_HIP(hipStreamSynchronize(s));
+    *iters = l;
+}
+
 void ac_run(int64_t n, int k, int m, const double *evals, const double *evecs, int64_t ldv,
             const int32_t *labels, const mlg_ac_params &prm, double *U, int32_t *pred, int *iters,
             hipStream_t s) {
     MLG_REQUIRE(m <= kAcMaxM, MLG_ERR_ARG, "m must be <= 64");
+    if (m <= kAcFastM && ac_fused_lds(k, m) <= 65536) {
+        ac_run_fused(n, k, m, evals, evecs, ldv, labels, prm, U, pred, iters, s);
+        return;
+    }
     DevBuf<double> Z((size_t)n * k), R((size_t)n * m), rowd(n), rown(n);
     const int64_t nch = (n + kAcChunk - 1) / kAcChunk;
     DevBuf<double> pa((size_t)nch * k * m), pb((size_t)((nch + 1) / 2) * k * m + 1), mx(2048),
@@ -271,12 +606,14 @@ void ac_run(int64_t n, int k, int m, const double *evals, const double *evecs, i
     onepcdt = 1.0 + onepcdt;
     const double coefT = prm.dt / (2.0 * prm.eps);
     const int nmx = std::min<int64_t>(1024, ceil_div(n, 256));
+    const size_t v_lds = (size_t)k * m * sizeof(double);
+    const bool v_in_lds = v_lds <= 65536;
     int l = 0;
     double rc = 0.0;
+    AC_M_SWITCH(m, hipLaunchKernelGGL(k_ac_rhs<MM>, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, m, U,
+                                      labels, onepcdt, coefT, prm.dt, prm.omega0, R.p));
+    MLG_LAUNCH_CHECK();
     do {
-        hipLaunchKernelGGL(k_ac_rhs, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, m, U, labels, onepcdt,
-                           coefT, prm.dt, prm.omega0, R.p);
-        MLG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_ac_zr, dim3((unsigned)nch), dim3(256), 0, s, n, k, m, Z.p, R.p, pa.p);
         MLG_LAUNCH_CHECK();
         double *src = pa.p, *dst = pb.p;
@@ -289,8 +626,17 @@ void ac_run(int64_t n, int k, int m, const double *evals, const double *evecs, i
             std::swap(src, dst);
             cnt = outc;
         }
-        hipLaunchKernelGGL(k_ac_update, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, k, m, evecs, ldv, src,
-                           U, rowd.p, rown.p);
+        if (v_in_lds) {
+            AC_M_SWITCH(m, hipLaunchKernelGGL((k_ac_update<MM, true>), dim3(ceil_div(n, 256)),
+                                              dim3(256), v_lds, s, n, k, m, evecs, ldv, src, U,
+                                              rowd.p, rown.p, labels, onepcdt, coefT, prm.dt,
+                                              prm.omega0, R.p));
+        } else {
+            AC_M_SWITCH(m, hipLaunchKernelGGL((k_ac_update<MM, false>), dim3(ceil_div(n, 256)),
+                                              dim3(256), 0, s, n, k, m, evecs, ldv, src, U, rowd.p,
+                                              rown.p, labels, onepcdt, coefT, prm.dt, prm.omega0,
+                                              R.p));
+        }
         MLG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_max2, dim3(nmx), dim3(256), 0, s, n, rowd.p, rown.p, mx.p);
         MLG_LAUNCH_CHECK();

@@ -225,6 +225,26 @@ def test_allen_cahn_bit_exact(mlg):
     assert it2 == ito2 and np.array_equal(U2, Uo2) and np.array_equal(p2, po2)
 
 
+@pytest.mark.parametrize("n,k,m", [(40_001, 120, 10), (20_003, 30, 16), (9_001, 12, 17),
+                                   (5_003, 300, 4), (3_001, 7, 2), (3_001, 250, 16),
+                                   (250, 5, 3)])
+def test_allen_cahn_bit_exact_shapes(mlg, n, k, m):
+    """The fused step (m <= 16, its LDS within 64 KiB; k > 256 too) and the
+    general kernels (m > 16, or k = 250 with m = 16), ragged last chunk of
+    256 rows, a single chunk: scores and labels bit-exact against the oracle
+    after 20 iterations.  Any orthonormal basis serves as the eigenvector
+    block of the scheme."""
+    g = gen.rng(1000 + n)
+    Phi, _ = np.linalg.qr(g.standard_normal((n, k)))
+    lam = np.sort(g.uniform(0.0, 1.5, k))
+    lab = gen.label_set(n, g.integers(0, m, n).astype(np.int32), 0.01, 2000 + n)
+    case_id("allen-cahn shapes n=%d k=%d m=%d 20 iterations" % (n, k, m))
+    U, pred, it = mlg.allen_cahn_ssl(lam, Phi, lab, m, tol=0.0, max_iter=20)
+    Uo, po, ito, _ = oracle.allen_cahn(lam, Phi, lab, m, tol=0.0, max_iter=20)
+    assert it == ito == 20
+    assert np.array_equal(U, Uo) and np.array_equal(pred, po)
+
+
 def test_allen_cahn_on_gpu_eigenpairs_end_to_end(mlg):
     c = gen.config1()
     pts = c["layers"][0]
