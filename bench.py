@@ -12,8 +12,9 @@ Printed as ONE JSON line with the roofline of the dominant kernel (timed
 with HIP events on the library's stream), the FP64-plain comparison (one
 vector per matvec, FP64 NFFT), the p = -10 power mean (one block product
 with L_{p,delta}^p through the Krylov power, and the eigenpair computation
-for p = -10 and p = 1), the relative error of sampled rows against the FP64
-oracle, and the oracle timed on the host cores on a bounded sample.
+for p = -10 and p = 1), Allen-Cahn steps at n = 10^7 (k = 30, m = 10), the
+relative error of sampled rows against the FP64 oracle, and the oracle timed
+on the host cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -51,6 +52,9 @@ def parse():
                     help="skip the p < 0 power-mean leg (Krylov power, eigenpairs)")
     ap.add_argument("--power-only", action="store_true",
                     help="run only the power-mean leg and print its JSON object (for profiling)")
+    ap.add_argument("--no-ac", action="store_true", help="skip the Allen-Cahn leg")
+    ap.add_argument("--ac-only", action="store_true",
+                    help="run only the Allen-Cahn leg and print its JSON object (for profiling)")
     ap.add_argument("--image", type=int, default=1000, help="image edge (n = edge^2)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (HBM counter calibration) and exit")
@@ -139,6 +143,39 @@ def power_leg(g, X, c, n, T, b):
             "eigs_k%d_tol1e-5" % c["k"]: eig}
 
 
+def allen_cahn_leg(iters=20):
+    """Allen-Cahn steps at the 10^7-node scale: n = 10^7, k = 30 eigenvectors,
+    m = 10 classes, 0.5 % labels.  Any orthonormal block serves as the basis
+    of the scheme; a seeded N(0, 1/n) block (orthonormal up to O(n^-1/2)) is
+    drawn on the device.  A fixed number of steps (tolerance 0) is timed.
+
+    Algorithmic HBM bytes per step: the chunk-major eigenvector block and Z
+    block read once each (2 k n 8), the scores read and written (2 n m 8) and
+    the labels (4 n)."""
+    import torch
+    import paper_2007_05239_amd.mlg as mlg
+    n, k, m = 10_000_000, 30, 10
+    g = torch.Generator(device="cuda").manual_seed(20070523)
+    lab = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    idx = torch.randperm(n, device="cuda", generator=g)[: n // 200]
+    lab[idx] = torch.randint(0, m, (idx.numel(),), device="cuda", dtype=torch.int32, generator=g)
+    E = torch.randn((k, n), dtype=torch.float64, device="cuda", generator=g) / math.sqrt(n)
+    ev = torch.linspace(0.0, 1.5, k, dtype=torch.float64, device="cuda")
+    mlg.allen_cahn_ssl(ev, E.t(), lab, m, tol=0.0, max_iter=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, it = mlg.allen_cahn_ssl(ev, E.t(), lab, m, tol=0.0, max_iter=iters)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    per = el / it
+    byts = 2.0 * k * n * 8 + 2.0 * n * m * 8 + 4.0 * n
+    return {"workload": "n1e7_k30_m10_labels0.5pct", "n": n, "k": k, "m": m, "iterations": it,
+            "seconds_incl_setup": round(el, 4), "ms_per_iteration": round(per * 1e3, 3),
+            "algorithmic_bytes_per_iteration": byts,
+            "achieved_GBps": round(byts / per / 1e9, 1),
+            "hbm_frac": round(byts / per / 1e9 / HBM_PEAK_GBS, 3)}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -148,6 +185,9 @@ def main():
         sys.exit(2)
     if a.copy_calib:
         copy_calibration(a.copy_calib)
+        return
+    if a.ac_only:
+        print(json.dumps({"allen_cahn": allen_cahn_leg()}))
         return
     import torch
     import paper_2007_05239_amd.mlg as mlg
@@ -225,6 +265,7 @@ def main():
         g64.close()
 
     power = None if a.no_power else power_leg(g, X, c, n, T, b)
+    ac = None if a.no_ac else allen_cahn_leg()
 
     # accuracy on sampled rows and the CPU oracle on the same sample
     acc = None
@@ -260,8 +301,8 @@ def main():
                       "block": b, "layer_params": infos, "plan_s": round(plan_s, 3),
                       "parallelism": "single GPU"},
            "stages_ms": {k: round(v, 4) for k, v in st.items()},
-           "roofline": roof, "fp64_plain": fp64, "power_mean": power, "accuracy": acc,
-           "cpu_baseline": cpu}
+           "roofline": roof, "fp64_plain": fp64, "power_mean": power, "allen_cahn": ac,
+           "accuracy": acc, "cpu_baseline": cpu}
     g.close()
     print(json.dumps(out))
 

@@ -85,4 +85,19 @@ void upload(DevBuf<T> &dst, const T *src, size_t count, bool src_on_device, hipS
                            src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
 }
 
+// Copies a column-major rows x cols block between leading dimensions dld and
+// sld (elements) with contiguous 1-D copies: one copy when both blocks are
+// dense, else one per column.
+template <class T>
+void copy_cols(T *dst, int64_t dld, const T *src, int64_t sld, int64_t rows, int64_t cols,
+               hipMemcpyKind kind, hipStream_t s) {
+    if (rows == 0 || cols == 0) return;
+    if (dld == rows && sld == rows) {
+        MLG_HIP(hipMemcpyAsync(dst, src, sizeof(T) * rows * cols, kind, s));
+        return;
+    }
+    for (int64_t c = 0; c < cols; ++c)
+        MLG_HIP(hipMemcpyAsync(dst + c * dld, src + c * sld, sizeof(T) * rows, kind, s));
+}
+
 }  // namespace mlg

@@ -434,11 +434,9 @@ mlg_status mlg_laplacian_matvec(mlg_graph *h, int layer, int op, int b, const do
             return;
         }
         DevBuf<double> dX((size_t)g.n * b), dY((size_t)g.n * b);
-        MLG_HIP(hipMemcpy2DAsync(dX.p, g.n * 8, X, ldx * 8, g.n * 8, b, hipMemcpyHostToDevice,
-                                 g.stream));
+        copy_cols(dX.p, g.n, X, ldx, g.n, b, hipMemcpyHostToDevice, g.stream);
         graph_matvec_enqueue(g, layer, op, b, dX.p, g.n, dY.p, g.n, nullptr);
-        MLG_HIP(hipMemcpy2DAsync(Y, ldy * 8, dY.p, g.n * 8, g.n * 8, b, hipMemcpyDeviceToHost,
-                                 g.stream));
+        copy_cols(Y, ldy, dY.p, g.n, g.n, b, hipMemcpyDeviceToHost, g.stream);
         MLG_HIP(hipStreamSynchronize(g.stream));
     });
 }
@@ -566,8 +564,7 @@ mlg_status mlg_lanczos_eigs(mlg_graph *h, int layer, double p, int k, int block,
             MLG_HIP(hipMemcpyAsync(evals, ev.data(), 8 * k, hipMemcpyHostToDevice, g.stream));
         } else {
             std::copy(ev.begin(), ev.end(), evals);
-            MLG_HIP(hipMemcpy2DAsync(evecs, ldv * 8, E, g.n * 8, g.n * 8, k, hipMemcpyDeviceToHost,
-                                     g.stream));
+            copy_cols(evecs, ldv, E, g.n, g.n, k, hipMemcpyDeviceToHost, g.stream);
         }
         MLG_HIP(hipStreamSynchronize(g.stream));
     });
@@ -597,11 +594,9 @@ mlg_status mlg_power_mean_matvec(mlg_graph *h, int layer, double p, int b, const
             op.apply(layer, X, ldx, Y, ldy, false);
         } else {
             DevBuf<double> dX((size_t)g.n * b), dY((size_t)g.n * b);
-            MLG_HIP(hipMemcpy2DAsync(dX.p, g.n * 8, X, ldx * 8, g.n * 8, b, hipMemcpyHostToDevice,
-                                     g.stream));
+            copy_cols(dX.p, g.n, X, ldx, g.n, b, hipMemcpyHostToDevice, g.stream);
             op.apply(layer, dX.p, g.n, dY.p, g.n, false);
-            MLG_HIP(hipMemcpy2DAsync(Y, ldy * 8, dY.p, g.n * 8, g.n * 8, b, hipMemcpyDeviceToHost,
-                                     g.stream));
+            copy_cols(Y, ldy, dY.p, g.n, g.n, b, hipMemcpyDeviceToHost, g.stream);
         }
         MLG_HIP(hipStreamSynchronize(g.stream));
         if (steps) *steps = op.max_used;
@@ -636,7 +631,7 @@ mlg_status mlg_allen_cahn_ssl(int64_t n, int k, int m, const double *evals, cons
         if (!dev) {
             upload(dE, evals, k, false, s);
             dV.alloc((size_t)n * k);
-            MLG_HIP(hipMemcpy2DAsync(dV.p, n * 8, evecs, ldv * 8, n * 8, k, hipMemcpyHostToDevice, s));
+            copy_cols(dV.p, n, evecs, ldv, n, k, hipMemcpyHostToDevice, s);
             upload(dL, labels, n, false, s);
             dU.alloc((size_t)n * m);
             dP.alloc(n);

@@ -554,11 +554,11 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
             MLG_HIP(hipStreamSynchronize(s));
         }
         // ---- Rayleigh-Ritz on H (m x m) ----
-        MLG_HIP(hipMemcpy2DAsync(Ad.p, 8 * ldh, Hd.p, 8 * ldh, 8 * m, m, hipMemcpyDeviceToDevice, s));
+        MLG_HIP(hipMemcpyAsync(Ad.p, Hd.p, sizeof(double) * m * ldh, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, m, Ad.p, ldh, Yd.p, 40);
         MLG_LAUNCH_CHECK();
         std::vector<double> Ah((size_t)m * ldh);
-        MLG_HIP(hipMemcpy2DAsync(Ah.data(), 8 * ldh, Ad.p, 8 * ldh, 8 * m, m, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipMemcpyAsync(Ah.data(), Ad.p, sizeof(double) * m * ldh, hipMemcpyDeviceToHost, s));
         MLG_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < m; ++i) th[i] = Ah[(size_t)i * ldh + i];
         std::iota(order.begin(), order.begin() + m, 0);
