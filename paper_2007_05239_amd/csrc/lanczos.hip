@@ -31,87 +31,108 @@ constexpr int kTnMaxQ = 32;    // columns of C
 constexpr int kRB = 16;        // rows per LDS batch
 
 // ---- C = A^T B, partials per row chunk --------------------------------------
+// Thread (ty, tx) of 16 x 16 owns C[ty + 16 a][tx + 16 c] for a < NA, c < NQ
+// (NA = ceil(p / 16), NQ = ceil(q / 16)); rows pass through LDS 16 at a time.
+template <int NA, int NQ>
 __global__ __launch_bounds__(256) void k_gemm_tn_part(int64_t n, int p, int q,
                                                       const double *__restrict__ A, int64_t lda,
                                                       const double *__restrict__ B, int64_t ldb,
                                                       int64_t rc, double *__restrict__ part) {
-    __shared__ double As[kRB][kTnMaxP];
-    __shared__ double Bs[kRB][kTnMaxQ];
+    __shared__ double As[kRB][NA * 16];
+    __shared__ double Bs[kRB][NQ * 16];
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     const int64_t r0 = (int64_t)blockIdx.x * rc;
     const int64_t r1 = (r0 + rc < n) ? r0 + rc : n;
-    double acc[16][2];
+    double acc[NA][NQ];
 #pragma unroll
-    for (int a = 0; a < 16; ++a) { acc[a][0] = 0.0; acc[a][1] = 0.0; }
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) acc[a][c] = 0.0;
     for (int64_t rb = r0; rb < r1; rb += kRB) {
         const int cnt = (int)((r1 - rb) < kRB ? (r1 - rb) : kRB);
         __syncthreads();
-        for (int e = tid; e < kRB * p; e += 256) {
-            int rr = e % kRB, i = e / kRB;
-            As[rr][i] = rr < cnt ? A[rb + rr + (int64_t)i * lda] : 0.0;
+        for (int e = tid; e < kRB * NA * 16; e += 256) {
+            const int rr = e % kRB, i = e / kRB;
+            As[rr][i] = (rr < cnt && i < p) ? A[rb + rr + (int64_t)i * lda] : 0.0;
         }
-        for (int e = tid; e < kRB * q; e += 256) {
-            int rr = e % kRB, j = e / kRB;
-            Bs[rr][j] = rr < cnt ? B[rb + rr + (int64_t)j * ldb] : 0.0;
+        for (int e = tid; e < kRB * NQ * 16; e += 256) {
+            const int rr = e % kRB, j = e / kRB;
+            Bs[rr][j] = (rr < cnt && j < q) ? B[rb + rr + (int64_t)j * ldb] : 0.0;
         }
         __syncthreads();
+#pragma unroll 4
         for (int rr = 0; rr < kRB; ++rr) {
-            const double b0 = Bs[rr][tx], b1 = Bs[rr][tx + 16];
+            double bv[NQ];
 #pragma unroll
-            for (int a = 0; a < 16; ++a) {
+            for (int c = 0; c < NQ; ++c) bv[c] = Bs[rr][tx + 16 * c];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
                 const double av = As[rr][ty + 16 * a];
-                acc[a][0] += av * b0;
-                acc[a][1] += av * b1;
+#pragma unroll
+                for (int c = 0; c < NQ; ++c) acc[a][c] += av * bv[c];
             }
         }
     }
     double *o = part + (int64_t)blockIdx.x * p * q;
 #pragma unroll
-    for (int a = 0; a < 16; ++a) {
+    for (int a = 0; a < NA; ++a) {
         const int i = ty + 16 * a;
-        if (i < p) {
-            if (tx < q) o[i * q + tx] = acc[a][0];
-            if (tx + 16 < q) o[i * q + tx + 16] = acc[a][1];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) {
+            const int j = tx + 16 * c;
+            if (i < p && j < q) o[i * q + j] = acc[a][c];
         }
     }
 }
 
-// C[e] = sum_c part[c][e], c ascending.
-__global__ void k_sum_parts(int nparts, int total, const double *__restrict__ part,
-                            double *__restrict__ C) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    double s = 0.0;
-    for (int c = 0; c < nparts; ++c) s += part[(int64_t)c * total + e];
-    C[e] = s;
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
-// Out[:, j] (=, +=, -=) sum_i A[:, i] C[i][j] for the column group in blockIdx.y
-// (C row-major p x q).  mode 0: =, 1: -=.
+// C[e] = sum_c part[c][e]: one wavefront per e; lane l adds c = l, l + 64, ...
+// in order, then a fixed butterfly over the lanes.
+__global__ __launch_bounds__(256) void k_sum_parts(int nparts, int total,
+                                                   const double *__restrict__ part,
+                                                   double *__restrict__ C) {
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (e >= total) return;
+    double s = 0.0;
+    for (int c = lane; c < nparts; c += 64) s += part[(int64_t)c * total + e];
+    s = wave_sum64(s);
+    if (lane == 0) C[e] = s;
+}
+
+// Out[:, j] (=, +=, -=) sum_i A[:, i] C[i][j] for the column group of QG
+// columns in blockIdx.y (C row-major p x q).  mode 0: =, 1: -=.
+template <int QG>
 __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int p, int q,
                                                  const double *__restrict__ A, int64_t lda,
                                                  const double *__restrict__ C,
                                                  double *__restrict__ Out, int64_t ldo, int mode) {
-    __shared__ double Cs[kTnMaxP * 32];
-    const int j0 = blockIdx.y * 32;
-    const int qq = (q - j0) < 32 ? (q - j0) : 32;
-    for (int e = threadIdx.x; e < p * 32; e += 256) {
-        int i = e / 32, j = e % 32;
+    __shared__ double Cs[kTnMaxP * QG];
+    const int j0 = blockIdx.y * QG;
+    const int qq = (q - j0) < QG ? (q - j0) : QG;
+    for (int e = threadIdx.x; e < p * QG; e += 256) {
+        int i = e / QG, j = e % QG;
         Cs[e] = j < qq ? C[i * q + j0 + j] : 0.0;
     }
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (r >= n) return;
-    double acc[32];
+    double acc[QG];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+    for (int j = 0; j < QG; ++j) acc[j] = 0.0;
+#pragma unroll 4
     for (int i = 0; i < p; ++i) {
         const double a = A[r + (int64_t)i * lda];
 #pragma unroll
-        for (int j = 0; j < 32; ++j) acc[j] += a * Cs[i * 32 + j];
+        for (int j = 0; j < QG; ++j) acc[j] += a * Cs[i * QG + j];
     }
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
+    for (int j = 0; j < QG; ++j) {
         if (j < qq) {
             double *o = Out + r + (int64_t)(j0 + j) * ldo;
             *o = mode ? *o - acc[j] : acc[j];
@@ -119,66 +140,91 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int p, int q,
     }
 }
 
-// W[r, :] <- W[r, :] M (q x q row-major), in place per row.
-__global__ void k_rowmul(int64_t n, int q, double *__restrict__ W, int64_t ldw,
-                         const double *__restrict__ M) {
-    __shared__ double Ms[kTnMaxQ * kTnMaxQ];
-    for (int e = threadIdx.x; e < q * q; e += blockDim.x) Ms[(e / q) * kTnMaxQ + e % q] = M[e];
+// W[r, :] <- W[r, :] M (q x q row-major, q <= QB), in place per row: the row
+// is held in registers, each output column is formed and stored in turn.
+template <int QB>
+__global__ __launch_bounds__(256) void k_rowmul(int64_t n, int q, double *__restrict__ W,
+                                                int64_t ldw, const double *__restrict__ M) {
+    __shared__ double Ms[QB * QB];
+    for (int e = threadIdx.x; e < q * q; e += blockDim.x) Ms[(e / q) * QB + e % q] = M[e];
     __syncthreads();
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    double w[kTnMaxQ], o[kTnMaxQ];
+    double w[QB];
 #pragma unroll
-    for (int i = 0; i < kTnMaxQ; ++i) w[i] = i < q ? W[r + (int64_t)i * ldw] : 0.0;
-#pragma unroll
-    for (int j = 0; j < kTnMaxQ; ++j) {
+    for (int i = 0; i < QB; ++i) w[i] = i < q ? W[r + (int64_t)i * ldw] : 0.0;
+    for (int j = 0; j < q; ++j) {
         double s = 0.0;
-        for (int i = 0; i < q; ++i) s += w[i] * Ms[i * kTnMaxQ + j];
-        o[j] = s;
+#pragma unroll
+        for (int i = 0; i < QB; ++i)
+            if (i < q) s += w[i] * Ms[i * QB + j];
+        W[r + (int64_t)j * ldw] = s;
     }
-    for (int j = 0; j < q; ++j) W[r + (int64_t)j * ldw] = o[j];
 }
 
 // Cholesky G = R^T R (G q x q row-major, symmetric); writes Rinv (q x q
 // row-major, upper) into out[0..q*q) and R into out[q*q..2q*q); flag = 1 if a
-// pivot is not positive relative to the largest diagonal.
-__global__ void k_chol_inv(int q, const double *__restrict__ G, double *__restrict__ out,
-                           int *flag) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double R[kTnMaxQ][kTnMaxQ], Ri[kTnMaxQ][kTnMaxQ];
-    double dmax = 0.0;
-    for (int i = 0; i < q; ++i) dmax = fmax(dmax, G[i * q + i]);
-    int bad = !(dmax > 0.0);
-    for (int i = 0; i < q; ++i)
-        for (int j = 0; j < q; ++j) { R[i][j] = 0.0; Ri[i][j] = 0.0; }
-    for (int j = 0; j < q && !bad; ++j) {
-        double s = G[j * q + j];
-        for (int k = 0; k < j; ++k) s -= R[k][j] * R[k][j];
-        if (!(s > 1e-28 * dmax)) { bad = 1; break; }
-        const double rjj = sqrt(s);
-        R[j][j] = rjj;
-        for (int i = j + 1; i < q; ++i) {
-            double t = G[j * q + i];
-            for (int k = 0; k < j; ++k) t -= R[k][j] * R[k][i];
-            R[j][i] = t / rjj;
-        }
+// pivot is not positive relative to the largest diagonal.  One wavefront:
+// right-looking elimination in LDS (each entry receives its updates in the
+// order k = 0, 1, ...), then one lane per column of the inverse (back
+// substitution).
+__global__ __launch_bounds__(64) void k_chol_inv(int q, const double *__restrict__ G,
+                                                 double *__restrict__ out, int *flag) {
+    __shared__ double A[kTnMaxQ][kTnMaxQ + 1];
+    __shared__ double Ri[kTnMaxQ][kTnMaxQ + 1];
+    __shared__ int bad_s;
+    __shared__ double dmax_s;
+    const int lane = threadIdx.x;
+    for (int e = lane; e < q * q; e += 64) {
+        A[e / q][e % q] = G[e];
+        Ri[e / q][e % q] = 0.0;
     }
+    __syncthreads();
+    if (lane == 0) {
+        double dmax = 0.0;
+        for (int i = 0; i < q; ++i) dmax = fmax(dmax, A[i][i]);
+        dmax_s = dmax;
+        bad_s = !(dmax > 0.0);
+    }
+    __syncthreads();
+    const double dmax = dmax_s;
+    for (int j = 0; j < q && !bad_s; ++j) {
+        if (lane == 0) {
+            const double sv = A[j][j];
+            if (!(sv > 1e-28 * dmax)) bad_s = 1;
+            else A[j][j] = sqrt(sv);
+        }
+        __syncthreads();
+        if (bad_s) break;
+        const double rjj = A[j][j];
+        for (int i = j + 1 + lane; i < q; i += 64) A[j][i] = A[j][i] / rjj;
+        __syncthreads();
+        const int w = q - j - 1;
+        for (int e = lane; e < w * w; e += 64) {
+            const int i = j + 1 + e / w, l = j + 1 + e % w;
+            if (l >= i) A[i][l] -= A[j][i] * A[j][l];
+        }
+        __syncthreads();
+    }
+    const int bad = bad_s;
     if (!bad) {
-        for (int j = q - 1; j >= 0; --j) {
-            Ri[j][j] = 1.0 / R[j][j];
+        for (int j = lane; j < q; j += 64) {
+            Ri[j][j] = 1.0 / A[j][j];
             for (int i = j - 1; i >= 0; --i) {
-                double s = 0.0;
-                for (int k = i + 1; k <= j; ++k) s += R[i][k] * Ri[k][j];
-                Ri[i][j] = -s / R[i][i];
+                double sv = 0.0;
+                for (int k = i + 1; k <= j; ++k) sv += A[i][k] * Ri[k][j];
+                Ri[i][j] = -sv / A[i][i];
             }
         }
     }
-    for (int i = 0; i < q; ++i)
-        for (int j = 0; j < q; ++j) {
-            out[i * q + j] = Ri[i][j];
-            out[q * q + i * q + j] = R[i][j];
-        }
-    flag[0] = bad;
+    __syncthreads();
+    for (int e = lane; e < q * q; e += 64) {
+        const int i = e / q, j = e % q;
+        const bool up = !bad && i <= j;
+        out[e] = up ? Ri[i][j] : 0.0;
+        out[q * q + e] = up ? A[i][j] : 0.0;
+    }
+    if (lane == 0) flag[0] = bad;
 }
 
 // C (m+b) x b row-major from CGS -> H columns [m, m+b) and rows; the diagonal
@@ -208,14 +254,22 @@ __global__ void k_store_R(int m, int b, const double *__restrict__ R, double *__
 
 // Parallel cyclic Jacobi (round-robin pairing) for a symmetric m x m matrix
 // in one workgroup.  A (ldh) is overwritten: diag = eigenvalues; Y (m x m,
-// row-major, column c = eigenvector c).
-__global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ A, int lda,
-                                                double *__restrict__ Y, int max_sweeps) {
+// row-major, column c = eigenvector c).  AL / YL: A / Y are worked on in LDS
+// (dynamic shared memory, A first) and written back at the end.
+template <bool AL, bool YL>
+__global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ Ag, int ldag,
+                                                double *__restrict__ Yg, int max_sweeps) {
     __shared__ double cs[kTnMaxP / 2 + 1], sn[kTnMaxP / 2 + 1];
     __shared__ int pp[kTnMaxP / 2 + 1], qq[kTnMaxP / 2 + 1];
     __shared__ int rotated;
+    extern __shared__ double jsm[];
+    double *A = AL ? jsm : Ag;
+    const int lda = AL ? m : ldag;
+    double *Y = YL ? (AL ? jsm + m * m : jsm) : Yg;
     const int tid = threadIdx.x;
     const int me = m + (m & 1);  // even, with a dummy index m if odd
+    if (AL)
+        for (int e = tid; e < m * m; e += 256) A[e] = Ag[(e / m) * ldag + e % m];
     for (int e = tid; e < m * m; e += 256) Y[e] = (e / m == e % m) ? 1.0 : 0.0;
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -280,6 +334,11 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ A, i
         if (!rotated) break;
         __syncthreads();
     }
+    __syncthreads();
+    if (AL)
+        for (int e = tid; e < m * m; e += 256) Ag[(e / m) * ldag + e % m] = A[e];
+    if (YL)
+        for (int e = tid; e < m * m; e += 256) Yg[e] = Y[e];
 }
 
 // Residual norms ||S y_c|| for the selected Ritz columns sel[0..ns).
@@ -415,17 +474,44 @@ struct Lz {
     }
     // Cout (p x q row-major) = A^T B
     void tn(int p, int q, const double *A, int64_t lda, const double *B, int64_t ldb, double *Cout) {
-        hipLaunchKernelGGL(k_gemm_tn_part, dim3(nchunks), dim3(256), 0, s, n, p, q, A, lda, B, ldb, rc,
-                           part.p);
+        MLG_REQUIRE(p >= 1 && p <= kTnMaxP && q >= 1 && q <= kTnMaxQ, MLG_ERR_ARG, "tn shape");
+        const int na = ceil_div(p, 16), nq = ceil_div(q, 16);
+        const dim3 g(nchunks), t(256);
+#define MLG_TN(NA)                                                                              \
+    case NA:                                                                                    \
+        if (nq == 1)                                                                            \
+            hipLaunchKernelGGL((k_gemm_tn_part<NA, 1>), g, t, 0, s, n, p, q, A, lda, B, ldb, rc, \
+                               part.p);                                                         \
+        else                                                                                    \
+            hipLaunchKernelGGL((k_gemm_tn_part<NA, 2>), g, t, 0, s, n, p, q, A, lda, B, ldb, rc, \
+                               part.p);                                                         \
+        break;
+        switch (na) {
+            MLG_TN(1) MLG_TN(2) MLG_TN(3) MLG_TN(4) MLG_TN(5) MLG_TN(6) MLG_TN(7) MLG_TN(8)
+            MLG_TN(9) MLG_TN(10) MLG_TN(11) MLG_TN(12) MLG_TN(13) MLG_TN(14) MLG_TN(15) MLG_TN(16)
+        }
+#undef MLG_TN
         MLG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(p * q, 256)), dim3(256), 0, s, nchunks, p * q,
+        hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(p * q, 4)), dim3(256), 0, s, nchunks, p * q,
                            part.p, Cout);
         MLG_LAUNCH_CHECK();
     }
     void nn(int p, int q, const double *A, int64_t lda, const double *Cm, double *Out, int64_t ldo,
             int mode) {
-        hipLaunchKernelGGL(k_gemm_nn, dim3(ceil_div(n, 256), ceil_div(q, 32)), dim3(256), 0, s, n, p,
-                           q, A, lda, Cm, Out, ldo, mode);
+        if (q <= 16)
+            hipLaunchKernelGGL(k_gemm_nn<16>, dim3(ceil_div(n, 256), 1), dim3(256), 0, s, n, p, q, A,
+                               lda, Cm, Out, ldo, mode);
+        else
+            hipLaunchKernelGGL(k_gemm_nn<32>, dim3(ceil_div(n, 256), ceil_div(q, 32)), dim3(256), 0, s,
+                               n, p, q, A, lda, Cm, Out, ldo, mode);
+        MLG_LAUNCH_CHECK();
+    }
+    void rowmul(int q, double *W, int64_t ldw, const double *M) {
+        const dim3 g(ceil_div(n, 256)), t(256);
+        if (q <= 4) hipLaunchKernelGGL(k_rowmul<4>, g, t, 0, s, n, q, W, ldw, M);
+        else if (q <= 8) hipLaunchKernelGGL(k_rowmul<8>, g, t, 0, s, n, q, W, ldw, M);
+        else if (q <= 16) hipLaunchKernelGGL(k_rowmul<16>, g, t, 0, s, n, q, W, ldw, M);
+        else hipLaunchKernelGGL(k_rowmul<32>, g, t, 0, s, n, q, W, ldw, M);
         MLG_LAUNCH_CHECK();
     }
     // W (n x q) -> orthonormal, R (q x q upper) with W_in = W_out R.  Returns
@@ -442,8 +528,7 @@ struct Lz {
                                    hipMemcpyDeviceToHost, s));
             MLG_HIP(hipStreamSynchronize(s));
             if (bad) return false;
-            hipLaunchKernelGGL(k_rowmul, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, q, W, ldw, RR.p);
-            MLG_LAUNCH_CHECK();
+            rowmul(q, W, ldw, RR.p);
         }
         // R = R2 R1 (upper triangular)
         Rhost.assign(q * q, 0.0);
@@ -555,7 +640,15 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
         }
         // ---- Rayleigh-Ritz on H (m x m) ----
         MLG_HIP(hipMemcpyAsync(Ad.p, Hd.p, sizeof(double) * m * ldh, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, m, Ad.p, ldh, Yd.p, 40);
+        if (2 * m * m * 8 <= 60 * 1024)
+            hipLaunchKernelGGL((k_jacobi<true, true>), dim3(1), dim3(256), 2 * m * m * 8, s, m, Ad.p, ldh,
+                               Yd.p, 40);
+        else if (m * m * 8 <= 60 * 1024)
+            hipLaunchKernelGGL((k_jacobi<true, false>), dim3(1), dim3(256), m * m * 8, s, m, Ad.p, ldh,
+                               Yd.p, 40);
+        else
+            hipLaunchKernelGGL((k_jacobi<false, false>), dim3(1), dim3(256), 0, s, m, Ad.p, ldh, Yd.p,
+                               40);
         MLG_LAUNCH_CHECK();
         std::vector<double> Ah((size_t)m * ldh);
         MLG_HIP(hipMemcpyAsync(Ah.data(), Ad.p, sizeof(double) * m * ldh, hipMemcpyDeviceToHost, s));
