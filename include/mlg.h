@@ -66,6 +66,10 @@ typedef enum {
 #define MLG_METHOD_DIRECT 0 /* O(n^2) tiled direct sum (Sec. 2 case (i))       */
 #define MLG_METHOD_NFFT 1   /* NFFT fast summation (Algorithm 1, Sec. 4)       */
 
+/* Kernel functions K of the weight w(x_i, x_j) = K(x_i - x_j) (Sec. 2, Sec. 4). */
+#define MLG_KERNEL_GAUSSIAN 0  /* exp(-||y||^2 / sigma^2)                        */
+#define MLG_KERNEL_LAPLACIAN 1 /* exp(-||y|| / sigma), direct summation only     */
+
 /* operator selector for mlg_laplacian_matvec */
 #define MLG_OP_NADJ 0 /* D^-1/2 W D^-1/2 (one layer) or I - L_1 (layer = -1) */
 #define MLG_OP_LSYM 1 /* L_sym (one layer) or L_1 (layer = -1)               */
@@ -89,7 +93,12 @@ typedef enum {
  *   p_reg      smoothness degree of the regularisation, 1..12.
  *   bin        bin edge in grid cells used to group points (1, 2 or 4;
  *              0 = 1).
- * Ignored for MLG_METHOD_DIRECT except `precision`.
+ *   kernel     MLG_KERNEL_GAUSSIAN (0) or MLG_KERNEL_LAPLACIAN.  The
+ *              Laplacian RBF has a cusp at the origin, so its Fourier
+ *              coefficients decay only algebraically and Algorithm 1 (no
+ *              near-field correction) cannot reach 1e-4: NFFT layers with it
+ *              return MLG_ERR_NOT_IMPL.
+ * Ignored for MLG_METHOD_DIRECT except `precision` and `kernel`.
  */
 typedef struct {
     int method;
@@ -99,6 +108,7 @@ typedef struct {
     double eps_B;
     int p_reg;
     int bin;
+    int kernel;
 } mlg_kparams;
 
 typedef struct mlg_graph mlg_graph;
@@ -130,6 +140,41 @@ const char *mlg_version(void);
 mlg_status mlg_graph_create(mlg_graph **out, int64_t n, int T, const int *d,
                             const double *const *points, const double *sigma,
                             const mlg_kparams *kp, int flags, void *stream);
+
+/*
+ * Feature grouping (Sec. 7): a multilayer graph whose layer t uses the
+ * feature columns of group t of one n x D feature matrix, so that data with
+ * D >= 4 features can use layers of dimension <= 3 (NFFT) that are merged
+ * again by the power mean (Sec. 2).
+ *   features    n x D row-major FP64 (host or device per flags; only read
+ *               during the call).
+ *   T           groups (layers), 1..1024.
+ *   group_dim   T group sizes d_t (1..3 for NFFT layers, 1..16 for direct).
+ *   group_cols  the groups' feature indices (0..D-1), concatenated in layer
+ *               order: sum_t d_t entries, host memory.
+ *   sigma, kp, flags, stream   as for mlg_graph_create.
+ * The layers are exactly those mlg_graph_create builds from the gathered
+ * columns.
+ */
+mlg_status mlg_graph_create_grouped(mlg_graph **out, int64_t n, int D, const double *features,
+                                    int T, const int *group_dim, const int *group_cols,
+                                    const double *sigma, const mlg_kparams *kp, int flags,
+                                    void *stream);
+
+/*
+ * Kernel width from the data: the median of the pairwise Euclidean distances
+ * ||x_a - x_b||_2 (a < b) between s sampled nodes, over the d feature columns
+ * cols (NULL: 0..d-1) of the n x D row-major feature matrix; for an even
+ * number of pairs, the mean of the two middle values.  The paper tunes sigma
+ * by a grid search (Sec. 6); this is the data-driven choice the synthetic
+ * workloads use.  Each squared distance is summed over the columns in order
+ * without fused multiply-add, then rounded to its square root.
+ *   sample   s distinct node indices (host memory), 2 <= s <= min(n, 8192).
+ *   sigma    out (host).
+ */
+mlg_status mlg_median_pairwise_distance(int64_t n, int D, const double *features, int d,
+                                        const int *cols, int s, const int64_t *sample,
+                                        double *sigma, int flags, void *stream);
 
 mlg_status mlg_graph_destroy(mlg_graph *g);
 

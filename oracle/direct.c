@@ -6,7 +6,10 @@
  * summation approximates (Sec. 4, eq. for (W~v)_i, with the self term removed
  * as in the W = W~ - K(0) I identity; Sec. 2 for the zero diagonal):
  *
- *     y_i = sum_{j != i} exp(-||x_i - x_j||^2 / sigma^2) * x_j
+ *     y_i = sum_{j != i} K(x_i - x_j) * x_j,
+ *
+ * K(y) = exp(-||y||^2 / sigma^2) (Gaussian, kernel 0) or exp(-||y|| / sigma)
+ * (Laplacian RBF, kernel 1), the two kernels Sec. 4 names.
  *
  * The squared distance is summed in coordinate order from the differences
  * (x_ik - x_jk), so w_ij and w_ji are the same bits.  Each output uses
@@ -33,10 +36,11 @@ static inline void neumaier_add(double *s, double *c, double v) {
  * Y:      nrows x b column-major with leading dim ldy.
  * Returns 0, or -1 for a bad argument.
  */
-int oracle_kernel_rows(int64_t n, int d, const double *points, double sigma,
-                       int64_t nrows, const int64_t *rows, int b,
-                       const double *X, int64_t ldx, double *Y, int64_t ldy) {
+int oracle_kernel_rows_k(int64_t n, int d, const double *points, double sigma, int kernel,
+                         int64_t nrows, const int64_t *rows, int b,
+                         const double *X, int64_t ldx, double *Y, int64_t ldy) {
     if (n < 0 || d < 1 || sigma <= 0.0 || b < 1 || nrows < 0) return -1;
+    if (kernel != 0 && kernel != 1) return -1;
     const double inv_s2 = 1.0 / (sigma * sigma);
     int bad = 0;
 #pragma omp parallel
@@ -57,7 +61,7 @@ int oracle_kernel_rows(int64_t n, int d, const double *points, double sigma,
                     double dk = xi[k] - xj[k];
                     r2 += dk * dk;
                 }
-                double w = exp(-r2 * inv_s2);
+                double w = kernel == 0 ? exp(-r2 * inv_s2) : exp(-sqrt(r2) / sigma);
                 for (int v = 0; v < b; ++v) neumaier_add(&s[v], &c[v], w * X[j + v * ldx]);
             }
             for (int v = 0; v < b; ++v) Y[r + v * ldy] = s[v] + c[v];
@@ -67,11 +71,9 @@ int oracle_kernel_rows(int64_t n, int d, const double *points, double sigma,
     return bad ? -1 : 0;
 }
 
-/* Degrees deg(x_i) = sum_{j != i} w_ij (Sec. 2), same summation as above. */
-int oracle_degrees(int64_t n, int d, const double *points, double sigma, double *deg) {
-    double *ones = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    for (int64_t i = 0; i < n; ++i) ones[i] = 1.0;
-    int rc = oracle_kernel_rows(n, d, points, sigma, n, NULL, 1, ones, n, deg, n);
-    free(ones);
-    return rc;
+/* The Gaussian kernel (kernel 0). */
+int oracle_kernel_rows(int64_t n, int d, const double *points, double sigma,
+                       int64_t nrows, const int64_t *rows, int b,
+                       const double *X, int64_t ldx, double *Y, int64_t ldy) {
+    return oracle_kernel_rows_k(n, d, points, sigma, 0, nrows, rows, b, X, ldx, Y, ldy);
 }

@@ -1,9 +1,12 @@
-// Direct tiled summation of the Gaussian weight matrix (Sec. 2 case (i):
+// Direct tiled summation of the kernel weight matrix (Sec. 2 case (i):
 // W assembled on the fly, O(d n^2) work), zero diagonal:
-//     F_i = sum_{j != i} exp(-||x_i - x_j||^2 / sigma^2) Z_j     (b vectors)
-// The coordinates are stored centred on the bounding box and divided by
-// sigma (FP64), or multiplied by sqrt(log2 e)/sigma (FP32), so that a weight
-// is exp(-r^2) or exp2(-r^2) of the scaled squared distance.
+//     F_i = sum_{j != i} K(x_i - x_j) Z_j     (b vectors)
+// with the Gaussian K(y) = exp(-||y||^2 / sigma^2) or the Laplacian RBF
+// K(y) = exp(-||y|| / sigma) (Sec. 4 names both).  The coordinates are stored
+// centred on the bounding box and divided by sigma (FP64), or multiplied by
+// sqrt(log2 e)/sigma (FP32 Gaussian) resp. log2(e)/sigma (FP32 Laplacian), so
+// that a weight is exp(-r^2), exp2(-r^2), exp(-r) or exp2(-r) of the scaled
+// distance r.
 //
 // The exp tile x vector block contraction runs on the matrix cores: per
 // wavefront, 16 target rows against 16 source points, the 16 x 16 weight
@@ -22,9 +25,12 @@ constexpr int kDmRT = 2;       // 16-row target tiles per wavefront (MFMA kernel
 constexpr int kDmRows = 4 * kDmRT * 16;  // target rows per workgroup (4 wavefronts)
 constexpr int kDmJC = 128;     // source points per LDS stage (MFMA kernel)
 
-// Gaussian weight of a scaled squared distance (see the file header).
-__device__ inline float kweight(float r2) { return __builtin_amdgcn_exp2f(-r2); }
-__device__ inline double kweight(double r2) { return exp(-r2); }
+// Weight of a scaled squared distance (see the file header); lap selects the
+// Laplacian RBF.
+__device__ inline float kweight(float r2, int lap) {
+    return __builtin_amdgcn_exp2f(lap ? -__builtin_sqrtf(r2) : -r2);
+}
+__device__ inline double kweight(double r2, int lap) { return exp(lap ? -sqrt(r2) : -r2); }
 
 // ---- MFMA kernel ------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -61,7 +67,7 @@ struct Mfma16<double> {
 // DK = d for d <= 3 (compile time), or 0 for a runtime d <= 16; VT = vector
 // tiles of 16 (bs < 16 uses one tile with lanes v >= bs reading zeros).
 template <class T, int DK, int VT>
-__global__ __launch_bounds__(256) void k_direct_mfma(int64_t n, int d, int bs,
+__global__ __launch_bounds__(256) void k_direct_mfma(int64_t n, int d, int bs, int lap,
                                                      const T *__restrict__ x,
                                                      const T *__restrict__ Zs,
                                                      T *__restrict__ out, int64_t jchunk) {
@@ -149,7 +155,7 @@ __global__ __launch_bounds__(256) void k_direct_mfma(int64_t n, int d, int bs,
                             const T dk = yi[rt][k] - xs[k][r];
                             r2 += dk * dk;
                         }
-                    e[r] = kweight(r2);
+                    e[r] = kweight(r2, lap);
                 }
                 if (jg == row0 + rt * 16) {   // diagonal tile: zero the self pairs
 #pragma unroll
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(256) void k_bbox_mid(int64_t n, int d, const double
     if (threadIdx.x == 0) mid[k] = 0.5 * (lo[0] + hi[0]);
 }
 
-// x64 = (x - mid) / sigma, x32 = (x - mid) sqrt(log2 e) / sigma, SoA d x n.
+// x64 = (x - mid) s64, x32 = (x - mid) s32, SoA d x n.
 __global__ void k_direct_coords(int64_t n, int d, const double *__restrict__ pts,
                                 const double *__restrict__ mid, double s64, double s32,
                                 double *__restrict__ x64, float *__restrict__ x32) {
@@ -225,8 +231,8 @@ __global__ void k_direct_coords(int64_t n, int d, const double *__restrict__ pts
     }
 }
 
-void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, DevBuf<double> &x64,
-                   DevBuf<float> &x32, hipStream_t s) {
+void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, int kernel,
+                   DevBuf<double> &x64, DevBuf<float> &x32, hipStream_t s) {
     MLG_REQUIRE(d >= 1 && d <= kDirectMaxD, MLG_ERR_RANGE, "direct summation supports d <= 16");
     DevBuf<double> mid(d);
     hipLaunchKernelGGL(k_bbox_mid, dim3(d), dim3(256), 0, s, n, d, pts_dev, mid.p);
@@ -234,8 +240,9 @@ void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, DevBuf
     x64.alloc((size_t)n * d);
     x32.alloc((size_t)n * d);
     const double log2e = 1.4426950408889634;
+    const double s32 = (kernel == MLG_KERNEL_LAPLACIAN ? log2e : std::sqrt(log2e)) / sigma;
     hipLaunchKernelGGL(k_direct_coords, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, pts_dev, mid.p,
-                       1.0 / sigma, std::sqrt(log2e) / sigma, x64.p, x32.p);
+                       1.0 / sigma, s32, x64.p, x32.p);
     MLG_LAUNCH_CHECK();
     MLG_HIP(hipStreamSynchronize(s));
 }
@@ -269,7 +276,7 @@ size_t direct_part_size(int64_t n, int bs) {
 }
 
 template <class T, int DK>
-static void launch_mfma_d(int64_t n, int d, int bs, const T *x, const T *Zs, T *dst, int S,
+static void launch_mfma_d(int64_t n, int d, int bs, int lap, const T *x, const T *Zs, T *dst, int S,
                           int64_t jchunk, hipStream_t s) {
     const dim3 grid(ceil_div(n, kDmRows), S);
     switch (bs) {
@@ -278,13 +285,16 @@ static void launch_mfma_d(int64_t n, int d, int bs, const T *x, const T *Zs, T *
         case 4:
         case 8:
         case 16:
-            hipLaunchKernelGGL((k_direct_mfma<T, DK, 1>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
+            hipLaunchKernelGGL((k_direct_mfma<T, DK, 1>), grid, dim3(256), 0, s, n, d, bs, lap, x, Zs, dst,
+                               jchunk);
             break;
         case 32:
-            hipLaunchKernelGGL((k_direct_mfma<T, DK, 2>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
+            hipLaunchKernelGGL((k_direct_mfma<T, DK, 2>), grid, dim3(256), 0, s, n, d, bs, lap, x, Zs, dst,
+                               jchunk);
             break;
         case 64:
-            hipLaunchKernelGGL((k_direct_mfma<T, DK, 4>), grid, dim3(256), 0, s, n, d, bs, x, Zs, dst, jchunk);
+            hipLaunchKernelGGL((k_direct_mfma<T, DK, 4>), grid, dim3(256), 0, s, n, d, bs, lap, x, Zs, dst,
+                               jchunk);
             break;
         default: throw Error(MLG_ERR_ARG, "direct: unsupported block stride");
     }
@@ -292,8 +302,9 @@ static void launch_mfma_d(int64_t n, int d, int bs, const T *x, const T *Zs, T *
 }
 
 template <class T>
-void launch_direct(int64_t n, int d, const T *x, int bs, const T *Zs, T *Fs, T *part,
+void launch_direct(int64_t n, int d, int kernel, const T *x, int bs, const T *Zs, T *Fs, T *part,
                    size_t part_cap, hipStream_t s) {
+    const int lap = kernel == MLG_KERNEL_LAPLACIAN ? 1 : 0;
     MLG_REQUIRE(d >= 1 && d <= kDirectMaxD, MLG_ERR_RANGE, "direct summation supports d <= 16");
     int S;
     int64_t jchunk;
@@ -304,10 +315,10 @@ void launch_direct(int64_t n, int d, const T *x, int bs, const T *Zs, T *Fs, T *
         dst = part;
     }
     switch (d) {
-        case 1: launch_mfma_d<T, 1>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
-        case 2: launch_mfma_d<T, 2>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
-        case 3: launch_mfma_d<T, 3>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
-        default: launch_mfma_d<T, 0>(n, d, bs, x, Zs, dst, S, jchunk, s); break;
+        case 1: launch_mfma_d<T, 1>(n, d, bs, lap, x, Zs, dst, S, jchunk, s); break;
+        case 2: launch_mfma_d<T, 2>(n, d, bs, lap, x, Zs, dst, S, jchunk, s); break;
+        case 3: launch_mfma_d<T, 3>(n, d, bs, lap, x, Zs, dst, S, jchunk, s); break;
+        default: launch_mfma_d<T, 0>(n, d, bs, lap, x, Zs, dst, S, jchunk, s); break;
     }
     if (S > 1) {
         const int64_t total = n * bs;
@@ -317,9 +328,9 @@ void launch_direct(int64_t n, int d, const T *x, int bs, const T *Zs, T *Fs, T *
     }
 }
 
-template void launch_direct<float>(int64_t, int, const float *, int, const float *, float *, float *,
-                                   size_t, hipStream_t);
-template void launch_direct<double>(int64_t, int, const double *, int, const double *, double *,
+template void launch_direct<float>(int64_t, int, int, const float *, int, const float *, float *,
+                                   float *, size_t, hipStream_t);
+template void launch_direct<double>(int64_t, int, int, const double *, int, const double *, double *,
                                     double *, size_t, hipStream_t);
 template size_t direct_part_size<float>(int64_t, int);
 template size_t direct_part_size<double>(int64_t, int);

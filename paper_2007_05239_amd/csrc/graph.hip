@@ -111,7 +111,7 @@ static void layer_core(Graph &g, int t, int bs, StageTimer *tm) {
     } else {
         const T *x = nullptr;
         if constexpr (sizeof(T) == 8) x = L.x64.p; else x = L.x32.p;
-        launch_direct<T>(g.n, L.d, x, bs, Zs, Fs,
+        launch_direct<T>(g.n, L.d, L.kp.kernel, x, bs, Zs, Fs,
                          reinterpret_cast<T *>(g.part.p), g.part.n / sizeof(T), s);
         if (tm) MLG_HIP(hipEventRecord(tm->ev[4], s));
     }
@@ -251,7 +251,7 @@ static void compute_degrees(Graph &g, Layer &L) {
         MLG_HIP(hipMemcpyAsync(dio.p, &io, sizeof(io), hipMemcpyHostToDevice, s));
         launch_scatter_in(n, 1, 1, ones.p, n, dio.p, 1, 0, s);
         DevBuf<double> part(direct_part_size<double>(n, 1));
-        launch_direct<double>(n, L.d, L.x64.p, 1, Z.p, F.p, part.p,
+        launch_direct<double>(n, L.d, L.kp.kernel, L.x64.p, 1, Z.p, F.p, part.p,
                               part.n, s);
         launch_gather_out(n, 1, 1, ones.p, n, L.deg.p, n, dio.p, 1, 0, 0, 1.0, s);
         MLG_HIP(hipStreamSynchronize(s));
@@ -279,7 +279,7 @@ static void build_layer(Graph &g, Layer &L, const double *pts, bool dev, bool de
         p = pd.p;
     }
     L.n = n;
-    if (L.kp.method == MLG_METHOD_DIRECT) direct_coords(n, L.d, p, L.sigma, L.x64, L.x32, s);
+    if (L.kp.method == MLG_METHOD_DIRECT) direct_coords(n, L.d, p, L.sigma, L.kp.kernel, L.x64, L.x32, s);
     if (L.kp.method == MLG_METHOD_NFFT) {
         nfft_plan_layer(L, p, s);
         int w = default_window(L);
@@ -341,6 +341,12 @@ static mlg_status create_graph(mlg_graph **out, int64_t n, int T, const int *d,
                         MLG_ERR_ARG, "bad method");
             MLG_REQUIRE(kp[t].precision == 32 || kp[t].precision == 64, MLG_ERR_ARG,
                         "precision must be 32 or 64");
+            MLG_REQUIRE(kp[t].kernel == MLG_KERNEL_GAUSSIAN || kp[t].kernel == MLG_KERNEL_LAPLACIAN,
+                        MLG_ERR_ARG, "bad kernel");
+            MLG_REQUIRE(kp[t].method == MLG_METHOD_DIRECT || kp[t].kernel == MLG_KERNEL_GAUSSIAN,
+                        MLG_ERR_NOT_IMPL,
+                        "the Laplacian RBF kernel runs on the direct path only (its cusp at the "
+                        "origin needs a near-field correction that Algorithm 1 does not have)");
             if (kp[t].method == MLG_METHOD_NFFT)
                 MLG_REQUIRE(d[t] >= 1 && d[t] <= 3, MLG_ERR_RANGE, "NFFT layers need d in 1..3");
             else
@@ -377,6 +383,40 @@ mlg_status mlg_graph_create(mlg_graph **out, int64_t n, int T, const int *d,
                             const mlg_kparams *kp, int flags, void *stream) {
     return create_graph(out, n, T, d, points, sigma, kp, flags, stream,
                         (flags & MLG_SKIP_DEGREES) == 0);
+}
+
+mlg_status mlg_graph_create_grouped(mlg_graph **out, int64_t n, int D, const double *features,
+                                    int T, const int *group_dim, const int *group_cols,
+                                    const double *sigma, const mlg_kparams *kp, int flags,
+                                    void *stream) {
+    std::vector<DevBuf<double>> pts;
+    mlg_status st = guard([&] {
+        MLG_REQUIRE(out, MLG_ERR_ARG, "null argument");
+        *out = nullptr;
+        gather_feature_groups(n, D, features, (flags & MLG_DEVICE_PTRS) != 0, T, group_dim,
+                              group_cols, pts);
+    });
+    if (st != MLG_OK) return st;
+    std::vector<const double *> ptrs(T);
+    for (int t = 0; t < T; ++t) ptrs[t] = pts[t].p;
+    return create_graph(out, n, T, group_dim, ptrs.data(), sigma, kp, flags | MLG_DEVICE_PTRS,
+                        stream, (flags & MLG_SKIP_DEGREES) == 0);
+}
+
+mlg_status mlg_median_pairwise_distance(int64_t n, int D, const double *features, int d,
+                                        const int *cols, int s, const int64_t *sample,
+                                        double *sigma, int flags, void *stream) {
+    return guard([&] {
+        MLG_REQUIRE(sigma, MLG_ERR_ARG, "null argument");
+        hipStream_t st = make_stream(stream);
+        struct SD {
+            hipStream_t s;
+            bool own;
+            ~SD() { if (own) (void)hipStreamDestroy(s); }
+        } sd{st, stream == nullptr};
+        *sigma = median_pair_distance(n, D, features, (flags & MLG_DEVICE_PTRS) != 0, d, cols, s,
+                                      sample, st);
+    });
 }
 
 mlg_status mlg_graph_destroy(mlg_graph *g) {

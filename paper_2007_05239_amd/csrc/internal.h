@@ -91,13 +91,13 @@ void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s);
 
 // ---- direct.hip ---------------------------------------------------------------
 // Scaled, centred coordinates of a direct layer (d x n SoA): x64 for the
-// FP64 kernels, x32 for the FP32 kernels.
-void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, DevBuf<double> &x64,
-                   DevBuf<float> &x32, hipStream_t s);
+// FP64 kernels, x32 for the FP32 kernels; kernel = MLG_KERNEL_*.
+void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, int kernel,
+                   DevBuf<double> &x64, DevBuf<float> &x32, hipStream_t s);
 // Fs = W Zs (zero diagonal) for n points with coordinates from direct_coords;
 // part: S x n x bs column-split partials (direct_part_size elements).
 template <class T>
-void launch_direct(int64_t n, int d, const T *x, int bs, const T *Zs, T *Fs, T *part,
+void launch_direct(int64_t n, int d, int kernel, const T *x, int bs, const T *Zs, T *Fs, T *part,
                    size_t part_cap, hipStream_t s);
 template <class T>
 size_t direct_part_size(int64_t n, int bs);
@@ -162,6 +162,19 @@ struct PowerMeanOp {
 void ac_run(int64_t n, int k, int m, const double *evals_dev, const double *evecs_dev,
             int64_t ldv, const int32_t *labels_dev, const mlg_ac_params &prm, double *U_dev,
             int32_t *pred_dev, int *iters, hipStream_t s);
+
+// ---- features.hip ---------------------------------------------------------------
+// Layer point arrays (device, n x d_t row-major) of T feature groups of the
+// n x D row-major feature matrix (host or device): group t takes the columns
+// group_cols[off_t .. off_t + d_t).
+void gather_feature_groups(int64_t n, int D, const double *features, bool dev, int T,
+                           const int *group_dim, const int *group_cols,
+                           std::vector<DevBuf<double>> &pts);
+// Median of the s (s - 1) / 2 pairwise distances of the sample rows over the
+// columns cols (NULL: 0..d-1); even counts give the mean of the middle two.
+double median_pair_distance(int64_t n, int D, const double *features, bool dev, int d,
+                            const int *cols_host, int s, const int64_t *sample_host,
+                            hipStream_t stream);
 
 // ---- graph.hip ----------------------------------------------------------------
 struct Graph {

@@ -28,13 +28,16 @@ MLG_DEVICE_PTRS = 1
 MLG_SKIP_DEGREES = 2
 MLG_METHOD_DIRECT = 0
 MLG_METHOD_NFFT = 1
+MLG_KERNEL_GAUSSIAN = 0
+MLG_KERNEL_LAPLACIAN = 1
 MLG_OP_NADJ = 0
 MLG_OP_LSYM = 1
 MLG_OP_W = 2
 
 STAGES = ["scatter_in", "spread", "gather", "fft", "interp", "gather_out", "direct", "unused"]
 
-EXPORTED = ["mlg_last_error", "mlg_version", "mlg_graph_create", "mlg_graph_destroy",
+EXPORTED = ["mlg_last_error", "mlg_version", "mlg_graph_create", "mlg_graph_create_grouped",
+            "mlg_median_pairwise_distance", "mlg_graph_destroy",
             "mlg_graph_degrees", "mlg_kernel_matvec", "mlg_laplacian_matvec",
             "mlg_lanczos_eigs", "mlg_power_mean_matvec", "mlg_allen_cahn_ssl",
             "mlg_profile_stages", "mlg_graph_layer_info"]
@@ -49,7 +52,7 @@ class MlgError(RuntimeError):
 class KParams(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("precision", ctypes.c_int), ("N", ctypes.c_int),
                 ("window", ctypes.c_int), ("eps_B", ctypes.c_double), ("p_reg", ctypes.c_int),
-                ("bin", ctypes.c_int)]
+                ("bin", ctypes.c_int), ("kernel", ctypes.c_int)]
 
 
 class EigInfo(ctypes.Structure):
@@ -67,9 +70,11 @@ class ACParams(ctypes.Structure):
                 ("dt", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
 
 
-def kparams(method="nfft", precision=32, N=64, window=0, eps_B=1.0 / 16, p_reg=5, bin=1):
+def kparams(method="nfft", precision=32, N=64, window=0, eps_B=1.0 / 16, p_reg=5, bin=1,
+            kernel="gaussian"):
     m = MLG_METHOD_NFFT if method == "nfft" else MLG_METHOD_DIRECT
-    return KParams(m, precision, N, window, eps_B, p_reg, bin)
+    kk = MLG_KERNEL_LAPLACIAN if kernel == "laplacian" else MLG_KERNEL_GAUSSIAN
+    return KParams(m, precision, N, window, eps_B, p_reg, bin, kk)
 
 
 def _load():
@@ -82,6 +87,9 @@ def _load():
         "mlg_version": ([], ctypes.c_char_p),
         "mlg_graph_create": ([ctypes.POINTER(P), i64, I, P, P, P, P, I, P], I),
         "mlg_graph_destroy": ([P], I),
+        "mlg_graph_create_grouped": ([ctypes.POINTER(P), i64, I, P, I, P, P, P, P, I, P], I),
+        "mlg_median_pairwise_distance": ([i64, I, P, I, P, I, P, ctypes.POINTER(ctypes.c_double),
+                                          I, P], I),
         "mlg_graph_degrees": ([P, I, P, I], I),
         "mlg_kernel_matvec": ([i64, I, P, ctypes.c_double, ctypes.POINTER(KParams), I, P, i64, P,
                                i64, I, P], I),
@@ -151,8 +159,81 @@ def _colmajor(X):
     return X, X.shape[0], X.shape[1]
 
 
+def stride_groups(D, per_layer):
+    """Feature groups of `per_layer` columns taken at stride D // per_layer:
+    (0, s, 2s, ...), (1, s + 1, ...), ...; leftover columns (D not a multiple)
+    form a last, smaller group.  For D = 102: per_layer 2 gives (0, 51), ...,
+    (50, 101) and per_layer 3 gives (0, 34, 68), ..., (33, 67, 101) -- the
+    band pairings of Sec. 8.3 (0-based)."""
+    if per_layer < 1 or D < 1:
+        raise ValueError("need D >= 1 and per_layer >= 1")
+    s = D // per_layer
+    if s == 0:
+        return [tuple(range(D))]
+    groups = [tuple(i + k * s for k in range(per_layer)) for i in range(s)]
+    used = s * per_layer
+    if used < D:
+        groups.append(tuple(range(used, D)))
+    return groups
+
+
+def median_pairwise_distance(features, sample, cols=None):
+    """Median of the pairwise distances of the sampled rows over `cols`
+    (mlg_median_pairwise_distance); features n x D (numpy or torch CUDA)."""
+    if _is_torch(features):
+        F = features.contiguous()
+        flags = MLG_DEVICE_PTRS if F.is_cuda else 0
+        if F.is_cuda:
+            _sync()
+    else:
+        F = np.ascontiguousarray(features, dtype=np.float64)
+        flags = 0
+    n, D = int(F.shape[0]), int(F.shape[1])
+    d = D if cols is None else len(cols)
+    colarr = None if cols is None else (ctypes.c_int * d)(*[int(c) for c in cols])
+    smp = np.ascontiguousarray(sample, dtype=np.int64)
+    out = ctypes.c_double(0.0)
+    _check(_lib.mlg_median_pairwise_distance(n, D, _ptr(F)[0], d, colarr, int(smp.shape[0]),
+                                             smp.ctypes.data_as(ctypes.c_void_p),
+                                             ctypes.byref(out), flags, None))
+    return out.value
+
+
 class Graph:
     """A multilayer graph (mlg_graph_create); one layer per point set."""
+
+    @classmethod
+    def from_features(cls, features, groups, sigmas, params=None, degrees=True):
+        """Feature grouping (mlg_graph_create_grouped): layer t uses the
+        columns groups[t] of the n x D feature matrix."""
+        self = cls.__new__(cls)
+        if _is_torch(features):
+            F = features.contiguous()
+            dev = bool(F.is_cuda)
+            if dev:
+                _sync()
+        else:
+            F = np.ascontiguousarray(features, dtype=np.float64)
+            dev = False
+        self.n = int(F.shape[0])
+        self.T = len(groups)
+        D = int(F.shape[1])
+        if params is None:
+            params = [kparams() for _ in groups]
+        elif isinstance(params, KParams):
+            params = [params] * self.T
+        dims = (ctypes.c_int * self.T)(*[len(g) for g in groups])
+        flat = [int(c) for g in groups for c in g]
+        cols = (ctypes.c_int * len(flat))(*flat)
+        sarr = (ctypes.c_double * self.T)(*[float(x) for x in sigmas])
+        karr = (KParams * self.T)(*params)
+        h = ctypes.c_void_p()
+        flags = (MLG_DEVICE_PTRS if dev else 0) | (0 if degrees else MLG_SKIP_DEGREES)
+        _check(_lib.mlg_graph_create_grouped(ctypes.byref(h), self.n, D, _ptr(F)[0], self.T, dims,
+                                             cols, sarr, karr, flags, None))
+        self._h = h
+        self._keep = []
+        return self
 
     def __init__(self, layers, sigmas, params=None, device=False, degrees=True):
         self.n = int(layers[0].shape[0])

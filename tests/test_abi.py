@@ -72,3 +72,14 @@ def test_argument_errors_before_device_work():
     # null graph
     assert lib.mlg_laplacian_matvec(None, 0, 0, 1, None, 1, None, 1, 0) == mlg.MLG_ERR_ARG
     assert lib.mlg_graph_destroy(None) == mlg.MLG_OK
+
+
+def test_stride_groups():
+    import paper_2007_05239_amd.mlg as mlg
+    g2 = mlg.stride_groups(102, 2)
+    assert len(g2) == 51 and g2[0] == (0, 51) and g2[-1] == (50, 101)
+    g3 = mlg.stride_groups(102, 3)
+    assert len(g3) == 34 and g3[0] == (0, 34, 68) and g3[-1] == (33, 67, 101)
+    g = mlg.stride_groups(7, 3)
+    assert g == [(0, 2, 4), (1, 3, 5), (6,)]
+    assert sorted(c for grp in mlg.stride_groups(13, 2) for c in grp) == list(range(13))

@@ -242,6 +242,48 @@ def test_pksm_special_inputs():
     assert steps == 4 and not conv
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_laplacian_kernel_brute_force(d):
+    """Laplacian RBF exp(-||y||/sigma) (Sec. 4) against math.fsum."""
+    g = gen.rng(17 + d)
+    n = 11
+    pts = g.uniform(-1, 1, size=(n, d))
+    sigma = 0.6
+    x = g.standard_normal(n)
+    y = oracle.kernel_matvec(pts, sigma, x, kernel="laplacian")
+    for i in range(n):
+        terms = [math.exp(-math.sqrt(sum((pts[i, k] - pts[j, k]) ** 2 for k in range(d))) / sigma)
+                 * x[j] for j in range(n) if j != i]
+        assert abs(y[i] - math.fsum(terms)) <= 1e-15 * max(1.0, abs(math.fsum(terms)))
+
+
+def test_laplacian_kernel_degrees_geometric_series():
+    """Nodes 0, 1, ..., n-1 on a line: deg_i = sum_{j != i} q^|i-j|,
+    q = exp(-1/sigma), a sum of two geometric series."""
+    n, sigma = 40, 3.0
+    pts = np.arange(n, dtype=np.float64)[:, None]
+    q = math.exp(-1.0 / sigma)
+    ref = np.array([q * (1 - q ** i) / (1 - q) + q * (1 - q ** (n - 1 - i)) / (1 - q)
+                    for i in range(n)])
+    np.testing.assert_allclose(oracle.degrees(pts, sigma, "laplacian"), ref, rtol=1e-14)
+    L = oracle.Layer(pts, sigma, "laplacian")
+    Ls = np.eye(n) - oracle.dense_nadj([L])
+    # L_sym D^1/2 1 = 0 for any kernel
+    assert np.abs(Ls @ np.sqrt(L.deg)).max() <= 1e-13
+
+
+def test_median_pairwise_distance_by_hand():
+    pts = np.array([[0.0, 0.0], [3.0, 4.0], [0.0, 1.0], [6.0, 8.0]])
+    # pairs of rows 0, 1, 2: distances 5, 1, sqrt(9 + 9) -> median sqrt(18) (odd count)
+    assert oracle.median_pairwise_distance(pts, [0, 1, 2]) == math.sqrt(18.0)
+    # rows 0, 1, 3: 5, 10, 5 -> 5; all four rows: 5, 1, 10, sqrt(18), 5, sqrt(36 + 49) -> even
+    assert oracle.median_pairwise_distance(pts, [0, 1, 3]) == 5.0
+    d = sorted([5.0, 1.0, 10.0, math.sqrt(18.0), 5.0, math.sqrt(85.0)])
+    assert oracle.median_pairwise_distance(pts, [0, 1, 2, 3]) == 0.5 * (d[2] + d[3])
+    # a column subset
+    assert oracle.median_pairwise_distance(pts, [0, 1, 3], cols=[1]) == 4.0
+
+
 def test_eigs_well_separated_clusters_count():
     pts, _ = gen.gaussian_mixture(200, 2, 4, 0.01, 51, mean_low=0, mean_high=10)
     L = oracle.Layer(pts, 0.05)
