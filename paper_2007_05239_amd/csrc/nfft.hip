@@ -1425,12 +1425,84 @@ __device__ inline void fft_stages2(C2 *buf, const C2 *tw, bool inverse, int line
     }
 }
 
+// 8-point DFT in registers (radix-2 decimation in frequency), natural order
+// in and out: a[k] <- sum_n a[n] exp(-+2 pi i n k / 8) (+ for the inverse).
+template <class C2>
+__device__ inline void dft8(C2 (&a)[8], bool inverse) {
+    using T = decltype(a[0].x);
+    const T h = T(0.70710678118654752440);
+    const T sg = inverse ? T(1) : T(-1);
+    auto add = [](C2 u, C2 v) { C2 r; r.x = u.x + v.x; r.y = u.y + v.y; return r; };
+    auto sub = [](C2 u, C2 v) { C2 r; r.x = u.x - v.x; r.y = u.y - v.y; return r; };
+    // multiply by sg * i
+    auto mul_i = [sg](C2 u) { C2 r; r.x = -sg * u.y; r.y = sg * u.x; return r; };
+    // multiply by (h, sg h) resp. (-h, sg h)
+    auto mul_w1 = [h, sg](C2 u) { C2 r; r.x = h * (u.x - sg * u.y); r.y = h * (u.y + sg * u.x); return r; };
+    auto mul_w3 = [h, sg](C2 u) { C2 r; r.x = -h * (u.x + sg * u.y); r.y = h * (sg * u.x - u.y); return r; };
+    const C2 b0 = add(a[0], a[4]), b4 = sub(a[0], a[4]);
+    const C2 b1 = add(a[1], a[5]), b5 = mul_w1(sub(a[1], a[5]));
+    const C2 b2 = add(a[2], a[6]), b6 = mul_i(sub(a[2], a[6]));
+    const C2 b3 = add(a[3], a[7]), b7 = mul_w3(sub(a[3], a[7]));
+    const C2 c0 = add(b0, b2), c2 = sub(b0, b2), c1 = add(b1, b3), c3 = mul_i(sub(b1, b3));
+    const C2 c4 = add(b4, b6), c6 = sub(b4, b6), c5 = add(b5, b7), c7 = mul_i(sub(b5, b7));
+    a[0] = add(c0, c1);
+    a[4] = sub(c0, c1);
+    a[2] = add(c2, c3);
+    a[6] = sub(c2, c3);
+    a[1] = add(c4, c5);
+    a[5] = sub(c4, c5);
+    a[3] = add(c6, c7);
+    a[7] = sub(c6, c7);
+}
+
+// 64-point FFTs of the 32 lines in buf (buf[k * LDL + line], natural order
+// in and out) as 8 x 8 Cooley-Tukey: thread (line, j) takes x[8 m + j],
+// m = 0..7, does an 8-point DFT, multiplies by exp(-+2 pi i j k1 / 64), and
+// after one transpose through LDS does the 8-point DFT over j for k1 = its
+// own index:  X[k1 + 8 k2] = sum_j W64^(j k1) W8^(j k2) sum_m x[8 m + j] W8^(m k1).
+// tw[q] = exp(-2 pi i q / 64), q < 32.
+template <class C2, int LDL>
+__device__ inline void fft64_r8(C2 *buf, const C2 *tw, bool inverse) {
+    const int ln = threadIdx.x >> 3, j = threadIdx.x & 7;
+    C2 v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = buf[(8 * m + j) * LDL + ln];
+    dft8(v, inverse);
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) {
+        const int q = j * k1;
+        C2 w = tw[q & 31];
+        if (q & 32) {
+            w.x = -w.x;
+            w.y = -w.y;
+        }
+        if (inverse) w.y = -w.y;
+        const C2 u = v[k1];
+        v[k1].x = u.x * w.x - u.y * w.y;
+        v[k1].y = u.x * w.y + u.y * w.x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) buf[(8 * k1 + j) * LDL + ln] = v[k1];
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) v[n2] = buf[(8 * j + n2) * LDL + ln];
+    dft8(v, inverse);
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) buf[(j + 8 * k2) * LDL + ln] = v[k2];
+    __syncthreads();
+}
+
 template <class T, int LOGL, int LOGLINES>
 __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict__ data, FftPass p,
                                              const typename Cplx<T>::type *__restrict__ twg,
                                              const T *__restrict__ M) {
     using C2 = typename Cplx<T>::type;
     constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES, LDL = LINES + 1;
+    // 64-point lines, 32 per workgroup: 8 x 8 in registers (fft64_r8),
+    // natural order; otherwise radix-2 stages on bit-reversed input
+    constexpr bool R8 = LOGL == 6 && LOGLINES == 5;
     __shared__ C2 buf[L * LDL];
     __shared__ C2 tw[L / 2];
     for (int j = threadIdx.x; j < L / 2; j += blockDim.x) tw[j] = twg[j];
@@ -1464,11 +1536,12 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
         const int cc = e & (C - 1);
         const int k = (e >> p.logC) & (L - 1);
         const int oo = e >> (p.logC + LOGL);
-        const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
+        const int rk = R8 ? k : (int)(__brev((unsigned)k) >> (32 - LOGL));
         buf[rk * LDL + (oo << p.logC) + cc] = val[it];
     }
     __syncthreads();
-    fft_stages2<C2, LOGL, LDL>(buf, tw, p.mode == 1, LOGLINES);
+    if constexpr (R8) fft64_r8<C2, LDL>(buf, tw, p.mode == 1);
+    else fft_stages2<C2, LOGL, LDL>(buf, tw, p.mode == 1, LOGLINES);
     if (p.mode == 2) {
         T m[PER];
 #pragma unroll
@@ -1494,19 +1567,23 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
             buf[i] = v;
         }
         __syncthreads();
+        if constexpr (R8) {
+            fft64_r8<C2, LDL>(buf, tw, true);
+        } else {
 #pragma unroll
-        for (int it = 0; it < PER; ++it) {
-            const int e = threadIdx.x + 256 * it;
-            const int ln = e & (LINES - 1), k = e >> LOGLINES;
-            const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
-            if (k < rk) {
-                const C2 t0 = buf[k * LDL + ln];
-                buf[k * LDL + ln] = buf[rk * LDL + ln];
-                buf[rk * LDL + ln] = t0;
+            for (int it = 0; it < PER; ++it) {
+                const int e = threadIdx.x + 256 * it;
+                const int ln = e & (LINES - 1), k = e >> LOGLINES;
+                const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
+                if (k < rk) {
+                    const C2 t0 = buf[k * LDL + ln];
+                    buf[k * LDL + ln] = buf[rk * LDL + ln];
+                    buf[rk * LDL + ln] = t0;
+                }
             }
+            __syncthreads();
+            fft_stages2<C2, LOGL, LDL>(buf, tw, true, LOGLINES);
         }
-        __syncthreads();
-        fft_stages2<C2, LOGL, LDL>(buf, tw, true, LOGLINES);
     }
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
