@@ -55,24 +55,67 @@ __device__ inline void load_block_row(const double *__restrict__ X, int64_t ldx,
         x[j] = (j < vgw && v0 + j < b) ? X[i + (int64_t)(v0 + j) * ldx] : 0.0;
 }
 
+// FP32 layer slices are written through an LDS tile of the block's 256 rows
+// (row-major, bs + 1 floats per row), so that each block stores one
+// contiguous, fully coalesced region of the slice; FP64 slices are stored
+// row by row.  kIoTile: the largest block stride with an LDS tile.  (The
+// exit kernel reads its slices row by row: one wavefront's rows are already
+// one contiguous region there, and an LDS round trip per layer costs more
+// than it saves.)
+constexpr int kIoTile = 32;
+
 __global__ __launch_bounds__(256) void k_scatter_in(int64_t n, int b, int bs,
                                                     const double *__restrict__ X, int64_t ldx,
                                                     const LayerIO *__restrict__ L, int nl,
                                                     int use_dinv) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float tile[256 * (kIoTile + 1)];
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t i = i0 + threadIdx.x;
+    const bool live = i < n;
+    const int rows = (n - i0) < 256 ? (int)(n - i0) : 256;
     const int vgw = bs < kIoVG ? bs : kIoVG;
-    for (int v0 = 0; v0 < bs; v0 += vgw) {
-        double x[kIoVG];
-        load_block_row(X, ldx, i, b, v0, vgw, x);
-        for (int t = 0; t < nl; ++t) {
-            const LayerIO d = L[t];
-            const double di = use_dinv ? d.dinv[i] : 1.0;
-            double z[kIoVG];
+    const int ng = (bs + vgw - 1) / vgw;
+    const bool tiled = bs <= kIoTile;
+    const int ldt = bs + 1;
+    constexpr int NG = kIoTile / kIoVG;
+    double x[NG][kIoVG];
 #pragma unroll
-            for (int j = 0; j < kIoVG; ++j) z[j] = use_dinv ? x[j] * di : x[j];
-            if (d.is64) store_row<double>(d.Z, i * bs + v0, z, vgw);
-            else store_row<float>(d.Z, i * bs + v0, z, vgw);
+    for (int gi = 0; gi < NG; ++gi) {
+        if (tiled && live && gi < ng) load_block_row(X, ldx, i, b, gi * vgw, vgw, x[gi]);
+        else
+#pragma unroll
+            for (int j = 0; j < kIoVG; ++j) x[gi][j] = 0.0;
+    }
+    for (int t = 0; t < nl; ++t) {
+        const LayerIO d = L[t];
+        if (tiled && !d.is64) {
+            const double di = (use_dinv && live) ? d.dinv[i] : 1.0;
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi)
+                if (gi < ng)
+#pragma unroll
+                    for (int j = 0; j < kIoVG; ++j)
+                        if (j < vgw)
+                            tile[threadIdx.x * ldt + gi * vgw + j] =
+                                (float)(use_dinv ? x[gi][j] * di : x[gi][j]);
+            __syncthreads();
+            float *dst = reinterpret_cast<float *>(d.Z) + i0 * bs;
+            for (int e = threadIdx.x; e < rows * bs; e += 256) {
+                const int r = e / bs, c = e - r * bs;
+                dst[e] = tile[r * ldt + c];
+            }
+            __syncthreads();
+        } else if (live) {
+            const double di = use_dinv ? d.dinv[i] : 1.0;
+            for (int v0 = 0; v0 < bs; v0 += vgw) {
+                double xr[kIoVG];
+                load_block_row(X, ldx, i, b, v0, vgw, xr);
+                double z[kIoVG];
+#pragma unroll
+                for (int j = 0; j < kIoVG; ++j) z[j] = use_dinv ? xr[j] * di : xr[j];
+                if (d.is64) store_row<double>(d.Z, i * bs + v0, z, vgw);
+                else store_row<float>(d.Z, i * bs + v0, z, vgw);
+            }
         }
     }
 }
