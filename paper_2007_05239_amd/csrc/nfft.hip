@@ -1393,6 +1393,7 @@ struct FftPass {
     int mode;
     int logC, logOB;     // workgroup tile: C = 2^logC columns, OB = 2^logOB outers
     int64_t nachunk;     // ceil(A / C)
+    int flat;            // lines numbered o * A + a, LINES consecutive ones per workgroup
 };
 
 template <class C2, int LOGL, int LDL>
@@ -1460,10 +1461,14 @@ __device__ inline void dft8(C2 (&a)[8], bool inverse) {
 // m = 0..7, does an 8-point DFT, multiplies by exp(-+2 pi i j k1 / 64), and
 // after one transpose through LDS does the 8-point DFT over j for k1 = its
 // own index:  X[k1 + 8 k2] = sum_j W64^(j k1) W8^(j k2) sum_m x[8 m + j] W8^(m k1).
-// tw[q] = exp(-2 pi i q / 64), q < 32.
+// tw[q] = exp(-2 pi i q / 64), q < 32.  Lines are the fastest thread index
+// (line = t mod 32, j = t / 32), so every LDS access of a half-wavefront
+// touches 16 consecutive lines of one row (no bank conflicts) and the
+// twiddle reads are broadcasts.  The first write-back goes to the slots the
+// thread itself read, so it needs no barrier.
 template <class C2, int LDL>
 __device__ inline void fft64_r8(C2 *buf, const C2 *tw, bool inverse) {
-    const int ln = threadIdx.x >> 3, j = threadIdx.x & 7;
+    const int ln = threadIdx.x & 31, j = threadIdx.x >> 5;
     C2 v[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) v[m] = buf[(8 * m + j) * LDL + ln];
@@ -1481,7 +1486,6 @@ __device__ inline void fft64_r8(C2 *buf, const C2 *tw, bool inverse) {
         v[k1].x = u.x * w.x - u.y * w.y;
         v[k1].y = u.x * w.y + u.y * w.x;
     }
-    __syncthreads();
 #pragma unroll
     for (int k1 = 0; k1 < 8; ++k1) buf[(8 * k1 + j) * LDL + ln] = v[k1];
     __syncthreads();
@@ -1492,6 +1496,113 @@ __device__ inline void fft64_r8(C2 *buf, const C2 *tw, bool inverse) {
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) buf[(j + 8 * k2) * LDL + ln] = v[k2];
     __syncthreads();
+}
+
+// 64-point FFTs (the 8 x 8 split of fft64_r8) of two lines per thread in
+// an LDS array with element k of a line at buf[off + k * KS]: slot s is the
+// thread's line of index 32 s + (t mod 32), j = t / 32; act[s] says whether
+// that line exists.  Every thread reaches every barrier.
+template <class C2, int KS>
+__device__ inline void fft64_r8_two(C2 *buf, const C2 *tw, bool inverse, const int (&off)[2],
+                                    const bool (&act)[2]) {
+    const int j = threadIdx.x >> 5;
+    C2 v[2][8];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!act[sl]) continue;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[sl][m] = buf[off[sl] + (8 * m + j) * KS];
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!act[sl]) continue;
+        dft8(v[sl], inverse);
+#pragma unroll
+        for (int k1 = 1; k1 < 8; ++k1) {
+            const int q = j * k1;
+            C2 w = tw[q & 31];
+            if (q & 32) {
+                w.x = -w.x;
+                w.y = -w.y;
+            }
+            if (inverse) w.y = -w.y;
+            const C2 u = v[sl][k1];
+            v[sl][k1].x = u.x * w.x - u.y * w.y;
+            v[sl][k1].y = u.x * w.y + u.y * w.x;
+        }
+        // the slots this thread read: no other thread touches them
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) buf[off[sl] + (8 * k1 + j) * KS] = v[sl][k1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!act[sl]) continue;
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) v[sl][n2] = buf[off[sl] + (8 * j + n2) * KS];
+        dft8(v[sl], inverse);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+        if (!act[sl]) continue;
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) buf[off[sl] + (j + 8 * k2) * KS] = v[sl][k2];
+    }
+    __syncthreads();
+}
+
+// The x and y passes of one z plane of a 64^3 grid (one workgroup per plane
+// and complex vector pair), held in LDS as buf[y * 65 + x]:
+//   INV = 0: x forward on all 64 rows, y forward on the N + 1 band x
+//            columns; stores the entries with x and y both in the band (the
+//            only ones the z pass and its inverse read);
+//   INV = 1: reads those entries (zero elsewhere), y inverse on the band x
+//            columns, x inverse on all rows; stores the whole plane.
+// The same transforms as the separate x and y passes, without the
+// intermediate round trip of the x-transformed plane through memory.
+template <class C2, int INV>
+__global__ __launch_bounds__(256) void k_fft_xy64(C2 *__restrict__ data, int N, int64_t qstr,
+                                                  const C2 *__restrict__ twg) {
+    constexpr int L = 64, LD = 65, PER = L * L / 256;
+    __shared__ C2 buf[L * LD];
+    __shared__ C2 tw[L / 2];
+    const int t = threadIdx.x;
+    if (t < L / 2) tw[t] = twg[t];
+    data += (int64_t)blockIdx.y * qstr + (int64_t)blockIdx.x * (L * L);
+    C2 val[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int e = t + 256 * it;
+        const int y = e >> 6, x = e & (L - 1);
+        val[it].x = 0;
+        val[it].y = 0;
+        if (!INV || (in_band(x, N, L) && in_band(y, N, L))) val[it] = data[e];
+    }
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int e = t + 256 * it;
+        buf[(e >> 6) * LD + (e & (L - 1))] = val[it];
+    }
+    __syncthreads();
+    const int l = t & 31;
+    const int rows[2] = {l * LD, (l + 32) * LD};
+    const bool all[2] = {true, true};
+    const int cols[2] = {band_index(l, N, L), l + 32 <= N ? band_index(l + 32, N, L) : 0};
+    const bool band[2] = {l <= N, l + 32 <= N};
+    if (!INV) {
+        fft64_r8_two<C2, 1>(buf, tw, false, rows, all);
+        fft64_r8_two<C2, LD>(buf, tw, false, cols, band);
+    } else {
+        fft64_r8_two<C2, LD>(buf, tw, true, cols, band);
+        fft64_r8_two<C2, 1>(buf, tw, true, rows, all);
+    }
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int e = t + 256 * it;
+        const int y = e >> 6, x = e & (L - 1);
+        if (INV || (in_band(x, N, L) && in_band(y, N, L))) data[e] = buf[y * LD + x];
+    }
 }
 
 template <class T, int LOGL, int LOGLINES>
@@ -1507,9 +1618,17 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
     __shared__ C2 tw[L / 2];
     for (int j = threadIdx.x; j < L / 2; j += blockDim.x) tw[j] = twg[j];
     data += (int64_t)blockIdx.y * p.qstr;
-    const int C = 1 << p.logC;
-    const int64_t a0 = ((int64_t)blockIdx.x % p.nachunk) << p.logC;
-    const int64_t o0 = ((int64_t)blockIdx.x / p.nachunk) << p.logOB;
+    int C = 1 << p.logC;
+    int64_t a0 = ((int64_t)blockIdx.x % p.nachunk) << p.logC;
+    int64_t o0 = ((int64_t)blockIdx.x / p.nachunk) << p.logOB;
+    if (p.flat) {
+        // C = LINES and one outer per tile: the thread's line is fixed
+        // (t mod LINES); number it o * A + a across the whole pass, so that
+        // no workgroup holds a partial chunk of columns
+        const int64_t lam = (int64_t)blockIdx.x * LINES + (threadIdx.x & (LINES - 1));
+        o0 = lam / p.A;
+        a0 = lam - o0 * p.A - (threadIdx.x & (LINES - 1));
+    }
     // in-plane offset of column a / outer o
     auto coff = [&](int64_t a) -> int64_t { return p.abnd ? (int64_t)band_index((int)a, p.N, L) : a; };
     auto ooff = [&](int64_t o) -> int64_t {
@@ -2082,7 +2201,10 @@ static void fft_launch(FftPass p, int nq, typename Cplx<T>::type *grid,
     p.logOB = LOGLINES - p.logC;
     p.nachunk = (p.A + ((int64_t)1 << p.logC) - 1) >> p.logC;
     const int64_t nob = (p.O + ((int64_t)1 << p.logOB) - 1) >> p.logOB;
-    const int64_t nblk = p.nachunk * nob;
+    // a full-width tile (one outer, LINES columns) numbers its lines across
+    // the outers instead of padding the last column chunk of every outer
+    p.flat = p.logC == LOGLINES && p.A > 1;
+    const int64_t nblk = p.flat ? (p.O * p.A + (1 << LOGLINES) - 1) >> LOGLINES : p.nachunk * nob;
     MLG_REQUIRE(nblk < ((int64_t)1 << 31) && nq <= 65535, MLG_ERR_RANGE, "FFT grid too large");
     hipLaunchKernelGGL((k_fft<T, LOGL, LOGLINES>), dim3((unsigned)nblk, nq), dim3(256), 0, s, grid, p, tw, M);
     MLG_LAUNCH_CHECK();
@@ -2148,7 +2270,8 @@ static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, in
 //          columns; x inverse (all rows, out-of-band x read as zero).
 //   d = 3: x forward (all); y forward on band x columns (all z); z forward *
 //          M * inverse on band x columns of band y rows; y inverse on band
-//          x columns; x inverse (all, out-of-band read as zero).
+//          x columns; x inverse (all, out-of-band read as zero).  FP32 grids
+//          of side 64 do the x and y passes of each plane in one kernel.
 // Only entries with every frequency inside the band are ever multiplied;
 // the out-of-band ones are never read again.
 template <class T>
@@ -2162,6 +2285,20 @@ static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid
         fft_pass<T>(P, bg, grid, 1, 2, M, s);
         fft_pass<T>(P, bg, grid, 0, 1, nullptr, s);
     } else {
+        if constexpr (std::is_same<T, float>::value) {
+            if (P.nos == 64) {
+                const int64_t qstr = (int64_t)64 * 64 * 64;
+                MLG_REQUIRE(bg / 2 <= 65535, MLG_ERR_RANGE, "FFT grid too large");
+                hipLaunchKernelGGL((k_fft_xy64<float2, 0>), dim3(64, bg / 2), dim3(256), 0, s, grid,
+                                   P.N, qstr, tw_of<T>(P));
+                MLG_LAUNCH_CHECK();
+                fft_pass<T>(P, bg, grid, 2, 2, M, s);
+                hipLaunchKernelGGL((k_fft_xy64<float2, 1>), dim3(64, bg / 2), dim3(256), 0, s, grid,
+                                   P.N, qstr, tw_of<T>(P));
+                MLG_LAUNCH_CHECK();
+                return;
+            }
+        }
         fft_pass<T>(P, bg, grid, 0, 0, nullptr, s);
         fft_pass<T>(P, bg, grid, 1, 0, nullptr, s);
         fft_pass<T>(P, bg, grid, 2, 2, M, s);
