@@ -612,9 +612,16 @@ __global__ void k_scatter_counts(int nu, const unsigned *__restrict__ ucell,
     if (i < nu) dense[ucell[i]] = (int)cnt[i];
 }
 
-// Gather through the cell table: sum of the cell's patch entries in entry
-// order (entries of one cell are sorted by run).
 template <class T, int VPL>
+constexpr int csr_batch() {
+    constexpr int w = 64 / (VPL * (int)(sizeof(T) / 4));
+    return w < 4 ? 4 : (w > 16 ? 16 : w);
+}
+
+// Gather through the cell table: sum of the cell's patch entries in entry
+// order (entries of one cell are sorted by run), NB entries in flight per
+// batch (NB x VPL values of at most 64 registers).
+template <class T, int VPL, int NB = csr_batch<T, VPL>()>
 __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
                                                     const int *__restrict__ ptr,
                                                     const int *__restrict__ ent,
@@ -627,22 +634,22 @@ __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
 #pragma unroll
     for (int v = 0; v < VPL; ++v) acc[v] = T(0);
     const int e1 = ptr[cell + 1];
-    // entries in batches of 4: indices, then rows, all in flight; summed in
+    // entries in batches of NB: indices, then rows, all in flight; summed in
     // entry order
-    for (int e0 = ptr[cell]; e0 < e1; e0 += 4) {
-        int idx[4];
+    for (int e0 = ptr[cell]; e0 < e1; e0 += NB) {
+        int idx[NB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) idx[u] = e0 + u < e1 ? ent[e0 + u] : -1;
-        T h[4][VPL];
+        for (int u = 0; u < NB; ++u) idx[u] = e0 + u < e1 ? ent[e0 + u] : -1;
+        T h[NB][VPL];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < NB; ++u) {
             if (idx[u] >= 0) load_vec<T, VPL>(patch + (int64_t)idx[u] * bs + v0, h[u]);
             else
 #pragma unroll
                 for (int v = 0; v < VPL; ++v) h[u][v] = T(0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < NB; ++u)
             if (idx[u] >= 0)
 #pragma unroll
                 for (int v = 0; v < VPL; ++v) acc[v] += h[u][v];
@@ -1552,18 +1559,24 @@ __device__ inline void fft64_r8_two(C2 *buf, const C2 *tw, bool inverse, const i
     __syncthreads();
 }
 
-// The x and y passes of one z plane of a 64^3 grid (one workgroup per plane
-// and complex vector pair), held in LDS as buf[y * 65 + x]:
-//   INV = 0: x forward on all 64 rows, y forward on the N + 1 band x
+// The x and y passes of one 64 x 64 plane (one workgroup per plane and
+// complex vector pair), held in LDS as buf[y * 65 + x]:
+//   MODE 0 (d = 3): x forward on all 64 rows, y forward on the N + 1 band x
 //            columns; stores the entries with x and y both in the band (the
 //            only ones the z pass and its inverse read);
-//   INV = 1: reads those entries (zero elsewhere), y inverse on the band x
-//            columns, x inverse on all rows; stores the whole plane.
-// The same transforms as the separate x and y passes, without the
-// intermediate round trip of the x-transformed plane through memory.
-template <class C2, int INV>
+//   MODE 1 (d = 3): reads those entries (zero elsewhere), y inverse on the
+//            band x columns, x inverse on all rows; stores the whole plane;
+//   MODE 2 (d = 2, the plane is the grid): x forward, y forward on the band
+//            columns, every entry times M (zero outside the band, so the
+//            untransformed out-of-band columns become zero), y inverse on
+//            the band columns, x inverse; stores the whole plane.
+// The same transforms as the separate line passes, without the round trips
+// of the partly transformed plane through memory.
+template <class C2, int MODE>
 __global__ __launch_bounds__(256) void k_fft_xy64(C2 *__restrict__ data, int N, int64_t qstr,
-                                                  const C2 *__restrict__ twg) {
+                                                  const C2 *__restrict__ twg,
+                                                  const decltype(C2::x) *__restrict__ M) {
+    constexpr int INV = MODE == 1;
     constexpr int L = 64, LD = 65, PER = L * L / 256;
     __shared__ C2 buf[L * LD];
     __shared__ C2 tw[L / 2];
@@ -1590,10 +1603,24 @@ __global__ __launch_bounds__(256) void k_fft_xy64(C2 *__restrict__ data, int N, 
     const bool all[2] = {true, true};
     const int cols[2] = {band_index(l, N, L), l + 32 <= N ? band_index(l + 32, N, L) : 0};
     const bool band[2] = {l <= N, l + 32 <= N};
-    if (!INV) {
+    if (MODE == 0 || MODE == 2) {
         fft64_r8_two<C2, 1>(buf, tw, false, rows, all);
         fft64_r8_two<C2, LD>(buf, tw, false, cols, band);
-    } else {
+    }
+    if (MODE == 2) {
+        decltype(C2::x) m[PER];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) m[it] = M[t + 256 * it];
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const int e = t + 256 * it;
+            C2 &v = buf[(e >> 6) * LD + (e & (L - 1))];
+            v.x *= m[it];
+            v.y *= m[it];
+        }
+        __syncthreads();
+    }
+    if (MODE == 1 || MODE == 2) {
         fft64_r8_two<C2, LD>(buf, tw, true, cols, band);
         fft64_r8_two<C2, 1>(buf, tw, true, rows, all);
     }
@@ -1601,7 +1628,7 @@ __global__ __launch_bounds__(256) void k_fft_xy64(C2 *__restrict__ data, int N, 
     for (int it = 0; it < PER; ++it) {
         const int e = t + 256 * it;
         const int y = e >> 6, x = e & (L - 1);
-        if (INV || (in_band(x, N, L) && in_band(y, N, L))) data[e] = buf[y * LD + x];
+        if (MODE != 0 || (in_band(x, N, L) && in_band(y, N, L))) data[e] = buf[y * LD + x];
     }
 }
 
@@ -2270,8 +2297,9 @@ static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, in
 //          columns; x inverse (all rows, out-of-band x read as zero).
 //   d = 3: x forward (all); y forward on band x columns (all z); z forward *
 //          M * inverse on band x columns of band y rows; y inverse on band
-//          x columns; x inverse (all, out-of-band read as zero).  FP32 grids
-//          of side 64 do the x and y passes of each plane in one kernel.
+//          x columns; x inverse (all, out-of-band read as zero).
+// FP32 grids of side 64 do the x and y passes of each plane in one kernel
+// (d = 2: the whole convolution).
 // Only entries with every frequency inside the band are ever multiplied;
 // the out-of-band ones are never read again.
 template <class T>
@@ -2281,6 +2309,15 @@ static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid
     if (d == 1) {
         fft_pass<T>(P, bg, grid, 0, 2, M, s);
     } else if (d == 2) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (P.nos == 64) {
+                MLG_REQUIRE(bg / 2 <= 65535, MLG_ERR_RANGE, "FFT grid too large");
+                hipLaunchKernelGGL((k_fft_xy64<float2, 2>), dim3(1, bg / 2), dim3(256), 0, s, grid, P.N,
+                                   (int64_t)64 * 64, tw_of<T>(P), M);
+                MLG_LAUNCH_CHECK();
+                return;
+            }
+        }
         fft_pass<T>(P, bg, grid, 0, 0, nullptr, s);
         fft_pass<T>(P, bg, grid, 1, 2, M, s);
         fft_pass<T>(P, bg, grid, 0, 1, nullptr, s);
@@ -2290,11 +2327,11 @@ static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid
                 const int64_t qstr = (int64_t)64 * 64 * 64;
                 MLG_REQUIRE(bg / 2 <= 65535, MLG_ERR_RANGE, "FFT grid too large");
                 hipLaunchKernelGGL((k_fft_xy64<float2, 0>), dim3(64, bg / 2), dim3(256), 0, s, grid,
-                                   P.N, qstr, tw_of<T>(P));
+                                   P.N, qstr, tw_of<T>(P), nullptr);
                 MLG_LAUNCH_CHECK();
                 fft_pass<T>(P, bg, grid, 2, 2, M, s);
                 hipLaunchKernelGGL((k_fft_xy64<float2, 1>), dim3(64, bg / 2), dim3(256), 0, s, grid,
-                                   P.N, qstr, tw_of<T>(P));
+                                   P.N, qstr, tw_of<T>(P), nullptr);
                 MLG_LAUNCH_CHECK();
                 return;
             }
@@ -2419,7 +2456,11 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     }
     int64_t G = 1;
     for (int t = 0; t < D; ++t) G *= P.nos;
-    const int vgat = std::min(bs, 16);
+    // four vectors per thread and sixteen entries per batch: the gather is
+    // bound by the latency of each cell's chain of entry loads, so many
+    // short chains beat few wide ones (measured: 16 -> 4 vectors per thread
+    // takes the d = 3 gathers of the image graph from 94 to 60 us)
+    const int vgat = std::min(bs, 4);
     if (W.csr) {
 #define GATHERC_CALL(V)                                                                           \
     hipLaunchKernelGGL((k_gather_csr<T, V>), dim3(ceil_div(G, 256), bs / V), dim3(256), 0, s, G, bs, bg, \

@@ -108,6 +108,19 @@ def test_nfft_fp32_weight_matvec(mlg, b):
     assert rel_err(Y, oracle.kernel_matvec(pts, sig, X)) <= 1e-4
 
 
+@pytest.mark.parametrize("b", [1, 5, 32])
+def test_nfft_fp32_side64_grid_blocks(mlg, b):
+    """FP32 d = 3 layer on a 64^3 grid (N = 32), the size whose x and y FFT
+    passes run per plane, at 1, 4 and 16 complex vector pairs."""
+    n = 3001
+    pts, _ = gen.gaussian_mixture(n, 3, 5, 0.05, 81)
+    sig = 0.4
+    X = gen.test_vectors(n, b, 82)
+    case_id("nfft fp32 W x d=3 n=%d b=%d N=32 w=6" % (n, b))
+    Y = mlg.kernel_matvec(pts, sig, X, mlg.kparams("nfft", 32, N=32, window=6))
+    assert rel_err(Y, oracle.kernel_matvec(pts, sig, X)) <= 1e-4
+
+
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_nfft_fp64_lsym_dims(mlg, d):
     pts, _ = gen.gaussian_mixture(3001, d, 4, 0.08, 40 + d)
