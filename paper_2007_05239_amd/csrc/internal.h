@@ -31,8 +31,8 @@ struct NfftPlan {
     DevBuf<int> bin_run;    // per bin: run index or -1
     DevBuf<unsigned> run_key;   // per run: its bin key
     int nred1 = 0, nred2 = 0;
-    DevBuf<int2> red1;      // level-1 reduction groups (first slot, count <= 32)
-    DevBuf<int4> red2;      // level-2 (run, first scratch slot, groups, 0)
+    DevBuf<int4> red1;      // level-1 groups (first slot, count <= 32, destination slot, 0)
+    DevBuf<int4> red2;      // level-2, runs of > 1 group (run, first scratch slot, groups, 0)
     int SB = 8, nsb = 0;    // superbin edge (bins) and superbins per dimension
     DevBuf<unsigned char> occ;  // per superbin: 1 if occupied
     DevBuf<double> bhat;    // kernel Fourier coefficients b^_l, l in [0,N)^d (index l mod N)

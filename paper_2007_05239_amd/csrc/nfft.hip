@@ -544,12 +544,14 @@ __global__ __launch_bounds__(64) void k_spread(Geom g, const int4 *__restrict__ 
 
 // Bins cut into several tasks: their task patches are summed in a fixed
 // two-level order.  Level 1: each group of up to 32 consecutive task patches
-// (int2: first slot, count) is summed in task order into its first slot.
+// (int4: first slot, count, destination slot, 0) is summed in task order
+// into its destination: the run's own patch slot when the run has a single
+// group, else the group's first slot.
 template <class T>
-__global__ void k_reduce1(int64_t elems, const int2 *__restrict__ grp, T *__restrict__ patch) {
+__global__ void k_reduce1(int64_t elems, const int4 *__restrict__ grp, T *__restrict__ patch) {
     const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
     if (e >= elems) return;
-    const int2 gr = grp[blockIdx.x];
+    const int4 gr = grp[blockIdx.x];
     const T *src = patch + (int64_t)gr.x * elems + e;
     // loads in batches of 8 (all in flight together), sums in task order
     T s = src[0];
@@ -561,11 +563,11 @@ __global__ void k_reduce1(int64_t elems, const int2 *__restrict__ grp, T *__rest
         for (int u = 0; u < 8; ++u)
             if (j0 + u < gr.y) s += h[u];
     }
-    patch[(int64_t)gr.x * elems + e] = s;
+    patch[(int64_t)gr.z * elems + e] = s;
 }
 
-// Level 2 (int4: run, first scratch slot, groups, 0): the group sums, in
-// group order, into the run's own patch slot.
+// Level 2 (int4: run, first scratch slot, groups, 0), runs of more than one
+// group only: the group sums, in group order, into the run's own patch slot.
 template <class T>
 __global__ void k_reduce2(int64_t elems, const int4 *__restrict__ runs, T *__restrict__ patch) {
     const int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
@@ -2054,12 +2056,14 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
         std::vector<int4> hm(P.nmulti);
         MLG_HIP(hipMemcpyAsync(hm.data(), P.multi.p, sizeof(int4) * P.nmulti, hipMemcpyDeviceToHost, s));
         MLG_HIP(hipStreamSynchronize(s));
-        std::vector<int2> g1;
+        std::vector<int4> g1;
         std::vector<int4> g2;
         for (const int4 &m : hm) {
             const int ng = (m.z + 31) / 32;
-            for (int q = 0; q < ng; ++q) g1.push_back(make_int2(m.y + 32 * q, std::min(32, m.z - 32 * q)));
-            g2.push_back(make_int4(m.x, m.y, ng, 0));
+            for (int q = 0; q < ng; ++q)
+                g1.push_back(make_int4(m.y + 32 * q, std::min(32, m.z - 32 * q),
+                                       ng == 1 ? m.x : m.y + 32 * q, 0));
+            if (ng > 1) g2.push_back(make_int4(m.x, m.y, ng, 0));
         }
         P.nred1 = (int)g1.size();
         P.nred2 = (int)g2.size();
@@ -2449,9 +2453,11 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
             hipLaunchKernelGGL(k_reduce1<T>, dim3(P.nred1, ceil_div(elems, 256)), dim3(256), 0, s, elems,
                                P.red1.p, patch);
             MLG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_reduce2<T>, dim3(P.nred2, ceil_div(elems, 256)), dim3(256), 0, s, elems,
-                               P.red2.p, patch);
-            MLG_LAUNCH_CHECK();
+            if (P.nred2 > 0) {
+                hipLaunchKernelGGL(k_reduce2<T>, dim3(P.nred2, ceil_div(elems, 256)), dim3(256), 0, s,
+                                   elems, P.red2.p, patch);
+                MLG_LAUNCH_CHECK();
+            }
         }
     }
     int64_t G = 1;
