@@ -4,8 +4,9 @@
 //   gather-out   y = coef sum_t D_t^-1/2 (F_t - K(0) z_t) in FP64, with the
 //                self term of W = W~ - K(0) I (Sec. 4) and the layer mean
 //                (1/T) sum_t (Sec. 3); y = x - that for L_sym / L_1.
-// One thread owns one row (its permutation entry and D^-1/2 are read once
-// per layer).  The layer sum runs in layer order.
+// The entry kernel gives one thread a row, the exit kernel a row's group of
+// kOutVG vectors (D^-1/2 is read once per layer and thread).  The layer sum
+// runs in layer order.
 #include "internal.h"
 
 namespace mlg {
@@ -120,44 +121,82 @@ __global__ __launch_bounds__(256) void k_scatter_in(int64_t n, int b, int bs,
     }
 }
 
-__global__ __launch_bounds__(256) void k_gather_out(int64_t n, int b, int bs,
+// Exit kernel: one thread per (row, group of kOutVG vectors), the groups of
+// a row in adjacent threads, so that a wavefront reads 64 / ng consecutive
+// rows of each layer's slice as one region and keeps few registers per
+// thread (the one-thread-per-row form held 16 vectors in flight per thread
+// at 2 wavefronts per SIMD).  Per vector the arithmetic and its order are
+// those of the layer sum described at the top of the file.
+constexpr int kOutVG = 8;
+
+__device__ inline void load_row8(const void *Fbase, bool is64, int64_t off, double (&f)[kOutVG],
+                                 int cnt) {
+    if (!is64) {
+        const float *src = reinterpret_cast<const float *>(Fbase) + off;
+        if (cnt == kOutVG) {
+            const float4 a = *reinterpret_cast<const float4 *>(src);
+            const float4 c = *reinterpret_cast<const float4 *>(src + 4);
+            f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = a.w;
+            f[4] = c.x; f[5] = c.y; f[6] = c.z; f[7] = c.w;
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < kOutVG; ++j) f[j] = j < cnt ? (double)src[j] : 0.0;
+    } else {
+        const double *src = reinterpret_cast<const double *>(Fbase) + off;
+        if (cnt == kOutVG) {
+#pragma unroll
+            for (int j = 0; j < kOutVG; j += 2) {
+                const double2 q = *reinterpret_cast<const double2 *>(src + j);
+                f[j] = q.x;
+                f[j + 1] = q.y;
+            }
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < kOutVG; ++j) f[j] = j < cnt ? src[j] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_out(int64_t n, int b, int bs, int lng,
                                                     const double *__restrict__ X, int64_t ldx,
                                                     double *__restrict__ Y, int64_t ldy,
                                                     const LayerIO *__restrict__ L, int nl,
                                                     int use_dinv, int lsym, double coef) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = gt >> lng;
     if (i >= n) return;
-    const int vgw = bs < kIoVG ? bs : kIoVG;
-    for (int v0 = 0; v0 < b; v0 += vgw) {
-        double x[kIoVG], acc[kIoVG];
-        load_block_row(X, ldx, i, b, v0, vgw, x);
+    const int v0 = (int)(gt & ((1 << lng) - 1)) * kOutVG;
+    const int vgw = bs < kOutVG ? bs : kOutVG;
+    double x[kOutVG], acc[kOutVG];
 #pragma unroll
-        for (int j = 0; j < kIoVG; ++j) acc[j] = 0.0;
-        for (int t = 0; t < nl; ++t) {
-            const LayerIO d = L[t];
-            const double di = use_dinv ? d.dinv[i] : 1.0;
-            double f[kIoVG];
-            if (d.is64) load_row<double>(d.F, i * bs + v0, f, vgw);
-            else load_row<float>(d.F, i * bs + v0, f, vgw);
+    for (int j = 0; j < kOutVG; ++j) {
+        x[j] = (j < vgw && v0 + j < b) ? X[i + (int64_t)(v0 + j) * ldx] : 0.0;
+        acc[j] = 0.0;
+    }
+    for (int t = 0; t < nl; ++t) {
+        const LayerIO d = L[t];
+        const double di = use_dinv ? d.dinv[i] : 1.0;
+        double f[kOutVG];
+        load_row8(d.F, d.is64, i * bs + v0, f, vgw);
 #pragma unroll
-            for (int j = 0; j < kIoVG; ++j) {
-                if (j < vgw) {
-                    const double zx = use_dinv ? x[j] * di : x[j];
-                    // the value the summation saw (FP32 layers round it)
-                    const double z = d.is64 ? zx : (double)(float)zx;
-                    double w = f[j] - d.K0 * z;
-                    if (use_dinv) w *= di;
-                    acc[j] += w;
-                }
+        for (int j = 0; j < kOutVG; ++j) {
+            if (j < vgw) {
+                const double zx = use_dinv ? x[j] * di : x[j];
+                // the value the summation saw (FP32 layers round it)
+                const double z = d.is64 ? zx : (double)(float)zx;
+                double w = f[j] - d.K0 * z;
+                if (use_dinv) w *= di;
+                acc[j] += w;
             }
         }
+    }
 #pragma unroll
-        for (int j = 0; j < kIoVG; ++j) {
-            if (j < vgw && v0 + j < b) {
-                double y = coef * acc[j];
-                if (lsym) y = x[j] - y;
-                Y[i + (int64_t)(v0 + j) * ldy] = y;
-            }
+    for (int j = 0; j < kOutVG; ++j) {
+        if (j < vgw && v0 + j < b) {
+            double y = coef * acc[j];
+            if (lsym) y = x[j] - y;
+            Y[i + (int64_t)(v0 + j) * ldy] = y;
         }
     }
 }
@@ -195,8 +234,13 @@ void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, d
                        int64_t ldy, const LayerIO *L, int nl, int use_dinv, int lsym, double coef,
                        hipStream_t s) {
     MLG_REQUIRE(bs <= 64 && b <= bs, MLG_ERR_ARG, "block too wide");
-    hipLaunchKernelGGL(k_gather_out, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, b, bs, X, ldx, Y,
-                       ldy, L, nl, use_dinv, lsym, coef);
+    // groups of kOutVG vectors per row; a power-of-two stride above kOutVG
+    // is a whole number of groups, so no group reads past its row
+    MLG_REQUIRE(bs >= 1 && (bs & (bs - 1)) == 0, MLG_ERR_ARG, "block stride must be a power of two");
+    int lng = 0;
+    while ((kOutVG << lng) < bs) ++lng;
+    hipLaunchKernelGGL(k_gather_out, dim3(blocks_for(n << lng, 256)), dim3(256), 0, s, n, b, bs, lng,
+                       X, ldx, Y, ldy, L, nl, use_dinv, lsym, coef);
     MLG_LAUNCH_CHECK();
 }
 
