@@ -1261,22 +1261,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     PtIn<3> pin;
     fetch_point<3>(c32, f32, g.n, (int64_t)tk.y + lane, lane < tk.z, pin);
     int prow = lane < tk.z ? g.perm[(int64_t)tk.y + lane] : 0;
-    // B fragments: grid at (cx, cy) = 4s + lk, cz, vector li
+    // B fragments: grid at (cx, cy) = 4s + lk, cz, vector li.  Addresses:
+    // the lane's vector plane (grid_index layout) plus twice the cell index,
+    // cell = task origin + cx + cy nos + cz nos^2 with (cx, cy) stepped
+    // along s instead of divided out per load.
     float hb[P][KS2];
-#pragma unroll
-    for (int cz = 0; cz < P; ++cz)
+    {
+        const int64_t nos = g.nos, nos2 = nos * nos;
+        const int v = v0 + li;
+        const float *gl = grid + 2 * ((int64_t)(v >> 1) * G) + (v & 1) +
+                          2 * ((int64_t)org[0] + org[1] * nos + org[2] * nos2);
+        int cx = lk, cy = 0;
 #pragma unroll
         for (int s = 0; s < KS2; ++s) {
-            const int cxy = 4 * s + lk;
-            float h = 0.0f;
-            if (cxy < C2) {
-                const int64_t cell = (int64_t)(org[0] + cxy % P) +
-                                     (int64_t)(org[1] + cxy / P) * g.nos +
-                                     (int64_t)(org[2] + cz) * g.nos * g.nos;
-                h = grid[grid_index<float>(G, cell, v0 + li)];
+            const bool ok = 4 * s + lk < C2;
+            const float *ps = gl + 2 * ((int64_t)cx + cy * nos);
+#pragma unroll
+            for (int cz = 0; cz < P; ++cz) hb[cz][s] = ok ? ps[2 * cz * nos2] : 0.0f;
+            cx += 4;
+            while (cx >= P) {
+                cx -= P;
+                ++cy;
             }
-            hb[cz][s] = h;
         }
+    }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
         __syncthreads();
