@@ -8,9 +8,13 @@ scaling and aggregation), inputs and outputs resident in HBM.
 
 Metric: n * layers * b / s (node-layer-vector rows per second).
 
+Layer parameters (NFFT window and bandwidth) come from the library's
+autotuner (mlg_autotune_layer) unless --window is given: the fastest measured
+candidate within a sampled-row budget of 5e-5 against the FP64 direct sum.
+
 Printed as ONE JSON line with the roofline of the dominant kernel (timed
 with HIP events on the library's stream), the FP64-plain comparison (one
-vector per matvec, FP64 NFFT), the p = -10 power mean (one block product
+vector per matvec, FP64 NFFT tuned to the same budget), the p = -10 power mean (one block product
 with L_{p,delta}^p through the Krylov power, and the eigenpair computation
 for p = -10 and p = 1), Allen-Cahn steps at n = 10^7 (k = 30, m = 10), the
 relative error of sampled rows against the FP64 oracle, and the oracle timed
@@ -44,8 +48,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--block", type=int, default=16)
-    ap.add_argument("--N", type=int, default=0, help="bandwidth (0 = automatic per layer)")
-    ap.add_argument("--window", type=int, default=6)
+    ap.add_argument("--N", type=int, default=0,
+                    help="bandwidth with --window (0 = the library's automatic rule)")
+    ap.add_argument("--window", type=int, default=0,
+                    help="fixed window width; 0 = both legs' layer parameters from the "
+                         "library's autotuner (mlg_autotune_layer)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-plain leg")
     ap.add_argument("--no-power", action="store_true",
@@ -176,6 +183,23 @@ def allen_cahn_leg(iters=20):
             "hbm_frac": round(byts / per / 1e9 / HBM_PEAK_GBS, 3)}
 
 
+TUNE_TOL = 5e-5       # sampled-row budget of the autotuner: a 2x margin under the 1e-4 gate
+TUNE_ROWS = 256
+
+
+def tune_layers(mlg, layers, sigmas, precision, b, seed):
+    """Per-layer NFFT parameters from the library's autotuner (window and
+    bandwidth meeting TUNE_TOL on sampled rows, fastest measured)."""
+    kps, infos = [], []
+    for t, (L, s) in enumerate(zip(layers, sigmas)):
+        kp, info = mlg.autotune_layer(L, s, precision=precision, b=b, tol=TUNE_TOL,
+                                      nrows=TUNE_ROWS, seed=seed + t)
+        kps.append(kp)
+        infos.append({"N": info["N"], "window": info["window"], "sampled_err": info["err"],
+                      "ms": round(info["ms"], 4), "tried": info["tried"]})
+    return kps, infos
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -196,9 +220,16 @@ def main():
     dev = torch.device("cuda:0")
     c = gen.config3(a.image, a.image)
     n, T, b = c["n"], len(c["layers"]), a.block
-    kp = [mlg.kparams("nfft", 32, N=a.N, window=a.window, eps_B=1.0 / 16, p_reg=5)
-          for _ in range(T)]
     layers_dev = [torch.from_numpy(L).to(dev) for L in c["layers"]]
+    tuning = None
+    if a.window > 0:
+        kp = [mlg.kparams("nfft", 32, N=a.N, window=a.window, eps_B=1.0 / 16, p_reg=5)
+              for _ in range(T)]
+    else:
+        t0 = time.time()
+        kp, tinfo = tune_layers(mlg, layers_dev, c["sigma"], 32, b, c["base_seed"] + 500)
+        tuning = {"budget": TUNE_TOL, "rows": TUNE_ROWS, "seconds": round(time.time() - t0, 2),
+                  "fp32": tinfo}
     t0 = time.time()
     g = mlg.Graph(layers_dev, c["sigma"], kp)
     torch.cuda.synchronize()
@@ -248,7 +279,12 @@ def main():
     # FP64 plain: FP64 NFFT, one vector per matvec
     fp64 = None
     if not a.no_fp64:
-        kp64 = [mlg.kparams("nfft", 64, N=a.N, window=a.window) for _ in range(T)]
+        if a.window > 0:
+            kp64 = [mlg.kparams("nfft", 64, N=a.N, window=a.window) for _ in range(T)]
+        else:
+            # the plain baseline's FP64 parameters tuned to the same budget
+            kp64, tinfo64 = tune_layers(mlg, layers_dev, c["sigma"], 64, 1, c["base_seed"] + 501)
+            tuning["fp64_plain"] = tinfo64
         g64 = mlg.Graph(layers_dev, c["sigma"], kp64)
         x1 = X[:, :1].contiguous()
         for _ in range(2):
@@ -299,6 +335,7 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "image1000x1000_3layer_L1_block16", "n": n, "layers": T,
                       "block": b, "layer_params": infos, "plan_s": round(plan_s, 3),
+                      "tuning": tuning,
                       "parallelism": "single GPU"},
            "stages_ms": {k: round(v, 4) for k, v in st.items()},
            "roofline": roof, "fp64_plain": fp64, "power_mean": power, "allen_cahn": ac,

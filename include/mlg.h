@@ -309,6 +309,47 @@ mlg_status mlg_allen_cahn_ssl(int64_t n, int k, int m, const double *evals,
                               const mlg_ac_params *prm, double *U, int32_t *pred, int *iters,
                               int flags, void *stream);
 
+/* ---- parameter selection ------------------------------------------------ */
+
+/* Result of mlg_autotune_layer. */
+typedef struct {
+    int window;    /* chosen window width w (even)                               */
+    int N;         /* chosen bandwidth N                                         */
+    int tried;     /* candidates planned and measured                            */
+    int passed;    /* candidates within the error budget                         */
+    double err;    /* sampled relative error of the choice: max over the b test  */
+                   /* vectors of ||Y_s - R_s|| / ||R_s|| over the sampled rows   */
+    double ms;     /* wall milliseconds of one b-vector product with the choice  */
+                   /* (-1 when no candidate met the budget)                      */
+} mlg_tune_info;
+
+/*
+ * Choose the NFFT window width w and bandwidth N of one Gaussian-kernel layer
+ * (Algorithm 1, Sec. 4) for an error budget: the fastest measured candidate
+ * whose error on a seeded sample of rows, against the FP64 direct sum of
+ * those rows (zero diagonal), is <= tol for a seeded block of b test vectors
+ * uniform in [-1, 1).
+ *   Candidates: N in {N0/2, N0, 2 N0} (powers of two in 8..256; N0 = the
+ *   automatic bandwidth of mlg_graph_create with N = 0) and w in {4, 6, 8, 10}
+ *   (FP32) or {4, 6, ..., 16} (FP64), bin 1, eps_B = 1/16, p_reg = 5.
+ *   For each N the windows are tried in increasing order and the first within
+ *   the budget is timed (5 products after one warm-up).
+ *   points     n x d row-major FP64 (device pointer with MLG_DEVICE_PTRS, else
+ *              host), d in 1..3; 2 <= n < 2^31.
+ *   precision  32 or 64 (the summation precision of the candidates).
+ *   b          test vectors, 1..64;  tol in (0, 1);  nrows sampled rows,
+ *              1..min(n, 4096);  seed selects the rows and the test block.
+ *   kp         out: the chosen parameters, ready for mlg_graph_create.
+ *   info       out: the choice and the counts (always filled when the
+ *              arguments are valid).
+ * Returns MLG_ERR_RANGE when no candidate meets tol; kp and info then hold
+ * the candidate with the smallest sampled error.  The reference rows cost
+ * O(nrows n d) on the device.
+ */
+mlg_status mlg_autotune_layer(int64_t n, int d, const double *points, double sigma,
+                              int precision, int b, double tol, int nrows, uint64_t seed,
+                              int flags, void *stream, mlg_kparams *kp, mlg_tune_info *info);
+
 /* ---- measurement helpers ------------------------------------------------ */
 
 /* Stages of one matvec, for mlg_profile_stages. */

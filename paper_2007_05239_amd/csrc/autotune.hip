@@ -1,0 +1,256 @@
+// Plan-time choice of the NFFT parameters of one layer: the window width w and
+// the bandwidth N of Algorithm 1.  Every candidate is planned and applied to a
+// seeded block of test vectors; its error is measured on a seeded sample of
+// rows against the FP64 direct sum of those rows (the definition the fast
+// summation approximates, Sec. 4), and the fastest candidate whose error is
+// within the budget is returned.  For each bandwidth the windows are tried in
+// increasing order and the first that meets the budget is timed: a wider
+// window at the same bandwidth only adds work.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.h"
+
+namespace mlg {
+
+namespace {
+
+// The finaliser of the SplitMix64 generator (Steele, Lea and Flood, 2014):
+// a bijective 64-bit mix.
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Test block: X[e] uniform in [-1, 1) from mix64(seed ^ mix64(e)).
+__global__ void k_test_block(int64_t cnt, uint64_t seed, double *__restrict__ X) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cnt) return;
+    X[e] = (double)(mix64(seed ^ mix64((uint64_t)e)) >> 11) * 0x1.0p-52 - 1.0;
+}
+
+// out[r + v nrow] = sum_{j != i} exp(-||x_i - x_j||^2 / sigma^2) X[j + v ldx],
+// i = rows[r]: one workgroup per row; thread t sums j = t, t + 256, ... in
+// FP64, then a fixed pairwise tree adds the 256 partial sums.
+constexpr int kRefVG = 16;
+
+__global__ __launch_bounds__(256) void k_ref_rows(int64_t n, int d, const double *__restrict__ pts,
+                                                  double inv_s2, const int64_t *__restrict__ rows,
+                                                  int nrow, int b, const double *__restrict__ X,
+                                                  int64_t ldx, double *__restrict__ out) {
+    __shared__ double red[256];
+    const int64_t i = rows[blockIdx.x];
+    double xi[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < d; ++k) xi[k] = pts[i * d + k];
+    for (int v0 = 0; v0 < b; v0 += kRefVG) {
+        const int nb = (b - v0) < kRefVG ? (b - v0) : kRefVG;
+        double acc[kRefVG];
+#pragma unroll
+        for (int v = 0; v < kRefVG; ++v) acc[v] = 0.0;
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
+            if (j == i) continue;
+            double r2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double dk = xi[k] - pts[j * d + k];
+                r2 += dk * dk;
+            }
+            const double w = exp(-r2 * inv_s2);
+#pragma unroll
+            for (int v = 0; v < kRefVG; ++v)
+                if (v < nb) acc[v] += w * X[j + (int64_t)(v0 + v) * ldx];
+        }
+        for (int v = 0; v < nb; ++v) {
+            red[threadIdx.x] = acc[v];
+            __syncthreads();
+            for (int h = 128; h > 0; h >>= 1) {
+                if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) out[blockIdx.x + (int64_t)(v0 + v) * nrow] = red[0];
+            __syncthreads();
+        }
+    }
+}
+
+// out[r + v nrow] = Y[rows[r] + v n]
+__global__ void k_take_rows(int nrow, int b, const int64_t *__restrict__ rows,
+                            const double *__restrict__ Y, int64_t n, double *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrow * b) return;
+    const int r = e % nrow, v = e / nrow;
+    out[e] = Y[rows[r] + (int64_t)v * n];
+}
+
+struct Cand {
+    int N = 0, w = 0;
+    double err = INFINITY, ms = INFINITY;
+};
+
+struct GraphHandle {
+    mlg_graph *h = nullptr;
+    ~GraphHandle() { if (h) (void)mlg_graph_destroy(h); }
+};
+
+void check_args(int64_t n, int d, const double *points, double sigma, int precision, int b,
+                double tol, int nrows, const mlg_kparams *kp, const mlg_tune_info *info) {
+    MLG_REQUIRE(points && kp && info, MLG_ERR_ARG, "null argument");
+    MLG_REQUIRE(n >= 2 && n < ((int64_t)1 << 31), MLG_ERR_ARG, "need 2 <= n < 2^31");
+    MLG_REQUIRE(d >= 1 && d <= 3, MLG_ERR_RANGE, "NFFT layers need d in 1..3");
+    MLG_REQUIRE(sigma > 0.0 && std::isfinite(sigma), MLG_ERR_RANGE, "sigma must be positive");
+    MLG_REQUIRE(precision == 32 || precision == 64, MLG_ERR_ARG, "precision must be 32 or 64");
+    MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
+    MLG_REQUIRE(tol > 0.0 && tol < 1.0, MLG_ERR_ARG, "tol must be in (0, 1)");
+    MLG_REQUIRE(nrows >= 1 && nrows <= 4096 && nrows <= n, MLG_ERR_ARG,
+                "nrows must be in 1..min(n, 4096)");
+}
+
+void autotune(int64_t n, int d, const double *points, double sigma, int precision, int b,
+              double tol, int nrows, uint64_t seed, int flags, hipStream_t s, mlg_kparams *kp,
+              mlg_tune_info *info) {
+    *info = mlg_tune_info{};
+    const bool dev = (flags & MLG_DEVICE_PTRS) != 0;
+    DevBuf<double> pcopy;
+    const double *P = points;
+    if (!dev) {
+        upload(pcopy, points, (size_t)n * d, false, s);
+        P = pcopy.p;
+    }
+    DevBuf<double> X((size_t)n * b), Y((size_t)n * b);
+    hipLaunchKernelGGL(k_test_block, dim3(ceil_div(n * b, 256)), dim3(256), 0, s, n * b, seed, X.p);
+    MLG_LAUNCH_CHECK();
+    std::vector<int64_t> rows(nrows);
+    for (int r = 0; r < nrows; ++r) rows[r] = (int64_t)(mix64(~seed + (uint64_t)r) % (uint64_t)n);
+    DevBuf<int64_t> drows;
+    upload(drows, rows.data(), rows.size(), false, s);
+    DevBuf<double> dref((size_t)nrows * b), dtake((size_t)nrows * b);
+    hipLaunchKernelGGL(k_ref_rows, dim3(nrows), dim3(256), 0, s, n, d, P, 1.0 / (sigma * sigma),
+                       drows.p, nrows, b, X.p, n, dref.p);
+    MLG_LAUNCH_CHECK();
+    std::vector<double> ref((size_t)nrows * b), got((size_t)nrows * b);
+    MLG_HIP(hipMemcpyAsync(ref.data(), dref.p, sizeof(double) * ref.size(), hipMemcpyDeviceToHost, s));
+    MLG_HIP(hipStreamSynchronize(s));
+    std::vector<double> rnorm(b, 0.0);
+    for (int v = 0; v < b; ++v) {
+        double q = 0.0;
+        for (int r = 0; r < nrows; ++r) q += ref[r + (size_t)v * nrows] * ref[r + (size_t)v * nrows];
+        rnorm[v] = std::sqrt(q);
+    }
+
+    auto make = [&](int N, int w, GraphHandle &gh) -> mlg_status {
+        mlg_kparams k{MLG_METHOD_NFFT, precision, N, w, 1.0 / 16, 5, 1, MLG_KERNEL_GAUSSIAN};
+        const double *parr[1] = {P};
+        const int darr[1] = {d};
+        return mlg_graph_create(&gh.h, n, 1, darr, parr, &sigma, &k,
+                                MLG_DEVICE_PTRS | MLG_SKIP_DEGREES, (void *)s);
+    };
+    auto apply = [&](GraphHandle &gh) {
+        const mlg_status st = mlg_laplacian_matvec(gh.h, 0, MLG_OP_W, b, X.p, n, Y.p, n, MLG_DEVICE_PTRS);
+        MLG_REQUIRE(st == MLG_OK, st, mlg_last_error());
+    };
+    // the bandwidth of the automatic rule, then half and twice it
+    int Nauto = 0;
+    {
+        GraphHandle gh;
+        const mlg_status st = make(0, precision == 32 ? 6 : 12, gh);
+        MLG_REQUIRE(st == MLG_OK, st, mlg_last_error());
+        int ip[6];
+        double dp[2];
+        const mlg_status st2 = mlg_graph_layer_info(gh.h, 0, ip, dp);
+        MLG_REQUIRE(st2 == MLG_OK, st2, mlg_last_error());
+        Nauto = ip[1];
+    }
+    std::vector<int> Ns;
+    for (int N : {Nauto / 2, Nauto, 2 * Nauto})
+        if (N >= 8 && N <= 256) Ns.push_back(N);
+    const std::vector<int> ws = precision == 32 ? std::vector<int>{4, 6, 8, 10}
+                                                : std::vector<int>{4, 6, 8, 10, 12, 14, 16};
+    Cand best, closest;
+    for (int N : Ns) {
+        for (int w : ws) {
+            if (1 + w / 2 > N / 2) continue;   // the window must fit the grid's band margin
+            GraphHandle gh;
+            const mlg_status st = make(N, w, gh);
+            if (st == MLG_ERR_RANGE) continue;   // a combination the plan rejects
+            MLG_REQUIRE(st == MLG_OK, st, mlg_last_error());
+            apply(gh);
+            hipLaunchKernelGGL(k_take_rows, dim3(ceil_div((int64_t)nrows * b, 256)), dim3(256), 0, s,
+                               nrows, b, drows.p, Y.p, n, dtake.p);
+            MLG_LAUNCH_CHECK();
+            MLG_HIP(hipMemcpyAsync(got.data(), dtake.p, sizeof(double) * got.size(),
+                                   hipMemcpyDeviceToHost, s));
+            MLG_HIP(hipStreamSynchronize(s));
+            double err = 0.0;
+            for (int v = 0; v < b; ++v) {
+                double q = 0.0;
+                for (int r = 0; r < nrows; ++r) {
+                    const double e = got[r + (size_t)v * nrows] - ref[r + (size_t)v * nrows];
+                    q += e * e;
+                }
+                err = std::max(err, rnorm[v] > 0.0 ? std::sqrt(q) / rnorm[v] : std::sqrt(q));
+            }
+            ++info->tried;
+            if (err < closest.err) closest = Cand{N, w, err, INFINITY};
+            if (!(err <= tol)) continue;
+            ++info->passed;
+            apply(gh);   // warm
+            constexpr int kReps = 5;
+            const auto t0 = std::chrono::steady_clock::now();
+            for (int r = 0; r < kReps; ++r) apply(gh);
+            const auto t1 = std::chrono::steady_clock::now();
+            const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / kReps;
+            if (ms < best.ms) best = Cand{N, w, err, ms};
+            break;   // wider windows at this bandwidth are slower
+        }
+    }
+    const Cand &c = best.w > 0 ? best : closest;
+    *kp = mlg_kparams{MLG_METHOD_NFFT, precision, c.N, c.w, 1.0 / 16, 5, 1, MLG_KERNEL_GAUSSIAN};
+    info->window = c.w;
+    info->N = c.N;
+    info->err = c.err;
+    info->ms = best.w > 0 ? best.ms : -1.0;
+    MLG_REQUIRE(best.w > 0, MLG_ERR_RANGE,
+                "no candidate meets the error budget (smallest sampled error " +
+                    std::to_string(closest.err) + ")");
+}
+
+}  // namespace
+
+}  // namespace mlg
+
+extern "C" mlg_status mlg_autotune_layer(int64_t n, int d, const double *points, double sigma,
+                                         int precision, int b, double tol, int nrows,
+                                         uint64_t seed, int flags, void *stream, mlg_kparams *kp,
+                                         mlg_tune_info *info) {
+    using namespace mlg;
+    hipStream_t s = (hipStream_t)stream;
+    bool own = false;
+    try {
+        set_last_error("");
+        // arguments first: no device work for a call that is rejected
+        check_args(n, d, points, sigma, precision, b, tol, nrows, kp, info);
+        if (!s) {
+            MLG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            own = true;
+        }
+        autotune(n, d, points, sigma, precision, b, tol, nrows, seed, flags, s, kp, info);
+        if (own) (void)hipStreamDestroy(s);
+        return MLG_OK;
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        if (own) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        return e.code;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        if (own) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        return MLG_ERR_HIP;
+    }
+}

@@ -40,7 +40,7 @@ EXPORTED = ["mlg_last_error", "mlg_version", "mlg_graph_create", "mlg_graph_crea
             "mlg_median_pairwise_distance", "mlg_graph_destroy",
             "mlg_graph_degrees", "mlg_kernel_matvec", "mlg_laplacian_matvec",
             "mlg_lanczos_eigs", "mlg_power_mean_matvec", "mlg_allen_cahn_ssl",
-            "mlg_profile_stages", "mlg_graph_layer_info"]
+            "mlg_profile_stages", "mlg_graph_layer_info", "mlg_autotune_layer"]
 
 
 class MlgError(RuntimeError):
@@ -63,6 +63,11 @@ class EigInfo(ctypes.Structure):
 
 class PksmParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_steps", ctypes.c_int)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int), ("N", ctypes.c_int), ("tried", ctypes.c_int),
+                ("passed", ctypes.c_int), ("err", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 class ACParams(ctypes.Structure):
@@ -103,6 +108,9 @@ def _load():
                                 ctypes.POINTER(ctypes.c_int), I, P], I),
         "mlg_profile_stages": ([P, I, I, I, P, i64, P, i64, I, P, I], I),
         "mlg_graph_layer_info": ([P, I, P, P], I),
+        "mlg_autotune_layer": ([i64, I, P, ctypes.c_double, I, I, ctypes.c_double, I,
+                                ctypes.c_uint64, I, P, ctypes.POINTER(KParams),
+                                ctypes.POINTER(TuneInfo)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -157,6 +165,35 @@ def _colmajor(X):
         X = X.reshape(-1, 1)
     X = np.asfortranarray(X)
     return X, X.shape[0], X.shape[1]
+
+
+def autotune_layer(points, sigma, precision=32, b=16, tol=1e-4, nrows=128, seed=0):
+    """NFFT window and bandwidth for one layer (mlg_autotune_layer): returns
+    (KParams, info dict).  points n x d (numpy or torch CUDA).  Raises
+    MlgError (MLG_ERR_RANGE) if no candidate meets tol; the exception then
+    carries the info of the most accurate candidate as `.info`."""
+    if _is_torch(points):
+        pts = points.contiguous()
+        flags = MLG_DEVICE_PTRS if pts.is_cuda else 0
+        if pts.is_cuda:
+            _sync()
+        ptr = _ptr(pts)[0]
+    else:
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        flags = 0
+        ptr = pts.ctypes.data
+    n, d = int(pts.shape[0]), int(pts.shape[1])
+    kp = KParams()
+    info = TuneInfo()
+    rc = _lib.mlg_autotune_layer(n, d, ptr, float(sigma), int(precision), int(b), float(tol),
+                                 int(nrows), int(seed) & (2 ** 64 - 1), flags, None,
+                                 ctypes.byref(kp), ctypes.byref(info))
+    out = {f: getattr(info, f) for f, _ in TuneInfo._fields_}
+    if rc != MLG_OK:
+        e = MlgError(rc, _lib.mlg_last_error().decode())
+        e.info = out
+        raise e
+    return kp, out
 
 
 def stride_groups(D, per_layer):

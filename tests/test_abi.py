@@ -71,6 +71,15 @@ def test_argument_errors_before_device_work():
                                   ctypes.byref(it), 0, None) == mlg.MLG_ERR_ARG
     # null graph
     assert lib.mlg_laplacian_matvec(None, 0, 0, 1, None, 1, None, 1, 0) == mlg.MLG_ERR_ARG
+    # autotuner: null outputs, bad precision, tolerance, sample size and dimension
+    kpo, tio = mlg.KParams(), mlg.TuneInfo()
+    at = lib.mlg_autotune_layer
+    assert at(10, 3, pts.ctypes.data, 0.5, 32, 4, 1e-4, 4, 0, 0, None, None, ctypes.byref(tio)) == mlg.MLG_ERR_ARG
+    assert at(10, 3, pts.ctypes.data, 0.5, 16, 4, 1e-4, 4, 0, 0, None, ctypes.byref(kpo), ctypes.byref(tio)) == mlg.MLG_ERR_ARG
+    assert at(10, 3, pts.ctypes.data, 0.5, 32, 4, 0.0, 4, 0, 0, None, ctypes.byref(kpo), ctypes.byref(tio)) == mlg.MLG_ERR_ARG
+    assert at(10, 3, pts.ctypes.data, 0.5, 32, 4, 1e-4, 11, 0, 0, None, ctypes.byref(kpo), ctypes.byref(tio)) == mlg.MLG_ERR_ARG
+    assert at(10, 4, pts.ctypes.data, 0.5, 32, 4, 1e-4, 4, 0, 0, None, ctypes.byref(kpo), ctypes.byref(tio)) == mlg.MLG_ERR_RANGE
+    assert at(10, 3, pts.ctypes.data, -1.0, 32, 4, 1e-4, 4, 0, 0, None, ctypes.byref(kpo), ctypes.byref(tio)) == mlg.MLG_ERR_RANGE
     assert lib.mlg_graph_destroy(None) == mlg.MLG_OK
 
 
