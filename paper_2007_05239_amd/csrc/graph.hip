@@ -22,7 +22,17 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 Graph::~Graph() {
     for (auto &c : caps) (void)hipGraphExecDestroy(c.exec);
     caps.clear();
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (hipStream_t q : side) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+    }
+    for (hipEvent_t e : fork_join) (void)hipEventDestroy(e);
 }
+
+// Concurrent branches of an all-layer product (at most this many layers'
+// summations in flight).
+constexpr int kMaxBranches = 3;
 
 static int block_stride(int b) {
     int bs = 1;
@@ -44,33 +54,45 @@ static int max_window(const NfftPlan &P) {
 }
 
 // Per-layer workspace slices: Zs/Fs hold n x bs values of each layer's
-// precision; patch and grid are shared by the layers (used one at a time).
+// precision; patch, grid and partials per branch, sized for its layers.
 static void ensure_ws(Graph &g, int bs) {
-    size_t zs = 0, patch = 0, grid = 0, part = 0;
+    const int nb = std::min(g.T, kMaxBranches);
+    size_t zs = 0;
+    std::vector<size_t> patch(nb, 0), grid(nb, 0), part(nb, 0);
     std::vector<size_t> slice(g.T);
     for (int t = 0; t < g.T; ++t) {
         const Layer &L = g.layers[t];
+        const int r = t % nb;
         const size_t esz = L.kp.precision == 64 ? 8 : 4;
         slice[t] = zs;
         zs += ((size_t)g.n * bs * esz + 255) / 256 * 256;
         if (L.kp.method == MLG_METHOD_NFFT) {
-            patch = std::max(patch, nfft_patch_elems(L.nf, L.win, bs) * esz);
-            grid = std::max(grid, nfft_grid_elems(L.nf, bs) * esz);
+            patch[r] = std::max(patch[r], nfft_patch_elems(L.nf, L.win, bs) * esz);
+            grid[r] = std::max(grid[r], nfft_grid_elems(L.nf, bs) * esz);
         } else {
             size_t ps = esz == 8 ? direct_part_size<double>(g.n, bs) : direct_part_size<float>(g.n, bs);
-            part = std::max(part, ps * esz);
+            part[r] = std::max(part[r], ps * esz);
         }
     }
-    void *before[5] = {g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
+    if ((int)g.br.size() != nb) {
+        for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
+        g.caps.clear();
+        g.br.clear();
+        g.br.resize(nb);
+        g.ws_bs = 0;
+    }
+    std::vector<void *> before{g.Zs.p, g.Fs.p};
+    for (auto &w : g.br) before.insert(before.end(), {w.patch.p, w.grid.p, w.part.p});
     g.Zs.ensure(zs);
     g.Fs.ensure(zs);
-    g.patch.ensure(patch);
-    g.grid.ensure(grid);
-    g.part.ensure(part);
-    void *after[5] = {g.Zs.p, g.Fs.p, g.patch.p, g.grid.p, g.part.p};
-    bool moved = g.ws_bs != bs;
-    for (int i = 0; i < 5; ++i)
-        if (before[i] != after[i]) moved = true;
+    for (int r = 0; r < nb; ++r) {
+        g.br[r].patch.ensure(patch[r]);
+        g.br[r].grid.ensure(grid[r]);
+        g.br[r].part.ensure(part[r]);
+    }
+    std::vector<void *> after{g.Zs.p, g.Fs.p};
+    for (auto &w : g.br) after.insert(after.end(), {w.patch.p, w.grid.p, w.part.p});
+    const bool moved = g.ws_bs != bs || before != after;
     if (!moved) return;
     for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
     g.caps.clear();
@@ -96,23 +118,24 @@ struct StageTimer {
     double *acc;
 };
 
-// F_t = W~ z_t (NFFT) or W z_t (direct) for one layer, in its slices.
+// F_t = W~ z_t (NFFT) or W z_t (direct) for one layer, in its slices, on
+// stream s with the scratch of the layer's branch.
 template <class T>
-static void layer_core(Graph &g, int t, int bs, StageTimer *tm) {
-    hipStream_t s = g.stream;
+static void layer_core(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s) {
     Layer &L = g.layers[t];
+    Graph::Scratch &w = g.br[t % g.br.size()];
     T *Zs = reinterpret_cast<T *>(g.Zs.p + g.slice[t]);
     T *Fs = reinterpret_cast<T *>(g.Fs.p + g.slice[t]);
     float ms = 0.f;
     if (tm) MLG_HIP(hipEventRecord(tm->ev[5], s));
     if (L.kp.method == MLG_METHOD_NFFT) {
-        nfft_apply<T>(L.nf, L.win, bs, Zs, Fs, reinterpret_cast<T *>(g.patch.p),
-                      reinterpret_cast<T *>(g.grid.p), s, tm ? tm->ev : nullptr);
+        nfft_apply<T>(L.nf, L.win, bs, Zs, Fs, reinterpret_cast<T *>(w.patch.p),
+                      reinterpret_cast<T *>(w.grid.p), s, tm ? tm->ev : nullptr);
     } else {
         const T *x = nullptr;
         if constexpr (sizeof(T) == 8) x = L.x64.p; else x = L.x32.p;
         launch_direct<T>(g.n, L.d, L.kp.kernel, x, bs, Zs, Fs,
-                         reinterpret_cast<T *>(g.part.p), g.part.n / sizeof(T), s);
+                         reinterpret_cast<T *>(w.part.p), w.part.n / sizeof(T), s);
         if (tm) MLG_HIP(hipEventRecord(tm->ev[4], s));
     }
     if (tm) {
@@ -133,13 +156,44 @@ static void layer_core(Graph &g, int t, int bs, StageTimer *tm) {
     }
 }
 
-static void core(Graph &g, int layer, int bs, StageTimer *tm) {
+static void core_layer(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s) {
+    if (g.layers[t].kp.precision == 64)
+        layer_core<double>(g, t, bs, tm, s);
+    else
+        layer_core<float>(g, t, bs, tm, s);
+}
+
+// All layers (layer = -1) or one.  With `fork`, the branches of an
+// all-layer product are enqueued on their own streams after an event on
+// g.stream and joined back into it (used under stream capture, where this
+// makes parallel branches of the captured graph); otherwise in layer order
+// on g.stream.
+static void core(Graph &g, int layer, int bs, StageTimer *tm, bool fork = false) {
+    const int nb = (int)g.br.size();
+    if (!fork || layer >= 0 || nb < 2) {
+        for (int t = 0; t < g.T; ++t)
+            if (layer < 0 || t == layer) core_layer(g, t, bs, tm, g.stream);
+        return;
+    }
+    while ((int)g.side.size() < nb - 1) {
+        hipStream_t q;
+        MLG_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        g.side.push_back(q);
+    }
+    while ((int)g.fork_join.size() < nb) {
+        hipEvent_t e;
+        MLG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        g.fork_join.push_back(e);
+    }
+    MLG_HIP(hipEventRecord(g.fork_join[0], g.stream));
+    for (int r = 1; r < nb; ++r) MLG_HIP(hipStreamWaitEvent(g.side[r - 1], g.fork_join[0], 0));
     for (int t = 0; t < g.T; ++t) {
-        if (layer >= 0 && t != layer) continue;
-        if (g.layers[t].kp.precision == 64)
-            layer_core<double>(g, t, bs, tm);
-        else
-            layer_core<float>(g, t, bs, tm);
+        const int r = t % nb;
+        core_layer(g, t, bs, tm, r == 0 ? g.stream : g.side[r - 1]);
+    }
+    for (int r = 1; r < nb; ++r) {
+        MLG_HIP(hipEventRecord(g.fork_join[r], g.side[r - 1]));
+        MLG_HIP(hipStreamWaitEvent(g.stream, g.fork_join[r], 0));
     }
 }
 
@@ -204,7 +258,7 @@ const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, cons
         hipGraph_t graph;
         MLG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-            core(g, layer, bs, nullptr);
+            core(g, layer, bs, nullptr, true);
         } catch (...) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(s, &junk);

@@ -183,9 +183,18 @@ struct Graph {
     bool has_degrees = true;
     hipStream_t stream = nullptr;
     std::vector<Layer> layers;
-    // workspaces: per-layer slices of Zs/Fs (n x bs, the layer's precision)
+    // workspaces: per-layer slices of Zs/Fs (n x bs, the layer's precision);
+    // summation scratch per branch: layer t uses branch t mod br.size(), and
+    // the branches of an all-layer product run side by side (the main
+    // stream and side[r - 1] for branch r), so each has its own patch, grid
+    // and direct-path partials
     DevBuf<char> Zs, Fs;
-    DevBuf<char> patch, grid, part;
+    struct Scratch {
+        DevBuf<char> patch, grid, part;
+    };
+    std::vector<Scratch> br;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> fork_join;   // [0]: fork, [r]: join of branch r
     int ws_bs = 0;                 // block stride the slices are laid out for
     std::vector<size_t> slice;     // byte offset of layer t's slice
     DevBuf<LayerIO> io;            // device copy of the T layer descriptors
