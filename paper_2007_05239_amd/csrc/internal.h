@@ -147,6 +147,8 @@ struct PowerMeanOp {
     int nblk = 0;
     int nrow = 0;              // blocks of the row-per-thread kernels
     DevBuf<double> V, W, part, xn, al, be, C[2], chg;
+    int vcap = 0;              // Krylov basis slots allocated in V (grown on demand)
+    void ensure_slots(int need);
     DevBuf<int> fail;
     int max_used = 0;          // longest Krylov dimension used so far
     int unconverged = 0;       // layer applications stopped at mcap

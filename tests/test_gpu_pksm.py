@@ -113,6 +113,19 @@ def test_power_matvec_repeat_bit_identical_and_step_limit(mlg, direct_case):
     assert i3["steps"] == 4 and not i3["converged"] and np.isfinite(Y3).all()
 
 
+def test_power_matvec_basis_growth(mlg, direct_case):
+    """More than 16 Krylov steps (tolerance out of reach, limit 40): the
+    basis grows past its first 16 slots with the written slots kept; the
+    result is the exact power."""
+    c = direct_case
+    X = gen.test_vectors(c["n"], 3, 507)
+    case_id("power matvec basis growth n=%d up to 40 steps" % c["n"])
+    Y, info = c["g"].power_mean_matvec(-1, -0.1, X, tol=1e-15, max_steps=40)
+    assert 16 < info["steps"] <= 40 and np.isfinite(Y).all()
+    ref = oracle.power_mean_power_matvec(c["layers"], -0.1, X)
+    assert power_err(Y, ref, X, -0.1) <= 1e-10
+
+
 def test_power_matvec_arguments(mlg, direct_case):
     g = direct_case["g"]
     X = np.ones((direct_case["n"], 1))
