@@ -163,23 +163,34 @@ static void core_layer(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s) {
         layer_core<float>(g, t, bs, tm, s);
 }
 
-// All layers (layer = -1) or one.  With `fork`, the branches of an
-// all-layer product are enqueued on their own streams after an event on
-// g.stream and joined back into it (used under stream capture, where this
-// makes parallel branches of the captured graph); otherwise in layer order
-// on g.stream.
-static void core(Graph &g, int layer, int bs, StageTimer *tm, bool fork = false) {
-    const int nb = (int)g.br.size();
-    if (!fork || layer >= 0 || nb < 2) {
-        for (int t = 0; t < g.T; ++t)
-            if (layer < 0 || t == layer) core_layer(g, t, bs, tm, g.stream);
-        return;
-    }
-    while ((int)g.side.size() < nb - 1) {
+int graph_branches(const Graph &g) { return std::min(g.T, kMaxBranches); }
+
+// Stream of branch r: g.stream for r = 0, else side stream r - 1 (created
+// on first use, default priority).
+hipStream_t graph_branch_stream(Graph &g, int r) {
+    if (r == 0) return g.stream;
+    while ((int)g.side.size() < r) {
         hipStream_t q;
         MLG_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
         g.side.push_back(q);
     }
+    return g.side[r - 1];
+}
+
+// All layers (layer = -1) or one.  With `fork`, the branches of an
+// all-layer product are enqueued on their own streams after an event on
+// g.stream and joined back into it (used under stream capture, where this
+// makes parallel branches of the captured graph); otherwise in layer order
+// on stream s (g.stream if null).
+static void core(Graph &g, int layer, int bs, StageTimer *tm, bool fork = false,
+                 hipStream_t s = nullptr) {
+    const int nb = (int)g.br.size();
+    if (!fork || layer >= 0 || nb < 2) {
+        for (int t = 0; t < g.T; ++t)
+            if (layer < 0 || t == layer) core_layer(g, t, bs, tm, s ? s : g.stream);
+        return;
+    }
+    for (int r = 1; r < nb; ++r) graph_branch_stream(g, r);
     while ((int)g.fork_join.size() < nb) {
         hipEvent_t e;
         MLG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -242,12 +253,12 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
 }
 
 const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
-                                  int64_t ldx) {
+                                  int64_t ldx, hipStream_t stream) {
     MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
     MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
     const int bs = block_stride(b);
     ensure_ws(g, bs);
-    hipStream_t s = g.stream;
+    hipStream_t s = stream ? stream : g.stream;
     const LayerIO *io = layer >= 0 ? g.io.p + layer : g.io.p;
     const int nl = layer >= 0 ? 1 : g.T;
     launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
@@ -258,7 +269,7 @@ const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, cons
         hipGraph_t graph;
         MLG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-            core(g, layer, bs, nullptr, true);
+            core(g, layer, bs, nullptr, s == g.stream, s);
         } catch (...) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(s, &junk);

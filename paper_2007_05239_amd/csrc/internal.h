@@ -135,8 +135,9 @@ constexpr int kPksmDefaultSteps = 128;
 int pksm_max_steps_device();
 // Y = (L_sym^(t) + delta I)^p X (one layer) or the layer mean of these terms,
 // p < 0, delta = log(1+|p|), by the polynomial Krylov method (Sec. 3).
-// Workspace for b columns and up to `max_steps` Krylov vectors is allocated
-// once and reused by every apply.
+// Workspace for b columns is allocated once per lane and reused by every
+// apply; the Krylov basis grows on demand up to `max_steps` vectors.  The
+// layers of different graph branches run side by side.
 struct PowerMeanOp {
     Graph &g;
     int b;
@@ -146,14 +147,34 @@ struct PowerMeanOp {
     int64_t rc = 0;            // rows per reduction block
     int nblk = 0;
     int nrow = 0;              // blocks of the row-per-thread kernels
-    DevBuf<double> V, W, part, xn, al, be, C[2], chg;
-    int vcap = 0;              // Krylov basis slots allocated in V (grown on demand)
-    void ensure_slots(int need);
-    DevBuf<int> fail;
+    // One Krylov run in flight: basis (grown on demand), work vectors,
+    // coefficients, and the stream it runs on (one lane per graph branch).
+    struct Lane {
+        DevBuf<double> V, W, part, xn, al, be, C[2], chg;
+        DevBuf<int> fail;
+        int vcap = 0;          // basis slots allocated in V
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+        std::vector<double> ch;
+        std::vector<int> bad;
+        int t = -1, m = 0, last = 1;
+        bool conv = false, active = false;
+    };
+    std::vector<Lane> lanes;
+    hipEvent_t free_ev = nullptr;
     int max_used = 0;          // longest Krylov dimension used so far
     int unconverged = 0;       // layer applications stopped at mcap
     int64_t layer_matvecs = 0; // single-vector layer matvecs
     PowerMeanOp(Graph &g, int b, double p, int max_steps);
+    ~PowerMeanOp();
+    PowerMeanOp(const PowerMeanOp &) = delete;
+    PowerMeanOp &operator=(const PowerMeanOp &) = delete;
+    void prepare(Lane &L);
+    void ensure_slots(Lane &L, int need);
+    void start(Lane &L, int t, const double *X, int64_t ldx);
+    void step(Lane &L, int j);
+    void run(const std::vector<int> &ts, const double *X, int64_t ldx);
+    void combine(Lane &L, double *Y, int64_t ldy, bool accumulate, double coef);
     void apply_layer(int t, const double *X, int64_t ldx, double *Y, int64_t ldy, bool accumulate,
                      double coef);
     // normalised: f / delta^p (spectrum in (0, 1]) instead of f.
@@ -217,8 +238,14 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
 // use_dinv) and the layers' summations, leaving F_t in the workspace slices
 // described by the returned device descriptors (one for layer >= 0, T for
 // -1; block stride = the next power of two >= b).  The caller enqueues its
-// own exit kernel on g.stream.
+// own exit kernel on the same stream: `stream`, or g.stream if null.  Two
+// layers may be enqueued on different streams at once only if they belong
+// to different branches (t mod graph_branches(g)).
 const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
-                                  int64_t ldx);
+                                  int64_t ldx, hipStream_t stream = nullptr);
+// Stream of branch r (g.stream for r = 0; side streams created on demand).
+hipStream_t graph_branch_stream(Graph &g, int r);
+// Number of branches (layers t and t' share scratch iff t = t' mod this).
+int graph_branches(const Graph &g);
 
 }  // namespace mlg
