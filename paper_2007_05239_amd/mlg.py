@@ -350,8 +350,10 @@ class Graph:
                                          MLG_DEVICE_PTRS))
         return Yc
 
-    def profile_stages(self, layer, op, X, reps=5):
-        """Average ms per matvec in each stage (dict), device tensors only."""
+    def profile_stages(self, layer, op, X, reps=5, return_y=False):
+        """Average ms per matvec in each stage (dict), device tensors only;
+        with return_y, also the product (n x b), computed without the HIP
+        graph and with the layers one after another."""
         import torch
         Xc, n, b = _colmajor(X)
         Y = torch.empty((b, n), dtype=torch.float64, device=Xc.device)
@@ -359,7 +361,8 @@ class Graph:
         _sync()
         _check(_lib.mlg_profile_stages(self._h, layer, op, b, _ptr(Xc)[0], n, _ptr(Y)[0], n, reps,
                                        ms, MLG_DEVICE_PTRS))
-        return dict(zip(STAGES, list(ms)))
+        st = dict(zip(STAGES, list(ms)))
+        return (st, Y.t()) if return_y else st
 
     def lanczos_eigs(self, layer, k, block=4, tol=1e-10, max_restarts=200, seed=0, p=1.0,
                      V0=None, device=False, inner_tol=0.0, inner_steps=0):

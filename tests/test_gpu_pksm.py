@@ -143,6 +143,24 @@ def test_power_matvec_arguments(mlg, direct_case):
     assert e.value.code == mlg.MLG_ERR_NOT_IMPL
 
 
+def test_power_matvec_more_layers_than_lanes(mlg):
+    """Four layers on three lanes: layers 0-2 run side by side, layer 3 after
+    them on the first lane; the terms are added in layer order."""
+    n, p = 500, -2.0
+    pts = [gen.gaussian_mixture(n, 3, 3, 0.06, 520)[0], gen.uniform_ball(n, 2, 1.0, 521),
+           gen.gaussian_mixture(n, 2, 4, 0.05, 522)[0], gen.uniform_ball(n, 1, 1.0, 523)]
+    sig = [0.15, 0.3, 0.1, 0.2]
+    g = mlg.Graph(pts, sig, [mlg.kparams("direct", 64)] * 4)
+    layers = [oracle.Layer(q, s) for q, s in zip(pts, sig)]
+    X = gen.test_vectors(n, 3, 524)
+    case_id("power matvec 4 layers / 3 lanes n=%d p=%g" % (n, p))
+    Y, info = g.power_mean_matvec(-1, p, X, tol=1e-12)
+    Y2, _ = g.power_mean_matvec(-1, p, X, tol=1e-12)
+    g.close()
+    assert info["converged"] and np.array_equal(Y, Y2)
+    assert power_err(Y, oracle.power_mean_power_matvec(layers, p, X), X, p) <= 1e-10
+
+
 @pytest.mark.parametrize("prec,window,gate", [(64, 12, 1e-6), (32, 6, 1e-4)])
 def test_power_matvec_nfft(mlg, prec, window, gate):
     n, p = 2500, -10.0

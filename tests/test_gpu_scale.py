@@ -153,6 +153,10 @@ def test_image_L1_repeat_bit_identical(mlg, image, image_graph):
         acc = acc + g.laplacian_matvec(t, mlg.MLG_OP_NADJ, X).cpu().numpy()
     Xh = X.cpu().numpy()
     np.testing.assert_allclose(Y1, Xh - acc / T, atol=1e-12 * np.abs(Xh).max())
+    # the captured product runs the layers as parallel branches; the same
+    # product without the graph, layers one after another, is bit-identical
+    _, Yseq = g.profile_stages(-1, mlg.MLG_OP_LSYM, X, reps=1, return_y=True)
+    assert np.array_equal(Y1, Yseq.cpu().numpy())
 
 
 def test_image_lanczos_and_allen_cahn(mlg, image, image_graph):
