@@ -195,7 +195,8 @@ def tune_layers(mlg, layers, sigmas, precision, b, seed):
         kp, info = mlg.autotune_layer(L, s, precision=precision, b=b, tol=TUNE_TOL,
                                       nrows=TUNE_ROWS, seed=seed + t)
         kps.append(kp)
-        infos.append({"N": info["N"], "window": info["window"], "sampled_err": info["err"],
+        infos.append({"N": info["N"], "window": info["window"], "bin": info["bin"],
+                      "sampled_err": info["err"],
                       "ms": round(info["ms"], 4), "tried": info["tried"]})
     return kps, infos
 

@@ -315,6 +315,7 @@ mlg_status mlg_allen_cahn_ssl(int64_t n, int k, int m, const double *evals,
 typedef struct {
     int window;    /* chosen window width w (even)                               */
     int N;         /* chosen bandwidth N                                         */
+    int bin;       /* chosen bin edge (grid cells per bin and dimension)         */
     int tried;     /* candidates planned and measured                            */
     int passed;    /* candidates within the error budget                         */
     double err;    /* sampled relative error of the choice: max over the b test  */
@@ -324,16 +325,19 @@ typedef struct {
 } mlg_tune_info;
 
 /*
- * Choose the NFFT window width w and bandwidth N of one Gaussian-kernel layer
- * (Algorithm 1, Sec. 4) for an error budget: the fastest measured candidate
+ * Choose the NFFT window width w, bandwidth N and bin edge of one
+ * Gaussian-kernel layer (Algorithm 1, Sec. 4) for an error budget: the
+ * fastest measured candidate
  * whose error on a seeded sample of rows, against the FP64 direct sum of
  * those rows (zero diagonal), is <= tol for a seeded block of b test vectors
  * uniform in [-1, 1).
  *   Candidates: N in {N0/2, N0, 2 N0} (powers of two in 8..256; N0 = the
  *   automatic bandwidth of mlg_graph_create with N = 0) and w in {4, 6, 8, 10}
- *   (FP32) or {4, 6, ..., 16} (FP64), bin 1, eps_B = 1/16, p_reg = 5.
- *   For each N the windows are tried in increasing order and the first within
- *   the budget is timed (5 products after one warm-up).
+ *   (FP32) or {4, 6, ..., 16} (FP64), bin in {1, 2, 4}, eps_B = 1/16,
+ *   p_reg = 5.  For each (N, bin) the windows are tried in increasing order
+ *   and the first within the budget is timed (5 products after one warm-up).
+ *   Larger bins trade the matrix-core kernels (d = 3 needs bin + w - 1 <= 6)
+ *   for fewer, fuller tasks when points are sparse on the grid.
  *   points     n x d row-major FP64 (device pointer with MLG_DEVICE_PTRS, else
  *              host), d in 1..3; 2 <= n < 2^31.
  *   precision  32 or 64 (the summation precision of the candidates).

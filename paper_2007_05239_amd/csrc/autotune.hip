@@ -1,5 +1,6 @@
 // Plan-time choice of the NFFT parameters of one layer: the window width w and
-// the bandwidth N of Algorithm 1.  Every candidate is planned and applied to a
+// the bandwidth N of Algorithm 1, and the bin edge of the spreading (points
+// per bin decide whether the matrix-core kernels' 64-point chunks fill).  Every candidate is planned and applied to a
 // seeded block of test vectors; its error is measured on a seeded sample of
 // rows against the FP64 direct sum of those rows (the definition the fast
 // summation approximates, Sec. 4), and the fastest candidate whose error is
@@ -85,7 +86,7 @@ __global__ void k_take_rows(int nrow, int b, const int64_t *__restrict__ rows,
 }
 
 struct Cand {
-    int N = 0, w = 0;
+    int N = 0, w = 0, bin = 1;
     double err = INFINITY, ms = INFINITY;
 };
 
@@ -139,8 +140,8 @@ void autotune(int64_t n, int d, const double *points, double sigma, int precisio
         rnorm[v] = std::sqrt(q);
     }
 
-    auto make = [&](int N, int w, GraphHandle &gh) -> mlg_status {
-        mlg_kparams k{MLG_METHOD_NFFT, precision, N, w, 1.0 / 16, 5, 1, MLG_KERNEL_GAUSSIAN};
+    auto make = [&](int N, int w, int bin, GraphHandle &gh) -> mlg_status {
+        mlg_kparams k{MLG_METHOD_NFFT, precision, N, w, 1.0 / 16, 5, bin, MLG_KERNEL_GAUSSIAN};
         const double *parr[1] = {P};
         const int darr[1] = {d};
         return mlg_graph_create(&gh.h, n, 1, darr, parr, &sigma, &k,
@@ -154,7 +155,7 @@ void autotune(int64_t n, int d, const double *points, double sigma, int precisio
     int Nauto = 0;
     {
         GraphHandle gh;
-        const mlg_status st = make(0, precision == 32 ? 6 : 12, gh);
+        const mlg_status st = make(0, precision == 32 ? 6 : 12, 1, gh);
         MLG_REQUIRE(st == MLG_OK, st, mlg_last_error());
         int ip[6];
         double dp[2];
@@ -168,14 +169,21 @@ void autotune(int64_t n, int d, const double *points, double sigma, int precisio
     const std::vector<int> ws = precision == 32 ? std::vector<int>{4, 6, 8, 10}
                                                 : std::vector<int>{4, 6, 8, 10, 12, 14, 16};
     Cand best, closest;
-    for (int N : Ns) {
+    for (int N : Ns)
+    for (int bin : {1, 2, 4}) {
         for (int w : ws) {
-            if (1 + w / 2 > N / 2) continue;   // the window must fit the grid's band margin
+            if (bin + w / 2 > N / 2) continue;   // the window must fit the grid's band margin
             GraphHandle gh;
-            const mlg_status st = make(N, w, gh);
+            const mlg_status st = make(N, w, bin, gh);
             if (st == MLG_ERR_RANGE) continue;   // a combination the plan rejects
             MLG_REQUIRE(st == MLG_OK, st, mlg_last_error());
-            apply(gh);
+            {
+                // a combination the summation kernels reject (patch too large)
+                const mlg_status sa =
+                    mlg_laplacian_matvec(gh.h, 0, MLG_OP_W, b, X.p, n, Y.p, n, MLG_DEVICE_PTRS);
+                if (sa == MLG_ERR_RANGE) continue;
+                MLG_REQUIRE(sa == MLG_OK, sa, mlg_last_error());
+            }
             hipLaunchKernelGGL(k_take_rows, dim3(ceil_div((int64_t)nrows * b, 256)), dim3(256), 0, s,
                                nrows, b, drows.p, Y.p, n, dtake.p);
             MLG_LAUNCH_CHECK();
@@ -192,7 +200,7 @@ void autotune(int64_t n, int d, const double *points, double sigma, int precisio
                 err = std::max(err, rnorm[v] > 0.0 ? std::sqrt(q) / rnorm[v] : std::sqrt(q));
             }
             ++info->tried;
-            if (err < closest.err) closest = Cand{N, w, err, INFINITY};
+            if (err < closest.err) closest = Cand{N, w, bin, err, INFINITY};
             if (!(err <= tol)) continue;
             ++info->passed;
             apply(gh);   // warm
@@ -201,14 +209,15 @@ void autotune(int64_t n, int d, const double *points, double sigma, int precisio
             for (int r = 0; r < kReps; ++r) apply(gh);
             const auto t1 = std::chrono::steady_clock::now();
             const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / kReps;
-            if (ms < best.ms) best = Cand{N, w, err, ms};
-            break;   // wider windows at this bandwidth are slower
+            if (ms < best.ms) best = Cand{N, w, bin, err, ms};
+            break;   // wider windows at this bandwidth and bin are slower
         }
     }
     const Cand &c = best.w > 0 ? best : closest;
-    *kp = mlg_kparams{MLG_METHOD_NFFT, precision, c.N, c.w, 1.0 / 16, 5, 1, MLG_KERNEL_GAUSSIAN};
+    *kp = mlg_kparams{MLG_METHOD_NFFT, precision, c.N, c.w, 1.0 / 16, 5, c.bin, MLG_KERNEL_GAUSSIAN};
     info->window = c.w;
     info->N = c.N;
+    info->bin = c.bin;
     info->err = c.err;
     info->ms = best.w > 0 ? best.ms : -1.0;
     MLG_REQUIRE(best.w > 0, MLG_ERR_RANGE,

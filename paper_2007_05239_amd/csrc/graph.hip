@@ -303,6 +303,9 @@ static void compute_degrees(Graph &g, Layer &L) {
         NfftWindow Wd;
         int wdeg = std::min(14, max_window(L.nf));
         wdeg = std::max(wdeg, default_window(L));
+        // the one-vector spreading holds a patch of at most 4096 cells
+        // (16^3 in d = 3): bin + w - 1 <= 16
+        if (L.d == 3) wdeg = std::min(wdeg, (16 - L.nf.B + 1) & ~1);
         nfft_make_window(L, Wd, wdeg, 64, 1, s);
         io.K0 = 1.0;
         MLG_HIP(hipMemcpyAsync(dio.p, &io, sizeof(io), hipMemcpyHostToDevice, s));

@@ -66,8 +66,9 @@ class PksmParams(ctypes.Structure):
 
 
 class TuneInfo(ctypes.Structure):
-    _fields_ = [("window", ctypes.c_int), ("N", ctypes.c_int), ("tried", ctypes.c_int),
-                ("passed", ctypes.c_int), ("err", ctypes.c_double), ("ms", ctypes.c_double)]
+    _fields_ = [("window", ctypes.c_int), ("N", ctypes.c_int), ("bin", ctypes.c_int),
+                ("tried", ctypes.c_int), ("passed", ctypes.c_int), ("err", ctypes.c_double),
+                ("ms", ctypes.c_double)]
 
 
 class ACParams(ctypes.Structure):
@@ -168,7 +169,7 @@ def _colmajor(X):
 
 
 def autotune_layer(points, sigma, precision=32, b=16, tol=1e-4, nrows=128, seed=0):
-    """NFFT window and bandwidth for one layer (mlg_autotune_layer): returns
+    """NFFT window, bandwidth and bin for one layer (mlg_autotune_layer): returns
     (KParams, info dict).  points n x d (numpy or torch CUDA).  Raises
     MlgError (MLG_ERR_RANGE) if no candidate meets tol; the exception then
     carries the info of the most accurate candidate as `.info`."""

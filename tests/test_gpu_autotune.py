@@ -2,7 +2,8 @@
 window and bandwidth meet the error budget on the full product against the
 oracle (the tuner itself measures a row sample, so the full-product gate is
 twice the budget), an unreachable budget is reported as MLG_ERR_RANGE with
-the most accurate candidate, and host and device inputs choose alike.
+the most accurate candidate, and host and device inputs measure the same
+candidates with the same errors.
 """
 import numpy as np
 import pytest
@@ -42,10 +43,11 @@ def test_autotune_meets_budget(mlg, ball, prec, tol):
     pts, sig = ball
     case_id("autotune fp%d tol %.0e n=%d" % (prec, tol, pts.shape[0]))
     kp, info = mlg.autotune_layer(pts, sig, precision=prec, b=8, tol=tol, nrows=256, seed=5)
-    case_id("  chose N=%d w=%d err %.2e %.3f ms (%d tried, %d within)" % (
-        info["N"], info["window"], info["err"], info["ms"], info["tried"], info["passed"]))
+    case_id("  chose N=%d w=%d bin=%d err %.2e %.3f ms (%d tried, %d within)" % (
+        info["N"], info["window"], info["bin"], info["err"], info["ms"], info["tried"], info["passed"]))
     assert info["err"] <= tol and info["ms"] > 0 and 1 <= info["passed"] <= info["tried"]
-    assert kp.N == info["N"] and kp.window == info["window"] and kp.precision == prec
+    assert kp.N == info["N"] and kp.window == info["window"] and kp.bin == info["bin"]
+    assert kp.precision == prec and info["bin"] in (1, 2, 4)
     X = gen.test_vectors(pts.shape[0], 4, 1003)
     Y = mlg.kernel_matvec(pts, sig, X, kp)
     assert rel_err(Y, oracle.kernel_matvec(pts, sig, X)) <= 2 * tol
@@ -61,11 +63,16 @@ def test_autotune_unreachable_budget(mlg, ball):
     assert info["tried"] >= 1 and info["passed"] == 0 and info["err"] > 1e-10 and info["ms"] < 0
 
 
-def test_autotune_device_input_same_choice(mlg, ball):
+def test_autotune_device_input_same_candidates(mlg, ball):
     import torch
     pts, sig = ball
     case_id("autotune host vs device input")
     kh, ih = mlg.autotune_layer(pts, sig, precision=32, b=4, tol=1e-4, nrows=128, seed=7)
     kd, idv = mlg.autotune_layer(torch.from_numpy(pts).cuda(), sig, precision=32, b=4, tol=1e-4,
                                  nrows=128, seed=7)
-    assert (kh.N, kh.window) == (kd.N, kd.window) and ih["err"] == idv["err"]
+    # which candidates are tried and which meet the budget depends only on the
+    # (deterministic) errors; the pick among those within the budget is by
+    # measured time
+    assert (ih["tried"], ih["passed"]) == (idv["tried"], idv["passed"])
+    if (kh.N, kh.window, kh.bin) == (kd.N, kd.window, kd.bin):
+        assert ih["err"] == idv["err"]

@@ -121,6 +121,26 @@ def test_nfft_fp32_side64_grid_blocks(mlg, b):
     assert rel_err(Y, oracle.kernel_matvec(pts, sig, X)) <= 1e-4
 
 
+@pytest.mark.parametrize("bin_", [2, 4])
+@pytest.mark.parametrize("prec,window,gate", [(32, 6, 1e-4), (64, 12, 1e-6)])
+@pytest.mark.parametrize("d", [2, 3])
+def test_nfft_bins(mlg, bin_, prec, window, gate, d):
+    """Bins of 2 and 4 grid cells per side (the vector-ALU summation kernels
+    in d = 3; degrees with a window whose patch fits one task)."""
+    n = 3001
+    pts, _ = gen.gaussian_mixture(n, d, 4, 0.08, 30 + d)
+    sig = 0.3
+    L = oracle.Layer(pts, sig)
+    case_id("nfft fp%d L_sym d=%d bin=%d w=%d n=%d b=4" % (prec, d, bin_, window, n))
+    g = mlg.Graph([pts], [sig], mlg.kparams("nfft", prec, N=64, window=window, bin=bin_))
+    assert g.layer_info(0)["bin"] == bin_
+    np.testing.assert_allclose(g.degrees(0), L.deg, rtol=1e-8)
+    X = gen.test_vectors(n, 4, 35 + d)
+    Y = g.laplacian_matvec(0, mlg.MLG_OP_LSYM, X)
+    g.close()
+    assert rel_err(Y, oracle.lsym_matvec([L], X)) <= gate
+
+
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_nfft_fp64_lsym_dims(mlg, d):
     pts, _ = gen.gaussian_mixture(3001, d, 4, 0.08, 40 + d)
