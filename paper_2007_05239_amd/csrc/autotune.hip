@@ -209,7 +209,9 @@ void autotune(int64_t n, int d, const double *points, double sigma, int precisio
             for (int r = 0; r < kReps; ++r) apply(gh);
             const auto t1 = std::chrono::steady_clock::now();
             const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / kReps;
-            if (ms < best.ms) best = Cand{N, w, bin, err, ms};
+            // a later candidate (larger N or bin) must be 5 % faster to win,
+            // so that near ties do not flip with timing noise
+            if (best.w == 0 || ms < 0.95 * best.ms) best = Cand{N, w, bin, err, ms};
             break;   // wider windows at this bandwidth and bin are slower
         }
     }
