@@ -53,6 +53,18 @@ def test_autotune_meets_budget(mlg, ball, prec, tol):
     assert rel_err(Y, oracle.kernel_matvec(pts, sig, X)) <= 2 * tol
 
 
+@pytest.mark.parametrize("d,sig", [(1, 0.2), (2, 0.3)])
+def test_autotune_low_dimensions(mlg, d, sig):
+    pts = gen.uniform_ball(4000, d, 1.0, 1010 + d)
+    case_id("autotune fp32 d=%d" % d)
+    kp, info = mlg.autotune_layer(pts, sig, precision=32, b=4, tol=1e-4, nrows=256, seed=9)
+    case_id("  chose N=%d w=%d bin=%d err %.2e" % (info["N"], info["window"], info["bin"], info["err"]))
+    assert info["err"] <= 1e-4
+    X = gen.test_vectors(pts.shape[0], 4, 1012)
+    Y = mlg.kernel_matvec(pts, sig, X, kp)
+    assert rel_err(Y, oracle.kernel_matvec(pts, sig, X)) <= 2e-4
+
+
 def test_autotune_unreachable_budget(mlg, ball):
     pts, sig = ball
     case_id("autotune fp32 unreachable tol")
