@@ -143,7 +143,11 @@ def power_leg(g, X, c, n, T, b):
         torch.cuda.synchronize()
         eig["p=%g" % pe] = {"seconds": round(time.perf_counter() - t0, 4), "block": blk,
                             "outer_iters": einf["iters"], "restarts": einf["restarts"],
-                            "inner_steps": einf["inner_steps"], "converged": einf["converged"]}
+                            "inner_steps": einf["inner_steps"], "converged": einf["converged"],
+                            # max over the k pairs of ||A phi - mu phi|| (A = I - L_1 for
+                            # p = 1, delta^-p L_{p,delta}^p for p < 0; unit phi): the
+                            # eigenpair error evidence at a size no dense oracle reaches
+                            "nconv": einf["nconv"], "max_resid": einf["max_resid"]}
     return {"p": p, "delta": math.log1p(abs(p)), "block": b,
             "ms_per_power_matvec": round(el_p * 1e3, 3), "inner_steps": pinf["steps"],
             "inner_tol": 1e-7, "layer_rows_per_s": n * T * b * pinf["steps"] / el_p,
