@@ -252,8 +252,14 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
     launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
 }
 
+const LayerIO *graph_layer_io(Graph &g, int b, int t) {
+    MLG_REQUIRE(t >= 0 && t < g.T && b >= 1 && b <= 64, MLG_ERR_ARG, "layer or block out of range");
+    ensure_ws(g, block_stride(b));
+    return g.io.p + t;
+}
+
 const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
-                                  int64_t ldx, hipStream_t stream) {
+                                  int64_t ldx, hipStream_t stream, bool scatter) {
     MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
     MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
     const int bs = block_stride(b);
@@ -261,7 +267,7 @@ const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, cons
     hipStream_t s = stream ? stream : g.stream;
     const LayerIO *io = layer >= 0 ? g.io.p + layer : g.io.p;
     const int nl = layer >= 0 ? 1 : g.T;
-    launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
+    if (scatter) launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
     hipGraphExec_t exec = nullptr;
     for (auto &c : g.caps)
         if (c.layer == layer && c.b == bs) exec = c.exec;

@@ -169,6 +169,9 @@ struct PowerMeanOp {
     ~PowerMeanOp();
     PowerMeanOp(const PowerMeanOp &) = delete;
     PowerMeanOp &operator=(const PowerMeanOp &) = delete;
+    bool fuse = false;         // next vector and the layer's summation input in one pass
+    void scale_next(Lane &L, const double *X, int64_t ldx, const double *den, int dstride,
+                    double *Vnext);
     void prepare(Lane &L);
     void ensure_slots(Lane &L, int need);
     void start(Lane &L, int t, const double *X, int64_t ldx);
@@ -241,8 +244,13 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
 // own exit kernel on the same stream: `stream`, or g.stream if null.  Two
 // layers may be enqueued on different streams at once only if they belong
 // to different branches (t mod graph_branches(g)).
+// With scatter = false the entry kernel is skipped: the caller has written
+// the layers' summation inputs itself (see graph_layer_io).
 const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
-                                  int64_t ldx, hipStream_t stream = nullptr);
+                                  int64_t ldx, hipStream_t stream = nullptr, bool scatter = true);
+// Device descriptor of layer t's slices for blocks of b vectors (workspace
+// laid out for that block stride first).
+const LayerIO *graph_layer_io(Graph &g, int b, int t);
 // Stream of branch r (g.stream for r = 0; side streams created on demand).
 hipStream_t graph_branch_stream(Graph &g, int r);
 // Number of branches (layers t and t' share scratch iff t = t' mod this).
