@@ -154,7 +154,8 @@ def test_nfft_fp64_lsym_dims(mlg, d):
     assert rel_err(Y, oracle.lsym_matvec([L], X)) <= 1e-6
 
 
-def test_nfft_fp32_multilayer_mean(mlg):
+@pytest.mark.parametrize("b", [1, 5, 16])
+def test_nfft_fp32_multilayer_mean(mlg, b):
     n = 4099
     p3, _ = gen.gaussian_mixture(n, 3, 5, 0.05, 61)
     p2 = gen.uniform_ball(n, 2, 10.0, 62)
@@ -164,8 +165,8 @@ def test_nfft_fp32_multilayer_mean(mlg):
     kp = [mlg.kparams("nfft", 32, N=32, window=6), mlg.kparams("nfft", 32, N=32, window=6),
           mlg.kparams("nfft", 32, N=64, window=6)]
     g = mlg.Graph([p3, p2, p1], sig, kp)
-    X = gen.test_vectors(n, 16, 64)
-    case_id("nfft fp32 L_1 x T=3 n=%d b=16" % n)
+    X = gen.test_vectors(n, b, 64)
+    case_id("nfft fp32 L_1 x T=3 n=%d b=%d" % (n, b))
     Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, X)
     assert rel_err(Y, oracle.lsym_matvec(layers, X)) <= 1e-4
     Y2 = g.laplacian_matvec(-1, mlg.MLG_OP_NADJ, X)
