@@ -134,8 +134,14 @@ const char *mlg_version(void);
  *            stream owned by the handle).
  * Plans every layer (torus scaling, kernel Fourier coefficients, bin sort)
  * and, unless MLG_SKIP_DEGREES is given, computes each layer's degrees in
- * FP64.  Returns MLG_ERR_ISOLATED if a degree is not positive (below 1e-9
- * for NFFT layers).
+ * FP64: direct layers by the direct sum, NFFT layers by one FP64 fast
+ * summation of the ones vector with a plan of its own (bandwidth from the
+ * FP64 tail rule, at least the layer's N; window 14, or 12 when a bin of 4
+ * is needed to keep its patches below 2 GiB).  The NFFT degree pass's error
+ * is measured on 64 evenly spaced rows against the FP64 direct sum.
+ * Returns MLG_ERR_ISOLATED if a degree is zero (direct layers) or at most 64
+ * times that measured error (NFFT layers: the pass cannot tell it from
+ * zero), and MLG_ERR_ARG if a coordinate is not finite.
  */
 mlg_status mlg_graph_create(mlg_graph **out, int64_t n, int T, const int *d,
                             const double *const *points, const double *sigma,

@@ -231,6 +231,16 @@ void autotune(int64_t n, int d, const double *points, double sigma, int precisio
 
 }  // namespace mlg
 
+namespace mlg {
+void launch_ref_rows(int64_t n, int d, const double *pts, double sigma, const int64_t *rows,
+                     int nrow, int b, const double *X, int64_t ldx, double *out, hipStream_t s) {
+    MLG_REQUIRE(d >= 1 && d <= 3 && nrow >= 1, MLG_ERR_ARG, "reference rows: bad shape");
+    hipLaunchKernelGGL(k_ref_rows, dim3(nrow), dim3(256), 0, s, n, d, pts, 1.0 / (sigma * sigma),
+                       rows, nrow, b, X, ldx, out);
+    MLG_LAUNCH_CHECK();
+}
+}  // namespace mlg
+
 extern "C" mlg_status mlg_autotune_layer(int64_t n, int d, const double *points, double sigma,
                                          int precision, int b, double tol, int nrows,
                                          uint64_t seed, int flags, void *stream, mlg_kparams *kp,

@@ -194,28 +194,34 @@ __global__ void k_direct_reduce(int64_t total, int S, const T *__restrict__ part
 }
 
 // ---- coordinates -----------------------------------------------------------------
-// Per dimension (one workgroup each): bounding-box midpoint.
+// Per dimension (one workgroup each): bounding-box midpoint, or NaN if a
+// coordinate of that dimension is not finite (fmin/fmax would skip a NaN).
 __global__ __launch_bounds__(256) void k_bbox_mid(int64_t n, int d, const double *__restrict__ pts,
                                                   double *__restrict__ mid) {
     __shared__ double lo[256], hi[256];
+    __shared__ int bad[256];
     const int k = blockIdx.x;
     double a = pts[k], b = pts[k];
+    int nf = 0;
     for (int64_t i = threadIdx.x; i < n; i += 256) {
         const double v = pts[i * d + k];
+        nf |= !isfinite(v);
         a = fmin(a, v);
         b = fmax(b, v);
     }
     lo[threadIdx.x] = a;
     hi[threadIdx.x] = b;
+    bad[threadIdx.x] = nf;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if (threadIdx.x < h) {
             lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + h]);
             hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + h]);
+            bad[threadIdx.x] |= bad[threadIdx.x + h];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) mid[k] = 0.5 * (lo[0] + hi[0]);
+    if (threadIdx.x == 0) mid[k] = bad[0] ? __builtin_nan("") : 0.5 * (lo[0] + hi[0]);
 }
 
 // x64 = (x - mid) s64, x32 = (x - mid) s32, SoA d x n.
@@ -231,20 +237,30 @@ __global__ void k_direct_coords(int64_t n, int d, const double *__restrict__ pts
     }
 }
 
+void direct_coords_into(int64_t n, int d, const double *pts_dev, double sigma, int kernel,
+                        double *mid, double *x64, float *x32, hipStream_t s) {
+    MLG_REQUIRE(d >= 1 && d <= kDirectMaxD, MLG_ERR_RANGE, "direct summation supports d <= 16");
+    hipLaunchKernelGGL(k_bbox_mid, dim3(d), dim3(256), 0, s, n, d, pts_dev, mid);
+    MLG_LAUNCH_CHECK();
+    const double log2e = 1.4426950408889634;
+    const double s32 = (kernel == MLG_KERNEL_LAPLACIAN ? log2e : std::sqrt(log2e)) / sigma;
+    hipLaunchKernelGGL(k_direct_coords, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, pts_dev, mid,
+                       1.0 / sigma, s32, x64, x32);
+    MLG_LAUNCH_CHECK();
+}
+
 void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, int kernel,
                    DevBuf<double> &x64, DevBuf<float> &x32, hipStream_t s) {
     MLG_REQUIRE(d >= 1 && d <= kDirectMaxD, MLG_ERR_RANGE, "direct summation supports d <= 16");
     DevBuf<double> mid(d);
-    hipLaunchKernelGGL(k_bbox_mid, dim3(d), dim3(256), 0, s, n, d, pts_dev, mid.p);
-    MLG_LAUNCH_CHECK();
     x64.alloc((size_t)n * d);
     x32.alloc((size_t)n * d);
-    const double log2e = 1.4426950408889634;
-    const double s32 = (kernel == MLG_KERNEL_LAPLACIAN ? log2e : std::sqrt(log2e)) / sigma;
-    hipLaunchKernelGGL(k_direct_coords, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, pts_dev, mid.p,
-                       1.0 / sigma, s32, x64.p, x32.p);
-    MLG_LAUNCH_CHECK();
+    direct_coords_into(n, d, pts_dev, sigma, kernel, mid.p, x64.p, x32.p, s);
+    double hm[kDirectMaxD];
+    MLG_HIP(hipMemcpyAsync(hm, mid.p, sizeof(double) * d, hipMemcpyDeviceToHost, s));
     MLG_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < d; ++k)
+        MLG_REQUIRE(std::isfinite(hm[k]), MLG_ERR_ARG, "point coordinates must be finite");
 }
 
 // ---- launch ------------------------------------------------------------------------

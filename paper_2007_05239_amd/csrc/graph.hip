@@ -292,8 +292,21 @@ const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, cons
     return io;
 }
 
-// Degrees deg = W 1 in FP64: for NFFT layers a high-accuracy FP64 window.
-static void compute_degrees(Graph &g, Layer &L) {
+// Patch bytes above which the degree pass takes a larger bin.
+constexpr double kDegPatchBytes = 2.0 * (1 << 30);
+// Rows sampled to measure the degree pass's error, and the margin of the
+// isolation threshold over the largest sampled error.
+constexpr int kDegSampleRows = 64;
+constexpr double kDegMargin = 64.0;
+
+// Degrees deg = W 1 in FP64 (Sec. 2).  NFFT layers take a plan of their own
+// for this one product: bandwidth from the FP64 tail rule (at least the
+// layer's own), FP64 window of width 14, the smallest bin whose patches fit
+// kDegPatchBytes.  Its error is then measured on kDegSampleRows rows against
+// the FP64 direct sum of those rows, and a degree at or below kDegMargin times
+// that error (the pass cannot tell it from zero) is MLG_ERR_ISOLATED.  Direct
+// layers sum exactly up to rounding; there only a zero degree is isolated.
+static void compute_degrees(Graph &g, Layer &L, const double *pts) {
     hipStream_t s = g.stream;
     const int64_t n = g.n;
     DevBuf<double> ones(n), Z(n), F(n);
@@ -305,21 +318,68 @@ static void compute_degrees(Graph &g, Layer &L) {
     io.dinv = nullptr;
     io.is64 = 1;
     DevBuf<LayerIO> dio(1);
+    double thresh = 0.0;
     if (L.kp.method == MLG_METHOD_NFFT) {
+        Layer Ld;
+        Ld.d = L.d;
+        Ld.sigma = L.sigma;
+        Ld.n = n;
+        Ld.kp = L.kp;
+        Ld.kp.precision = 64;
+        Ld.kp.N = std::max(L.nf.N, nfft_auto_bandwidth(L.nf.sigma_s, L.d, 64));
+        // bin 1 unless its patches are too large and a larger bin still admits
+        // a window of at least 10
+        auto deg_window = [&](int B) {
+            int w = std::min(14, max_window(Ld.nf));
+            // the one-vector spreading holds a patch of at most 4096 cells
+            // (16^3 in d = 3): bin + w - 1 <= 16
+            if (L.d == 3) w = std::min(w, (16 - B + 1) & ~1);
+            return w;
+        };
+        auto patch_bytes = [&](int B, int w) {
+            double cells = 1.0;
+            for (int t = 0; t < L.d; ++t) cells *= (double)(B + w - 1);
+            return cells * 8.0 * (double)(Ld.nf.nruns + Ld.nf.nscratch);
+        };
+        Ld.kp.bin = 1;
+        nfft_plan_layer(Ld, pts, s);
+        int wdeg = deg_window(1);
+        for (int B = 2; B <= 4 && patch_bytes(Ld.nf.B, wdeg) > kDegPatchBytes; B *= 2) {
+            if (B / 2 + 5 > Ld.nf.N / 2) break;   // bin + 10/2 <= N/2 needed
+            Ld.kp.bin = B;
+            nfft_plan_layer(Ld, pts, s);
+            wdeg = deg_window(B);
+        }
         NfftWindow Wd;
-        int wdeg = std::min(14, max_window(L.nf));
-        wdeg = std::max(wdeg, default_window(L));
-        // the one-vector spreading holds a patch of at most 4096 cells
-        // (16^3 in d = 3): bin + w - 1 <= 16
-        if (L.d == 3) wdeg = std::min(wdeg, (16 - L.nf.B + 1) & ~1);
-        nfft_make_window(L, Wd, wdeg, 64, 1, s);
+        nfft_make_window(Ld, Wd, wdeg, 64, 1, s);
         io.K0 = 1.0;
         MLG_HIP(hipMemcpyAsync(dio.p, &io, sizeof(io), hipMemcpyHostToDevice, s));
         launch_scatter_in(n, 1, 1, ones.p, n, dio.p, 1, 0, s);
-        DevBuf<double> patch(nfft_patch_elems(L.nf, Wd, 1)), grid(nfft_grid_elems(L.nf, 1));
-        nfft_apply<double>(L.nf, Wd, 1, Z.p, F.p, patch.p, grid.p, s, nullptr);
+        DevBuf<double> patch(nfft_patch_elems(Ld.nf, Wd, 1)), grid(nfft_grid_elems(Ld.nf, 1));
+        nfft_apply<double>(Ld.nf, Wd, 1, Z.p, F.p, patch.p, grid.p, s, nullptr);
         launch_gather_out(n, 1, 1, ones.p, n, L.deg.p, n, dio.p, 1, 0, 0, 1.0, s);
+        // measured error on evenly spaced rows
+        const int ns = (int)std::min<int64_t>(n, kDegSampleRows);
+        std::vector<int64_t> rows(ns);
+        for (int k = 0; k < ns; ++k) rows[k] = (int64_t)((double)k * (double)n / ns);
+        DevBuf<int64_t> drows;
+        upload(drows, rows.data(), rows.size(), false, s);
+        DevBuf<double> ref(ns);
+        launch_ref_rows(n, L.d, pts, L.sigma, drows.p, ns, 1, ones.p, n, ref.p, s);
+        std::vector<double> href(ns);
+        MLG_HIP(hipMemcpyAsync(href.data(), ref.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+        std::vector<double> got(ns);
+        for (int k = 0; k < ns; ++k)
+            MLG_HIP(hipMemcpyAsync(&got[k], L.deg.p + rows[k], 8, hipMemcpyDeviceToHost, s));
         MLG_HIP(hipStreamSynchronize(s));
+        double err = 0.0, typ = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            err = std::max(err, std::fabs(got[k] - href[k]));
+            typ = std::max(typ, href[k]);
+        }
+        L.deg_err = err;
+        // FP64 rounding floor of an n-term sum of weights <= 1
+        thresh = kDegMargin * std::max(err, 1e-16 * std::max(typ, 1.0));
     } else {
         io.K0 = 0.0;
         MLG_HIP(hipMemcpyAsync(dio.p, &io, sizeof(io), hipMemcpyHostToDevice, s));
@@ -329,15 +389,20 @@ static void compute_degrees(Graph &g, Layer &L) {
                               part.n, s);
         launch_gather_out(n, 1, 1, ones.p, n, L.deg.p, n, dio.p, 1, 0, 0, 1.0, s);
         MLG_HIP(hipStreamSynchronize(s));
+        L.deg_err = 0.0;
     }
+    L.iso_thresh = thresh;
     DevBuf<int> flag(1);
     MLG_HIP(hipMemsetAsync(flag.p, 0, 4, s));
-    const double thresh = L.kp.method == MLG_METHOD_NFFT ? 1e-9 : 0.0;
     launch_check_degrees(n, L.deg.p, thresh, flag.p, s);
     int hf = 0;
     MLG_HIP(hipMemcpyAsync(&hf, flag.p, 4, hipMemcpyDeviceToHost, s));
     MLG_HIP(hipStreamSynchronize(s));
-    MLG_REQUIRE(hf == 0, MLG_ERR_ISOLATED, "a node has zero degree (isolated) in some layer");
+    MLG_REQUIRE(hf == 0, MLG_ERR_ISOLATED,
+                "a node has zero degree (isolated) in some layer: degree <= " +
+                    std::to_string(thresh) + (L.kp.method == MLG_METHOD_NFFT
+                                                  ? " (the degree pass's measured error margin)"
+                                                  : ""));
     L.dinv.alloc(n);
     launch_dinv(n, L.deg.p, L.dinv.p, s);
     MLG_HIP(hipStreamSynchronize(s));
@@ -360,7 +425,7 @@ static void build_layer(Graph &g, Layer &L, const double *pts, bool dev, bool de
         nfft_make_window(L, L.win, w, L.kp.precision, 1, s);
     }
     MLG_HIP(hipStreamSynchronize(s));
-    if (degrees) compute_degrees(g, L);
+    if (degrees) compute_degrees(g, L, p);
 }
 
 static hipStream_t make_stream(void *user) {

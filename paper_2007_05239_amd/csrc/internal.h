@@ -67,6 +67,8 @@ struct Layer {
     NfftWindow win;          // matvec window
     DevBuf<double> deg;      // degrees, original order
     DevBuf<double> dinv;     // D^-1/2, original order
+    double deg_err = 0;      // NFFT: largest sampled absolute error of the degree pass
+    double iso_thresh = 0;   // degrees <= this are isolated (MLG_ERR_ISOLATED)
 };
 
 // What the block entry/exit kernels need to know about one layer.
@@ -92,8 +94,14 @@ void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s);
 // ---- direct.hip ---------------------------------------------------------------
 // Scaled, centred coordinates of a direct layer (d x n SoA): x64 for the
 // FP64 kernels, x32 for the FP32 kernels; kernel = MLG_KERNEL_*.
+// Returns MLG_ERR_ARG if a coordinate is not finite.
 void direct_coords(int64_t n, int d, const double *pts_dev, double sigma, int kernel,
                    DevBuf<double> &x64, DevBuf<float> &x32, hipStream_t s);
+// The same into caller-provided buffers (mid: d doubles; x64, x32: n x d),
+// enqueued only: no allocation, no wait.  A non-finite coordinate makes its
+// dimension's midpoint NaN, and with it every coordinate of that dimension.
+void direct_coords_into(int64_t n, int d, const double *pts_dev, double sigma, int kernel,
+                        double *mid, double *x64, float *x32, hipStream_t s);
 // Fs = W Zs (zero diagonal) for n points with coordinates from direct_coords;
 // part: S x n x bs column-split partials (direct_part_size elements).
 template <class T>
@@ -104,6 +112,8 @@ size_t direct_part_size(int64_t n, int bs);
 
 // ---- nfft.hip -----------------------------------------------------------------
 void nfft_plan_layer(Layer &L, const double *pts_dev, hipStream_t s);
+// Bandwidth of the automatic rule (N = 0) for a scaled sigma and precision.
+int nfft_auto_bandwidth(double sigma_s, int d, int prec);
 void nfft_make_window(const Layer &L, NfftWindow &W, int w, int prec, int bs, hipStream_t s);
 size_t nfft_patch_elems(const NfftPlan &P, const NfftWindow &W, int bs);
 size_t nfft_grid_elems(const NfftPlan &P, int bs);
@@ -126,6 +136,12 @@ struct LanczosOp {
 mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int block, double tol, int max_restarts,
                        uint64_t seed, const double *V0_dev, double *evals_host,
                        double *evecs_dev, int64_t ldv, mlg_eig_info *info);
+
+// ---- autotune.hip -------------------------------------------------------------
+// out[r + v nrow] = sum_{j != rows[r]} exp(-||x_i - x_j||^2 / sigma^2) X[j + v ldx]
+// in FP64 (one workgroup per row, fixed-order tree), d <= 3, device pointers.
+void launch_ref_rows(int64_t n, int d, const double *pts, double sigma, const int64_t *rows,
+                     int nrow, int b, const double *X, int64_t ldx, double *out, hipStream_t s);
 
 // ---- pksm.hip -------------------------------------------------------------------
 constexpr int kPksmMaxSteps = 128;      // Krylov dimension limit of the matrix power

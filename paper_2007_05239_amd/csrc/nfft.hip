@@ -1915,7 +1915,7 @@ static KRParams make_kr(double sigma_s, double eps_B, int p) {
 // Smallest power-of-two bandwidth (16..256) whose dropped Gaussian Fourier
 // tail, about 2 d sqrt(pi) sigma exp(-pi^2 sigma^2 N^2 / 4), is below a
 // precision-dependent bound.
-static int auto_bandwidth(double sigma_s, int d, int prec) {
+int nfft_auto_bandwidth(double sigma_s, int d, int prec) {
     const double tol = prec == 64 ? 1e-13 : 1e-8;
     int N = 16;
     while (N < 256) {
@@ -1989,7 +1989,7 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     const double rho = 0.25 - 0.5 * P.eps_B;
     P.scale = R > 0 ? rho / R : 1.0;
     P.sigma_s = P.scale * L.sigma;
-    P.N = L.kp.N > 0 ? L.kp.N : auto_bandwidth(P.sigma_s, d, L.kp.precision);
+    P.N = L.kp.N > 0 ? L.kp.N : nfft_auto_bandwidth(P.sigma_s, d, L.kp.precision);
     P.nos = 2 * P.N;
     P.nb = P.nos / P.B;
     P.nbins = 1;

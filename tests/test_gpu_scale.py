@@ -135,8 +135,9 @@ def test_image_weight_and_degree_rows(mlg, image, image_graph):
         Y = g.laplacian_matvec(t, mlg.MLG_OP_W, X)
         ref = oracle.kernel_rows(c["layers"][t], c["sigma"][t], X, rows)
         assert rows_rel_err(np.asarray(Y)[rows], ref) <= 1e-4
+        # degrees gated row by row (D^-1/2 amplifies the error of small degrees)
         dref = oracle.kernel_rows(c["layers"][t], c["sigma"][t], np.ones(n), rows)
-        assert np.abs(g.degrees(t)[rows] - dref).max() <= 1e-6 * np.abs(dref).max()
+        assert (np.abs(g.degrees(t)[rows] - dref) / dref).max() <= 1e-6
 
 
 def test_image_L1_repeat_bit_identical(mlg, image, image_graph):
