@@ -38,6 +38,7 @@
 #ifndef MLG_H
 #define MLG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -361,6 +362,42 @@ typedef struct {
 mlg_status mlg_autotune_layer(int64_t n, int d, const double *points, double sigma,
                               int precision, int b, double tol, int nrows, uint64_t seed,
                               int flags, void *stream, mlg_kparams *kp, mlg_tune_info *info);
+
+/* ---- allocation-free product ------------------------------------------- */
+
+/* Bytes of device scratch the library holds per device (from the first
+ * mlg_kernel_matvec_noalloc call on it until the process ends). */
+#define MLG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops with a fixed memory budget, harnesses that forbid
+ * hipMalloc.  Y = W X as mlg_kernel_matvec computes it with
+ * MLG_METHOD_DIRECT (same kernels, same column split, same bits), without
+ * any device allocation, host synchronisation or library call that
+ * allocates.
+ *   points   n x d row-major FP64, device pointer, d in 1..16, n >= 2.
+ *   kp       method must be MLG_METHOD_DIRECT (else MLG_ERR_NOT_IMPL);
+ *            precision 32 or 64; kernel MLG_KERNEL_GAUSSIAN or
+ *            MLG_KERNEL_LAPLACIAN; other fields ignored.
+ *   X, Y     n x b column-major FP64 device blocks (ldx, ldy >= n), b in
+ *            1..64, not overlapping.
+ *   stream   hipStream_t of the current device (NULL = its null stream).
+ * Every intermediate (coordinates, summation slices, column partials) lives
+ * in one library-owned array of MLG_NOALLOC_SCRATCH_BYTES per device, so the
+ * size is limited: with bs = the next power of two >= b, e = 8 (precision
+ * 64) or 4 (32), and S column splits (S = 1 for n >= 131072, about
+ * 1024 / (n / 128) below), it needs about n (12 d + (2 + S) bs e) bytes;
+ * larger requests return MLG_ERR_RANGE and enqueue nothing.
+ * The call only enqueues work on `stream` and returns: Y is ready once the
+ * stream has reached that point.  Non-finite coordinates are not rejected
+ * (they make the outputs NaN).  All calls on one device share the array, so
+ * calls that can overlap on one device (other streams, other threads) race;
+ * calls on one stream are ordered and safe.
+ */
+mlg_status mlg_kernel_matvec_noalloc(int64_t n, int d, const double *points, double sigma,
+                                     const mlg_kparams *kp, int b, const double *X, int64_t ldx,
+                                     double *Y, int64_t ldy, void *stream);
 
 /* ---- measurement helpers ------------------------------------------------ */
 

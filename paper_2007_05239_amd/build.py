@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmlg.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["graph.hip", "layer_ops.hip", "direct.hip", "nfft.hip", "lanczos.hip", "pksm.hip",
-           "ac.hip", "features.hip", "autotune.hip"]
+           "ac.hip", "features.hip", "autotune.hip", "noalloc.hip"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]

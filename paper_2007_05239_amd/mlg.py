@@ -40,7 +40,10 @@ EXPORTED = ["mlg_last_error", "mlg_version", "mlg_graph_create", "mlg_graph_crea
             "mlg_median_pairwise_distance", "mlg_graph_destroy",
             "mlg_graph_degrees", "mlg_kernel_matvec", "mlg_laplacian_matvec",
             "mlg_lanczos_eigs", "mlg_power_mean_matvec", "mlg_allen_cahn_ssl",
-            "mlg_profile_stages", "mlg_graph_layer_info", "mlg_autotune_layer"]
+            "mlg_profile_stages", "mlg_graph_layer_info", "mlg_autotune_layer",
+            "mlg_kernel_matvec_noalloc"]
+
+MLG_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class MlgError(RuntimeError):
@@ -99,6 +102,8 @@ def _load():
         "mlg_graph_degrees": ([P, I, P, I], I),
         "mlg_kernel_matvec": ([i64, I, P, ctypes.c_double, ctypes.POINTER(KParams), I, P, i64, P,
                                i64, I, P], I),
+        "mlg_kernel_matvec_noalloc": ([i64, I, P, ctypes.c_double, ctypes.POINTER(KParams), I, P,
+                                       i64, P, i64, P], I),
         "mlg_laplacian_matvec": ([P, I, I, I, P, i64, P, i64, I], I),
         "mlg_lanczos_eigs": ([P, I, ctypes.c_double, I, I, ctypes.c_double, I, ctypes.c_uint64, P,
                               P, P, i64, ctypes.POINTER(EigInfo), ctypes.POINTER(PksmParams), I],
@@ -444,6 +449,23 @@ def kernel_matvec(points, sigma, X, params=None):
     _check(_lib.mlg_kernel_matvec(n, pts.shape[1], _ptr(pts)[0], float(sigma),
                                   ctypes.byref(params), b, _ptr(Xc)[0], n, _ptr(Y)[0], n, 0, None))
     return Y
+
+
+def kernel_matvec_noalloc(points, sigma, X, Y, params, stream=None):
+    """Enqueue Y = W X (direct summation, zero diagonal) without any device
+    allocation (mlg_kernel_matvec_noalloc).  points: n x d torch CUDA tensor
+    (row-major, contiguous); X, Y: n x b column-major device blocks given as
+    b x n contiguous torch tensors (Y is written).  Returns without waiting:
+    Y is ready once `stream` (default: the current torch stream) reaches the
+    call."""
+    import torch
+    assert points.is_cuda and points.is_contiguous() and X.is_contiguous() and Y.is_contiguous()
+    b, n = X.shape
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.mlg_kernel_matvec_noalloc(n, points.shape[1], _ptr(points)[0], float(sigma),
+                                          ctypes.byref(params), b, _ptr(X)[0], n, _ptr(Y)[0], n,
+                                          ctypes.c_void_p(stream)))
 
 
 def allen_cahn_ssl(evals, evecs, labels, m, eps=5e-3, omega0=1000.0, c=None, dt=0.01, tol=1e-6,
