@@ -33,6 +33,14 @@ struct NfftPlan {
     int nred1 = 0, nred2 = 0;
     DevBuf<int4> red1;      // level-1 groups (first slot, count <= 32, destination slot, 0)
     DevBuf<int4> red2;      // level-2, runs of > 1 group (run, first scratch slot, groups, 0)
+    // Spreading schedule of the d = 3 matrix-core kernel: runs cut into tasks
+    // of at most seg_chunks 64-point chunks (chosen per plan so the tasks
+    // fill the device's slots evenly), larger tasks first.  Runs cut into
+    // several tasks accumulate in scratch slots after the task list's
+    // nscratch, summed by sred1/sred2 like red1/red2.
+    int nseg = 0, seg_chunks = 0, nsscr = 0, nsred1 = 0, nsred2 = 0;
+    DevBuf<int4> seg;       // (bin key, first point, count, destination patch slot)
+    DevBuf<int4> sred1, sred2;
     int SB = 8, nsb = 0;    // superbin edge (bins) and superbins per dimension
     DevBuf<unsigned char> occ;  // per superbin: 1 if occupied
     DevBuf<double> bhat;    // kernel Fourier coefficients b^_l, l in [0,N)^d (index l mod N)

@@ -36,6 +36,9 @@
 #include <cstring>
 #include <type_traits>
 
+#include <numeric>
+#include <queue>
+
 #include "internal.h"
 
 #include <rocprim/rocprim.hpp>
@@ -1071,23 +1074,20 @@ struct SpreadTiles3 {
     static constexpr int TR = (RR * P + 15) / 16;
 };
 
-// Two wavefronts per SIMD keep one wave's matrix work running while the
-// other stages its records; the register budget is capped to allow that.
+// One task (points of one bin) of the d = 3 matrix-core spreading, written to
+// its patch slot tk.w.  LDS: wxy (64 RS), wzs (64 x 8), zv (64 x 16).
 template <int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_spread_mfma3(Geom g, const int4 *__restrict__ tasks,
-                                                     const int *__restrict__ c32,
-                                                     const float *__restrict__ f32,
-                                                     const float *__restrict__ Zs, float beta,
-                                                     float *__restrict__ patch) {
+__device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
+                                             const int *__restrict__ c32,
+                                             const float *__restrict__ f32,
+                                             const float *__restrict__ Zs, float beta,
+                                             float *__restrict__ patch, float *wxy, float *wzs,
+                                             float *zv) {
     using S = MfShape3<P>;
     using U = SpreadTiles3<P>;
     constexpr int RS = S::RS, C2 = S::C2, TF = U::TF, RR = U::RR, TR = U::TR;
-    __shared__ __attribute__((aligned(16))) float wxy[64 * RS];
-    __shared__ __attribute__((aligned(16))) float wzs[64 * 8];
-    __shared__ __attribute__((aligned(16))) float zv[64 * 16];
     const int bs = g.bs;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
-    const int4 tk = tasks[blockIdx.x];
     const int v0 = blockIdx.y * 16;
     int org[3];
     task_origin<3>(g, (unsigned)tk.x, org);
@@ -1224,6 +1224,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const int cz = flat / (RR > 0 ? RR : 1);
             if (cz < P) out[(int64_t)(16 * TF + flat % (RR > 0 ? RR : 1) + C2 * cz) * bs] = accr[u][m];
         }
+}
+
+// Two wavefronts per SIMD keep one wave's matrix work running while the
+// other stages its records; the register budget is capped to allow that.
+// Workgroup w runs task w (of the plan's task list or of its spreading
+// schedule).
+template <int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_spread_mfma3(Geom g, const int4 *__restrict__ tasks,
+                                                     const int *__restrict__ c32,
+                                                     const float *__restrict__ f32,
+                                                     const float *__restrict__ Zs, float beta,
+                                                     float *__restrict__ patch) {
+    using S = MfShape3<P>;
+    __shared__ __attribute__((aligned(16))) float wxy[64 * S::RS];
+    __shared__ __attribute__((aligned(16))) float wzs[64 * 8];
+    __shared__ __attribute__((aligned(16))) float zv[64 * 16];
+    spread3_task<P>(g, tasks[blockIdx.x], c32, f32, Zs, beta, patch, wxy, wzs, zv);
 }
 
 template <int P>
@@ -1926,6 +1943,108 @@ int nfft_auto_bandwidth(double sigma_s, int d, int prec) {
     return N;
 }
 
+// Two-level fixed-order reduction lists for runs whose patch is the sum of
+// several scratch slots: multi = (run, first scratch slot, slot count).
+// Level 1 sums groups of <= 32 slots (straight into the run's slot when one
+// group covers it); level 2 sums a run's group results.
+static void reduction_lists(const std::vector<int4> &multi, std::vector<int4> &g1,
+                            std::vector<int4> &g2) {
+    for (const int4 &m : multi) {
+        const int ng = (m.z + 31) / 32;
+        for (int q = 0; q < ng; ++q)
+            g1.push_back(make_int4(m.y + 32 * q, std::min(32, m.z - 32 * q),
+                                   ng == 1 ? m.x : m.y + 32 * q, 0));
+        if (ng > 1) g2.push_back(make_int4(m.x, m.y, ng, 0));
+    }
+}
+
+// Workgroup slots of the matrix-core spreading: two wavefronts per SIMD of
+// the device.
+static int spread_slots() {
+    int dev = 0, cus = 0;
+    MLG_HIP(hipGetDevice(&dev));
+    MLG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return std::max(1, cus) * 4 * 2;
+}
+
+// Makespan of tasks dispatched in list order onto `slots` equal slots, each
+// task costing its 64-point chunks plus a fixed overhead (patch write and
+// set-up, about half a chunk).
+static double list_makespan(const std::vector<int> &chunks, int slots) {
+    std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+    for (int i = 0; i < slots; ++i) q.push(0.0);
+    double end = 0.0;
+    for (int c : chunks) {
+        const double t = q.top() + c + 0.5;
+        q.pop();
+        q.push(t);
+        end = std::max(end, t);
+    }
+    return end;
+}
+
+// Spreading schedule of a plan (see NfftPlan::seg): each run cut into tasks
+// of at most c chunks of 64 points, c chosen so that the tasks, dispatched in
+// order of decreasing size onto the device's slots, finish earliest (equal
+// tasks whose count is just above a multiple of the slots leave the last
+// round nearly empty).  Scratch slots of a run cut into several tasks start
+// at runs + nscratch (after the task list's own) and follow the run's task
+// order, so the reduction sums in a fixed order.
+static void build_spread_schedule(NfftPlan &P, const std::vector<unsigned> &key,
+                                  const std::vector<unsigned> &start,
+                                  const std::vector<unsigned> &count, hipStream_t s) {
+    const int runs = (int)key.size();
+    const int slots = spread_slots();
+    std::vector<int> nch(runs);
+    for (int r = 0; r < runs; ++r) nch[r] = (int)((count[r] + 63) / 64);
+    int best_c = 4;
+    double best = INFINITY;
+    for (int c = 2; c <= 16; ++c) {
+        std::vector<int> sizes;
+        for (int r = 0; r < runs; ++r)
+            for (int k = 0; k < nch[r]; k += c) sizes.push_back(std::min(c, nch[r] - k));
+        std::stable_sort(sizes.begin(), sizes.end(), std::greater<int>());
+        const double t = list_makespan(sizes, slots);
+        if (t < best * 0.999) {
+            best = t;
+            best_c = c;
+        }
+    }
+    std::vector<int4> seg, multi;
+    std::vector<int> size;
+    int scr = 0;
+    for (int r = 0; r < runs; ++r) {
+        const int nt = (nch[r] + best_c - 1) / best_c;
+        const int base = runs + P.nscratch + scr;
+        for (int k = 0; k < nt; ++k) {
+            const int64_t p0 = (int64_t)k * best_c * 64;
+            const int64_t cnt = std::min<int64_t>((int64_t)count[r] - p0, (int64_t)best_c * 64);
+            seg.push_back(make_int4((int)key[r], (int)(start[r] + p0), (int)cnt, nt == 1 ? r : base + k));
+            size.push_back((int)((cnt + 63) / 64));
+        }
+        if (nt > 1) {
+            multi.push_back(make_int4(r, base, nt, 0));
+            scr += nt;
+        }
+    }
+    // dispatch order: larger tasks first (stable: ties keep run order)
+    std::vector<int> ord(seg.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return size[x] > size[y]; });
+    std::vector<int4> sorted(seg.size());
+    for (size_t i = 0; i < ord.size(); ++i) sorted[i] = seg[ord[i]];
+    std::vector<int4> g1, g2;
+    reduction_lists(multi, g1, g2);
+    P.nseg = (int)sorted.size();
+    P.seg_chunks = best_c;
+    P.nsscr = scr;
+    P.nsred1 = (int)g1.size();
+    P.nsred2 = (int)g2.size();
+    upload(P.seg, sorted.data(), sorted.size(), false, s);
+    upload(P.sred1, g1.data(), g1.size(), false, s);
+    upload(P.sred2, g2.data(), g2.size(), false, s);
+}
+
 template <class F>
 static void with_temp(DevBuf<char> &tmp, size_t bytes, F f) {
     tmp.ensure(bytes ? bytes : 1);
@@ -2077,17 +2196,21 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
         MLG_HIP(hipStreamSynchronize(s));
         std::vector<int4> g1;
         std::vector<int4> g2;
-        for (const int4 &m : hm) {
-            const int ng = (m.z + 31) / 32;
-            for (int q = 0; q < ng; ++q)
-                g1.push_back(make_int4(m.y + 32 * q, std::min(32, m.z - 32 * q),
-                                       ng == 1 ? m.x : m.y + 32 * q, 0));
-            if (ng > 1) g2.push_back(make_int4(m.x, m.y, ng, 0));
-        }
+        reduction_lists(hm, g1, g2);
         P.nred1 = (int)g1.size();
         P.nred2 = (int)g2.size();
         upload(P.red1, g1.data(), g1.size(), false, s);
         upload(P.red2, g2.data(), g2.size(), false, s);
+    }
+    // balanced spreading schedule for d = 3 plans whose runs hold a full
+    // chunk of points on average (the matrix-core spreading's work unit)
+    if (d == 3 && runs > 0 && (int64_t)n >= 64 * (int64_t)runs) {
+        std::vector<unsigned> hkey(runs), hst(runs), hcnt(runs);
+        MLG_HIP(hipMemcpyAsync(hkey.data(), ukeys.p, 4 * (size_t)runs, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipMemcpyAsync(hst.data(), run_start.p, 4 * (size_t)runs, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipMemcpyAsync(hcnt.data(), counts.p, 4 * (size_t)runs, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        build_spread_schedule(P, hkey, hst, hcnt, s);
     }
     P.SB = std::min(8, P.nb);
     P.nsb = (P.nb + P.SB - 1) / P.SB;
@@ -2211,8 +2334,16 @@ static int patch_cells(const NfftPlan &P, const NfftWindow &W) {
     return pd;
 }
 
+// The d = 3 matrix-core spreading (FP32, blocks of 16 vectors, patches of
+// at most 6^3 cells) runs the balanced schedule when the plan has one.
+static bool uses_spread_schedule(const NfftPlan &P, const NfftWindow &W, int bs) {
+    return P.nseg > 0 && P.d == 3 && W.prec == 32 && bs % 16 == 0 &&
+           mfma_patch_ok(3, patch_side(P, W));
+}
+
 size_t nfft_patch_elems(const NfftPlan &P, const NfftWindow &W, int bs) {
-    return (size_t)patch_cells(P, W) * bs * (size_t)(P.nruns + P.nscratch);
+    const size_t slots = (size_t)P.nruns + P.nscratch + (uses_spread_schedule(P, W, bs) ? P.nsscr : 0);
+    return (size_t)patch_cells(P, W) * bs * slots;
 }
 
 size_t nfft_grid_elems(const NfftPlan &P, int bs) {
@@ -2444,13 +2575,14 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     // FP32 blocks of 16 vectors with patches of <= 256 cells use the matrix
     // cores; everything else the vector-ALU kernels.
     const bool mf = std::is_same<T, float>::value && bs % 16 == 0 && mfma_patch_ok(D, g.P);
+    const bool sched = mf && uses_spread_schedule(P, W, bs);
     if (P.ntasks > 0) {
         if constexpr (std::is_same<T, float>::value) {
             if (mf) {
 #define SPREADM_CALL(DD, PP)                                                                      \
     if constexpr (DD == 3)                                                                        \
-        hipLaunchKernelGGL((k_spread_mfma3<PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
-                           P.c32.p, P.f32.p, Zs, beta, patch);                                   \
+        hipLaunchKernelGGL((k_spread_mfma3<PP>), dim3(sched ? P.nseg : P.ntasks, bs / 16), dim3(64), 0, s, \
+                           g, sched ? P.seg.p : P.tasks.p, P.c32.p, P.f32.p, Zs, beta, patch);   \
     else                                                                                          \
         hipLaunchKernelGGL((k_spread_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
                            P.c32.p, P.f32.p, Zs, beta, patch)
@@ -2467,14 +2599,16 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     }
     if (ev) MLG_HIP(hipEventRecord(ev[1], s));   // spreading kernel alone
     if (P.ntasks > 0) {
-        if (P.nred1 > 0) {
+        const int nr1 = sched ? P.nsred1 : P.nred1, nr2 = sched ? P.nsred2 : P.nred2;
+        const int4 *r1 = sched ? P.sred1.p : P.red1.p, *r2 = sched ? P.sred2.p : P.red2.p;
+        if (nr1 > 0) {
             const int64_t elems = (int64_t)g.PD * bs;
-            hipLaunchKernelGGL(k_reduce1<T>, dim3(P.nred1, ceil_div(elems, 256)), dim3(256), 0, s, elems,
-                               P.red1.p, patch);
+            hipLaunchKernelGGL(k_reduce1<T>, dim3(nr1, ceil_div(elems, 256)), dim3(256), 0, s, elems,
+                               r1, patch);
             MLG_LAUNCH_CHECK();
-            if (P.nred2 > 0) {
-                hipLaunchKernelGGL(k_reduce2<T>, dim3(P.nred2, ceil_div(elems, 256)), dim3(256), 0, s,
-                                   elems, P.red2.p, patch);
+            if (nr2 > 0) {
+                hipLaunchKernelGGL(k_reduce2<T>, dim3(nr2, ceil_div(elems, 256)), dim3(256), 0, s,
+                                   elems, r2, patch);
                 MLG_LAUNCH_CHECK();
             }
         }

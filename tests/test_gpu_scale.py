@@ -271,3 +271,40 @@ def test_large_fp32_and_fp64_rows(mlg):
     ref = oracle.kernel_rows(c["layers"][0], c["sigma"][0], X[:, :1], rows)
     assert rows_rel_err(Y[rows], ref) <= 1e-6
     g.close()
+
+
+def test_large_lanczos_30_eigenpairs(mlg):
+    """30 smallest eigenpairs of L_1 at n = 10^7 (three FP32 NFFT layers,
+    FP64 degrees, block Lanczos with FP64 CGS2 full reorthogonalisation):
+    every residual ||L_1 phi - lambda phi|| within tol (it bounds the
+    eigenvalue error of the symmetric operator), orthonormal vectors,
+    eigenvalues ascending in [0, 2), and sampled rows of the operator the
+    residuals were taken with against the oracle's W rows."""
+    import torch
+    c = gen.config5()
+    n, T, k = c["n"], len(c["layers"]), c["k"]
+    layers = [device_block(L) for L in c["layers"]]
+    kp = [mlg.kparams("nfft", 32, N=c["N"], window=6) for _ in range(T)]
+    case_id("large graph with degrees n=%d T=%d" % (n, T))
+    g = mlg.Graph(layers, c["sigma"], kp)
+    tol = 1e-5
+    case_id("large lanczos L_1 n=%d k=%d block=16 tol=%g" % (n, k, tol))
+    lam, V, info = g.lanczos_eigs(-1, k, block=16, tol=tol, seed=c["base_seed"] + 200,
+                                  device=True)
+    case_id("  %s" % info)
+    assert info["converged"] and info["nconv"] == k, info
+    lam = lam.cpu().numpy()
+    assert np.all(np.diff(lam) >= 0) and lam[0] > -1e-4 and lam[-1] < 2.0
+    G = (V.t() @ V).cpu().numpy()
+    np.testing.assert_allclose(G, np.eye(k), atol=1e-10)
+    LV = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, V)
+    res = torch.linalg.norm(LV - V * torch.from_numpy(lam).to(V.device)[None, :], dim=0)
+    assert float(res.max()) <= tol * (1 + 1e-3), res
+    # the W rows behind that operator, against the oracle (sampled rows)
+    rows = sample_rows(n, 16, c["base_seed"] + 402)
+    Vh = V[:, :4].cpu().numpy()
+    for t in range(T):
+        Y = g.laplacian_matvec(t, mlg.MLG_OP_W, V[:, :4].contiguous()).cpu().numpy()
+        ref = oracle.kernel_rows(c["layers"][t], c["sigma"][t], Vh, rows)
+        assert rows_rel_err(Y[rows], ref) <= 1e-4
+    g.close()
