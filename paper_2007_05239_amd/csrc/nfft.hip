@@ -1193,16 +1193,24 @@ __device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
             if (gi + 1 < 16) read_ops(gi + 1, nxt);
             // keep the reads above the matrix instructions that hide them
             __builtin_amdgcn_sched_barrier(0);
+            // every B operand of the group in its own register before the
+            // first matrix instruction: the products do not rewrite a
+            // register that an issued matrix instruction still reads
+            float bb[P], rb[TR > 0 ? TR : 1];
+#pragma unroll
+            for (int cz = 0; cz < P; ++cz) bb[cz] = cur.z * cur.wz[cz];
+#pragma unroll
+            for (int u = 0; u < TR; ++u) rb[u] = cur.rx[u] * cur.rz[u];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int cz = 0; cz < P; ++cz) {
-                const float b = cur.z * cur.wz[cz];
 #pragma unroll
                 for (int t = 0; t < TF; ++t)
-                    acc[t][cz] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.a[t], b, acc[t][cz], 0, 0, 0);
+                    acc[t][cz] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.a[t], bb[cz], acc[t][cz], 0, 0, 0);
             }
 #pragma unroll
             for (int u = 0; u < TR; ++u)
-                accr[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.rx[u] * cur.rz[u], cur.z, accr[u], 0, 0, 0);
+                accr[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(rb[u], cur.z, accr[u], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
