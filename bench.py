@@ -28,6 +28,8 @@ Printed as ONE JSON line with:
   allen_cahn     Allen-Cahn steps at n = 10^7 (k = 30, m = 10);
   large_eigs     the 30 smallest eigenpairs of L_1 at n = 10^7 (three layers,
                  block Lanczos with FP64 CGS2);
+  direct         the direct tiled summation (exp tiles on the vector ALUs,
+                 contraction on the matrix cores), FP32 and FP64, n = 10^5;
   accuracy       the timed product's output against the stored oracle rows of
                  L_1 X (4096 rows), W_t rows and degrees against the oracle;
   cpu_baseline   the oracle timed on the host cores on a bounded sample.
@@ -51,6 +53,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Laplacian matvecs/sec (n*layers/s) at 1e-4 rel err vs FP64; FP32-batched vs FP64 plain"
 UNIT = "node-layer-vector rows/s"
 FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -72,6 +75,9 @@ def parse():
     ap.add_argument("--power-only", action="store_true",
                     help="run only the power-mean leg and print its JSON object (for profiling)")
     ap.add_argument("--no-ac", action="store_true", help="skip the Allen-Cahn leg")
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct-summation leg")
+    ap.add_argument("--direct-only", action="store_true",
+                    help="run only the direct-summation leg and print its JSON object")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the n = 10^7 eigenpair leg (30 pairs, block Lanczos)")
     ap.add_argument("--large-only", action="store_true",
@@ -329,6 +335,33 @@ def large_eigs_leg():
             "lambda_first_last": [float(lam[0]), float(lam[-1])]}
 
 
+def direct_leg(n=100_000, b=16):
+    """Direct tiled summation W X (zero diagonal) on the 10^5-point ball
+    (sigma 0.05), FP32 and FP64, b = 16: the kernel time from HIP events
+    around the direct stage only.  Per pair: the exp weight on the vector
+    ALUs (d differences and multiply-adds, one exp) and 2 b flop of the
+    weight-tile x vector-block product on the matrix cores."""
+    import torch
+    import paper_2007_05239_amd.mlg as mlg
+    from workloads import gen
+    c = gen.config2(n)
+    pts = torch.from_numpy(c["layers"][0]).to("cuda")
+    X = torch.from_numpy(np.ascontiguousarray(gen.test_vectors(n, b, c["base_seed"] + 300))).to("cuda")
+    out = {"workload": "ball3d_n%d_W_block%d" % (n, b), "n": n, "b": b, "pairs": n * (n - 1)}
+    for prec, peak in ((32, FP32_PEAK_TFLOPS), (64, FP64_PEAK_TFLOPS)):
+        g = mlg.Graph([pts], c["sigma"], mlg.kparams("direct", precision=prec), degrees=False)
+        g.profile_stages(0, mlg.MLG_OP_W, X, reps=1)
+        st = g.profile_stages(0, mlg.MLG_OP_W, X, reps=5)
+        g.close()
+        t = st["direct"] * 1e-3
+        mf = 2.0 * n * n * b / t / 1e12
+        out["fp%d" % prec] = {"ms": round(st["direct"], 4), "pairs_per_s": n * (n - 1) / t,
+                              "mfma_TFLOPs": round(mf, 2), "mfma_frac": round(mf / peak, 4),
+                              "exp_per_s": n * (n - 1) / t,
+                              "rows_per_s": n * b / t}
+    return out
+
+
 TUNE_TOL = 5e-5       # sampled-row budget of the autotuner: a 2x margin under the 1e-4 gate
 TUNE_ROWS = 256
 
@@ -359,6 +392,9 @@ def main():
         return
     if a.ac_only:
         print(json.dumps({"allen_cahn": allen_cahn_leg()}))
+        return
+    if a.direct_only:
+        print(json.dumps({"direct": direct_leg()}))
         return
     if a.large_only:
         print(json.dumps({"large_eigs": large_eigs_leg()}))
@@ -487,6 +523,7 @@ def main():
     power = None if a.no_power else power_leg(g, X, c, n, T, b)
     ac = None if a.no_ac else allen_cahn_leg()
     large = None if a.no_large else large_eigs_leg()
+    direct = None if a.no_direct else direct_leg()
 
     # accuracy of the timed product itself: its last output against the
     # stored oracle rows of L_1 X (4096 rows, every layer's degrees from the
@@ -539,7 +576,7 @@ def main():
                       "parallelism": "single GPU"},
            "stages_ms": {k: round(v, 4) for k, v in st.items()},
            "roofline": roof, "step_roofline": step_roof, "fp64_plain": fp64, "power_mean": power,
-           "allen_cahn": ac, "large_eigs": large,
+           "allen_cahn": ac, "large_eigs": large, "direct": direct,
            "accuracy": acc, "cpu_baseline": cpu}
     g.close()
     print(json.dumps(out))

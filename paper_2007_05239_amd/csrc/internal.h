@@ -41,6 +41,11 @@ struct NfftPlan {
     int nseg = 0, seg_chunks = 0, nsscr = 0, nsred1 = 0, nsred2 = 0;
     DevBuf<int4> seg;       // (bin key, first point, count, destination patch slot)
     DevBuf<int4> sred1, sred2;
+    // Interpolation schedule of the same kernel family: runs cut into tasks
+    // of at most iseg_chunks chunks for three wavefronts per SIMD, larger
+    // first; one workgroup per task.
+    int niseg = 0, iseg_chunks = 0;
+    DevBuf<int4> iseg;
     int SB = 8, nsb = 0;    // superbin edge (bins) and superbins per dimension
     DevBuf<unsigned char> occ;  // per superbin: 1 if occupied
     DevBuf<double> bhat;    // kernel Fourier coefficients b^_l, l in [0,N)^d (index l mod N)

@@ -1256,7 +1256,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                      const int *__restrict__ c32,
                                                      const float *__restrict__ f32,
                                                      const float *__restrict__ grid, int bg,
-                                                     float beta, float *__restrict__ Fs, int split) {
+                                                     float beta, float *__restrict__ Fs, int split,
+                                                     int per) {
     using S = MfShape3<P>;
     constexpr int KS2 = S::KS2, ES = S::ES, NE = S::NE, C2 = S::C2;
     // entry-major weights: entry e of point p at wt[e * ES + p]; entries
@@ -1271,7 +1272,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     // barrier)
     int4 tk = tasks[blockIdx.x / split];
     {
-        const int per = kMaxTaskPoints / split;
         const int lo = (blockIdx.x % split) * per;
         if (lo >= tk.z) return;
         tk.y += lo;
@@ -1966,91 +1966,105 @@ static void reduction_lists(const std::vector<int4> &multi, std::vector<int4> &g
     }
 }
 
-// Workgroup slots of the matrix-core spreading: two wavefronts per SIMD of
-// the device.
-static int spread_slots() {
-    int dev = 0, cus = 0;
-    MLG_HIP(hipGetDevice(&dev));
-    MLG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    return std::max(1, cus) * 4 * 2;
-}
-
-// Makespan of tasks dispatched in list order onto `slots` equal slots, each
-// task costing its 64-point chunks plus a fixed overhead (patch write and
-// set-up, about half a chunk).
-static double list_makespan(const std::vector<int> &chunks, int slots) {
-    std::priority_queue<double, std::vector<double>, std::greater<double>> q;
-    for (int i = 0; i < slots; ++i) q.push(0.0);
-    double end = 0.0;
-    for (int c : chunks) {
-        const double t = q.top() + c + 0.5;
-        q.pop();
-        q.push(t);
-        end = std::max(end, t);
-    }
-    return end;
-}
-
-// Spreading schedule of a plan (see NfftPlan::seg): each run cut into tasks
-// of at most c chunks of 64 points, c chosen so that the tasks, dispatched in
-// order of decreasing size onto the device's slots, finish earliest (equal
-// tasks whose count is just above a multiple of the slots leave the last
-// round nearly empty).  Scratch slots of a run cut into several tasks start
-// at runs + nscratch (after the task list's own) and follow the run's task
-// order, so the reduction sums in a fixed order.
-static void build_spread_schedule(NfftPlan &P, const std::vector<unsigned> &key,
-                                  const std::vector<unsigned> &start,
-                                  const std::vector<unsigned> &count, hipStream_t s) {
-    const int runs = (int)key.size();
-    const int slots = spread_slots();
-    std::vector<int> nch(runs);
-    for (int r = 0; r < runs; ++r) nch[r] = (int)((count[r] + 63) / 64);
+// Chunks per task (2..16) for which the runs' tasks, dispatched in order of
+// decreasing size onto `slots` equal slots, finish earliest; `over` is a
+// task's fixed cost in chunks (set-up, patch load or store).
+static int best_task_chunks(const std::vector<int> &nch, int slots, double over) {
     int best_c = 4;
     double best = INFINITY;
     for (int c = 2; c <= 16; ++c) {
         std::vector<int> sizes;
-        for (int r = 0; r < runs; ++r)
-            for (int k = 0; k < nch[r]; k += c) sizes.push_back(std::min(c, nch[r] - k));
+        for (int k : nch)
+            for (int j = 0; j < k; j += c) sizes.push_back(std::min(c, k - j));
         std::stable_sort(sizes.begin(), sizes.end(), std::greater<int>());
-        const double t = list_makespan(sizes, slots);
-        if (t < best * 0.999) {
-            best = t;
+        std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+        for (int i = 0; i < slots; ++i) q.push(0.0);
+        double end = 0.0;
+        for (int z : sizes) {
+            const double t = q.top() + z + over;
+            q.pop();
+            q.push(t);
+            end = std::max(end, t);
+        }
+        if (end < best * 0.999) {
+            best = end;
             best_c = c;
         }
     }
-    std::vector<int4> seg, multi;
+    return best_c;
+}
+
+// The runs cut into tasks of at most c chunks of 64 points, larger tasks
+// first (stable: ties keep run order).  With `slots_base` >= 0, a run cut
+// into several tasks gets consecutive scratch patch slots from slots_base on
+// (in task order) and a multi entry (run, first slot, tasks); a run of one
+// task writes its own slot.
+static std::vector<int4> cut_runs(const std::vector<unsigned> &key,
+                                  const std::vector<unsigned> &start,
+                                  const std::vector<unsigned> &count, int c, int slots_base,
+                                  std::vector<int4> &multi, int &scr) {
+    const int runs = (int)key.size();
+    std::vector<int4> seg;
     std::vector<int> size;
-    int scr = 0;
+    scr = 0;
     for (int r = 0; r < runs; ++r) {
-        const int nt = (nch[r] + best_c - 1) / best_c;
-        const int base = runs + P.nscratch + scr;
+        const int nch = (int)((count[r] + 63) / 64);
+        const int nt = (nch + c - 1) / c;
+        const int base = slots_base + scr;
         for (int k = 0; k < nt; ++k) {
-            const int64_t p0 = (int64_t)k * best_c * 64;
-            const int64_t cnt = std::min<int64_t>((int64_t)count[r] - p0, (int64_t)best_c * 64);
-            seg.push_back(make_int4((int)key[r], (int)(start[r] + p0), (int)cnt, nt == 1 ? r : base + k));
+            const int64_t p0 = (int64_t)k * c * 64;
+            const int64_t cnt = std::min<int64_t>((int64_t)count[r] - p0, (int64_t)c * 64);
+            seg.push_back(make_int4((int)key[r], (int)(start[r] + p0), (int)cnt,
+                                    nt == 1 ? r : base + k));
             size.push_back((int)((cnt + 63) / 64));
         }
-        if (nt > 1) {
+        if (nt > 1 && slots_base >= 0) {
             multi.push_back(make_int4(r, base, nt, 0));
             scr += nt;
         }
     }
-    // dispatch order: larger tasks first (stable: ties keep run order)
     std::vector<int> ord(seg.size());
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return size[x] > size[y]; });
     std::vector<int4> sorted(seg.size());
     for (size_t i = 0; i < ord.size(); ++i) sorted[i] = seg[ord[i]];
+    return sorted;
+}
+
+// Matrix-core schedules of a d = 3 plan (see NfftPlan::seg and ::iseg):
+// spreading on two wavefronts per SIMD (task overhead: its patch store,
+// about half a chunk), interpolation on three (overhead: its patch load,
+// about one chunk).  Scratch slots of the spreading start at
+// runs + nscratch, after the task list's own.
+static void build_mfma_schedules(NfftPlan &P, const std::vector<unsigned> &key,
+                                 const std::vector<unsigned> &start,
+                                 const std::vector<unsigned> &count, hipStream_t s) {
+    const int runs = (int)key.size();
+    int dev = 0, cus = 0;
+    MLG_HIP(hipGetDevice(&dev));
+    MLG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int simds = std::max(1, cus) * 4;
+    std::vector<int> nch(runs);
+    for (int r = 0; r < runs; ++r) nch[r] = (int)((count[r] + 63) / 64);
+    std::vector<int4> multi, unused;
+    int scr = 0, iscr = 0;
+    const int cs = best_task_chunks(nch, 2 * simds, 0.5);
+    std::vector<int4> seg = cut_runs(key, start, count, cs, runs + P.nscratch, multi, scr);
+    const int ci = best_task_chunks(nch, 3 * simds, 1.0);
+    std::vector<int4> iseg = cut_runs(key, start, count, ci, -1, unused, iscr);
     std::vector<int4> g1, g2;
     reduction_lists(multi, g1, g2);
-    P.nseg = (int)sorted.size();
-    P.seg_chunks = best_c;
+    P.nseg = (int)seg.size();
+    P.seg_chunks = cs;
     P.nsscr = scr;
     P.nsred1 = (int)g1.size();
     P.nsred2 = (int)g2.size();
-    upload(P.seg, sorted.data(), sorted.size(), false, s);
+    upload(P.seg, seg.data(), seg.size(), false, s);
     upload(P.sred1, g1.data(), g1.size(), false, s);
     upload(P.sred2, g2.data(), g2.size(), false, s);
+    P.niseg = (int)iseg.size();
+    P.iseg_chunks = ci;
+    upload(P.iseg, iseg.data(), iseg.size(), false, s);
 }
 
 template <class F>
@@ -2218,7 +2232,7 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
         MLG_HIP(hipMemcpyAsync(hst.data(), run_start.p, 4 * (size_t)runs, hipMemcpyDeviceToHost, s));
         MLG_HIP(hipMemcpyAsync(hcnt.data(), counts.p, 4 * (size_t)runs, hipMemcpyDeviceToHost, s));
         MLG_HIP(hipStreamSynchronize(s));
-        build_spread_schedule(P, hkey, hst, hcnt, s);
+        build_mfma_schedules(P, hkey, hst, hcnt, s);
     }
     P.SB = std::min(8, P.nb);
     P.nsb = (P.nb + P.SB - 1) / P.SB;
@@ -2651,11 +2665,18 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
             // twice as many shorter wavefronts fill the chip better (image
             // graph, b = 16: 65.8 -> 69 TFLOP/s; four parts: 57).  The
             // d <= 2 kernel measured no gain from it.
-            const int isplit = 2;
+            // With the plan's interpolation schedule (tasks of a few chunks
+            // sized for three wavefronts per SIMD) one workgroup runs a whole
+            // task and loads its grid patch once.
+            const bool isch = P.niseg > 0 && sched;
+            const int isplit = isch ? 1 : 2;
+            const int iper = isch ? (1 << 30) : kMaxTaskPoints / isplit;
+            const int ntk = isch ? P.niseg : P.ntasks;
+            const int4 *itk = isch ? P.iseg.p : P.tasks.p;
 #define INTERPM_CALL(DD, PP)                                                                      \
     if constexpr (DD == 3)                                                                        \
-        hipLaunchKernelGGL((k_interp_mfma3<PP>), dim3(P.ntasks * isplit, bs / 16), dim3(64), 0, s, g,  \
-                           P.tasks.p, P.c32.p, P.f32.p, grid, bg, beta, Fs, isplit);             \
+        hipLaunchKernelGGL((k_interp_mfma3<PP>), dim3(ntk * isplit, bs / 16), dim3(64), 0, s, g,  \
+                           itk, P.c32.p, P.f32.p, grid, bg, beta, Fs, isplit, iper);             \
     else                                                                                          \
         hipLaunchKernelGGL((k_interp_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
                            P.c32.p, P.f32.p, grid, bg, beta, Fs)
