@@ -173,8 +173,6 @@ struct PowerMeanOp {
     double p, delta = 0.0;
     double tol = 1e-12;        // stopping threshold on the change of f(T_m) e_1 / delta^p
     int mcap = 0;              // Krylov dimension limit
-    int64_t rc = 0;            // rows per reduction block
-    int nblk = 0;
     int nrow = 0;              // blocks of the row-per-thread kernels
     // One Krylov run in flight: basis (grown on demand), work vectors,
     // coefficients, and the stream it runs on (one lane per graph branch).
@@ -199,8 +197,8 @@ struct PowerMeanOp {
     PowerMeanOp(const PowerMeanOp &) = delete;
     PowerMeanOp &operator=(const PowerMeanOp &) = delete;
     bool fuse = false;         // next vector and the layer's summation input in one pass
-    void scale_next(Lane &L, const double *X, int64_t ldx, const double *den, int dstride,
-                    double *Vnext);
+    void scale_next(Lane &L, const double *X, int64_t ldx, const double *Q, const double *alpha,
+                    const double *den, int dstride, double *Vnext);
     void prepare(Lane &L);
     void ensure_slots(Lane &L, int need);
     void start(Lane &L, int t, const double *X, int64_t ldx);
