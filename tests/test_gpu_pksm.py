@@ -161,15 +161,19 @@ def test_power_matvec_more_layers_than_lanes(mlg):
     assert power_err(Y, oracle.power_mean_power_matvec(layers, p, X), X, p) <= 1e-10
 
 
-@pytest.mark.parametrize("prec,window,gate", [(64, 12, 1e-6), (32, 6, 1e-4)])
-def test_power_matvec_nfft(mlg, prec, window, gate):
+@pytest.mark.parametrize("prec,window,gate,b", [(64, 12, 1e-6, 4), (32, 6, 1e-4, 4),
+                                                (32, 6, 1e-4, 12), (32, 6, 1e-4, 16)])
+def test_power_matvec_nfft(mlg, prec, window, gate, b):
+    """b = 12 and 16 take the fused next-vector/summation-input kernel with
+    the FP32 slice written four columns at a time (16) or padded past b
+    (12)."""
     n, p = 2500, -10.0
     pts, sig = two_layers(n, 511)
     kp = [mlg.kparams("nfft", prec, N=64, window=window)] * 2
     g = mlg.Graph(pts, sig, kp)
     layers = [oracle.Layer(q, s) for q, s in zip(pts, sig)]
-    X = gen.test_vectors(n, 4, 512)
-    case_id("power matvec nfft fp%d n=%d p=%g b=4" % (prec, n, p))
+    X = gen.test_vectors(n, b, 512)
+    case_id("power matvec nfft fp%d n=%d p=%g b=%d" % (prec, n, p, b))
     Y, info = g.power_mean_matvec(-1, p, X, tol=1e-12)
     g.close()
     assert info["converged"]

@@ -140,6 +140,29 @@ def test_image_weight_and_degree_rows(mlg, image, image_graph):
         assert (np.abs(g.degrees(t)[rows] - dref) / dref).max() <= 1e-6
 
 
+def test_image_L1_rows_against_stored_oracle(mlg, image, image_graph):
+    """4096 rows of L_1 X (b = 16, the benchmark's block) of the image graph
+    against stored oracle rows: tests/golden/image1000_L1_rows4096_b16.npz,
+    written by tests/golden/make_golden.py from the CPU oracle alone, with
+    every layer's degrees summed over all 10^6 nodes.  Also the stored
+    D^-1/2 of those rows against the graph's degrees, row by row."""
+    import os
+    c, g = image, image_graph
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "image1000_L1_rows4096_b16.npz")
+    z = np.load(path, allow_pickle=False)
+    rows, ref = z["rows"], z["L1X"]
+    n, T = c["n"], len(c["layers"])
+    assert np.allclose(z["sigma"], c["sigma"], rtol=0, atol=0)
+    X = device_block(gen.test_vectors(n, 16, c["base_seed"] + 300))
+    case_id("image L_1 x against 4096 stored oracle rows n=%d b=16" % n)
+    Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, X).cpu().numpy()
+    assert rows_rel_err(Y[rows], ref) <= 1e-4
+    for t in range(T):
+        dinv = 1.0 / np.sqrt(g.degrees(t)[rows])
+        assert (np.abs(dinv - z["dinv_sqrt_rows"][:, t]) / z["dinv_sqrt_rows"][:, t]).max() <= 1e-6
+
+
 def test_image_L1_repeat_bit_identical(mlg, image, image_graph):
     c, g = image, image_graph
     X = device_block(gen.test_vectors(c["n"], 16, c["base_seed"] + 301))

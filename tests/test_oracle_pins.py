@@ -436,3 +436,27 @@ def test_allen_cahn_is_deterministic():
     a = oracle.allen_cahn(lam, V, lab, 5, tol=0.0, max_iter=20)
     b = oracle.allen_cahn(lam, V, lab, 5, tol=0.0, max_iter=20)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_stored_image_rows_match_their_recipe():
+    """The stored oracle rows of the image graph (written by
+    tests/golden/make_golden.py from the oracle) belong to the seeded sample
+    and kernel widths the recipe gives: sorted distinct rows from the row
+    seed, 16 vectors, the three layers' sigma, finite values, and positive
+    D^-1/2."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(here, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    z = np.load(os.path.join(here, "image1000_L1_rows4096_b16.npz"), allow_pickle=False)
+    base = gen.SEED_BASE + 3
+    n = 1000 * 1000
+    assert np.array_equal(z["rows"], mg.image_sample(n, base))
+    assert z["L1X"].shape == (mg.IMAGE_ROWS, mg.IMAGE_B) and np.isfinite(z["L1X"]).all()
+    assert np.all(z["dinv_sqrt_rows"] > 0)
+    # sigma of each layer by the workload rule (1000 seeded samples)
+    img, _ = gen.synthetic_image(1000, 1000, base)
+    assert z["sigma"][0] == gen.median_pairwise_distance(np.ascontiguousarray(img.reshape(n, 3)), 1000,
+                                                         base + 10)
