@@ -28,6 +28,8 @@ Printed as ONE JSON line with:
   allen_cahn     Allen-Cahn steps at n = 10^7 (k = 30, m = 10);
   large_eigs     the 30 smallest eigenpairs of L_1 at n = 10^7 (three layers,
                  block Lanczos with FP64 CGS2);
+  cube           the L_1 block product of the 52-layer cube (512 x 512, d = 2
+                 layers, uneven N);
   direct         the direct tiled summation (exp tiles on the vector ALUs,
                  contraction on the matrix cores), FP32 and FP64, n = 10^5;
   accuracy       the timed product's output against the stored oracle rows of
@@ -76,6 +78,9 @@ def parse():
                     help="run only the power-mean leg and print its JSON object (for profiling)")
     ap.add_argument("--no-ac", action="store_true", help="skip the Allen-Cahn leg")
     ap.add_argument("--no-direct", action="store_true", help="skip the direct-summation leg")
+    ap.add_argument("--no-cube", action="store_true", help="skip the 52-layer cube leg")
+    ap.add_argument("--cube-only", action="store_true",
+                    help="run only the 52-layer cube leg and print its JSON object")
     ap.add_argument("--direct-only", action="store_true",
                     help="run only the direct-summation leg and print its JSON object")
     ap.add_argument("--no-large", action="store_true",
@@ -362,6 +367,41 @@ def direct_leg(n=100_000, b=16):
     return out
 
 
+def cube_leg(steps=20):
+    """The L_1 block product (b = 16) of the 52-layer hyperspectral-like cube
+    (512 x 512 pixels, band pairs (i, i + 52), d = 2 per layer, N_t =
+    32, 64, 128 in turn, w = 6, FP32 NFFT): rows/s and the step roofline."""
+    import torch
+    import paper_2007_05239_amd.mlg as mlg
+    from workloads import gen
+    c = gen.config4()
+    n, T, b = c["n"], len(c["layers"]), 16
+    kp = [mlg.kparams("nfft", 32, N=c["N"][t], window=6) for t in range(T)]
+    layers = [torch.from_numpy(L).to("cuda") for L in c["layers"]]
+    t0 = time.perf_counter()
+    g = mlg.Graph(layers, c["sigma"], kp)
+    torch.cuda.synchronize()
+    plan = time.perf_counter() - t0
+    infos = [g.layer_info(t) for t in range(T)]
+    X = torch.from_numpy(np.ascontiguousarray(gen.test_vectors(n, b, c["base_seed"] + 300))).to("cuda")
+    Xc = X.t().contiguous()
+    Yc = torch.empty_like(Xc)
+    for _ in range(3):
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    g.close()
+    sr = step_roofline(infos, n, b, el)
+    sr.pop("layers")
+    return {"workload": "hyperspectral512x512_52layer_L1_block16", "n": n, "layers": T, "block": b,
+            "graph_create_s": round(plan, 3), "ms_per_step": round(el * 1e3, 4),
+            "rows_per_s": n * T * b / el, "step_roofline": sr}
+
+
 TUNE_TOL = 5e-5       # sampled-row budget of the autotuner: a 2x margin under the 1e-4 gate
 TUNE_ROWS = 256
 
@@ -392,6 +432,9 @@ def main():
         return
     if a.ac_only:
         print(json.dumps({"allen_cahn": allen_cahn_leg()}))
+        return
+    if a.cube_only:
+        print(json.dumps({"cube": cube_leg()}))
         return
     if a.direct_only:
         print(json.dumps({"direct": direct_leg()}))
@@ -524,6 +567,7 @@ def main():
     ac = None if a.no_ac else allen_cahn_leg()
     large = None if a.no_large else large_eigs_leg()
     direct = None if a.no_direct else direct_leg()
+    cube = None if a.no_cube else cube_leg()
 
     # accuracy of the timed product itself: its last output against the
     # stored oracle rows of L_1 X (4096 rows, every layer's degrees from the
@@ -576,7 +620,7 @@ def main():
                       "parallelism": "single GPU"},
            "stages_ms": {k: round(v, 4) for k, v in st.items()},
            "roofline": roof, "step_roofline": step_roof, "fp64_plain": fp64, "power_mean": power,
-           "allen_cahn": ac, "large_eigs": large, "direct": direct,
+           "allen_cahn": ac, "large_eigs": large, "direct": direct, "cube": cube,
            "accuracy": acc, "cpu_baseline": cpu}
     g.close()
     print(json.dumps(out))

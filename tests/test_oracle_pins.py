@@ -460,3 +460,79 @@ def test_stored_image_rows_match_their_recipe():
     img, _ = gen.synthetic_image(1000, 1000, base)
     assert z["sigma"][0] == gen.median_pairwise_distance(np.ascontiguousarray(img.reshape(n, 3)), 1000,
                                                          base + 10)
+
+
+# ---------------------------------------------------------------------------
+# Why the Laplacian RBF kernel stays on the direct path: the truncated Fourier
+# series of Algorithm 1 (Sec. 4) converges algebraically for its cusp
+# ---------------------------------------------------------------------------
+def _truncation_error(kind, s, N, n=600, seed=5):
+    """Relative error of W x when K is replaced by its truncated Fourier
+    series K_RF (bandwidth N, coefficients from N^3 samples of the
+    regularised kernel: two-point Taylor on (1/2 - eps_B, 1/2), eps_B = 1/16,
+    5 matched derivatives).  Points sit on the 2N lattice inside the scaled
+    ball (radius 1/4 - eps_B/2), so every pair difference is a lattice vector
+    and K_RF there is read off one inverse FFT exactly."""
+    import math
+    epsB, p = 1.0 / 16, 5
+    r0 = 0.5 - epsB
+    if kind == "gauss":
+        K = lambda r: np.exp(-r * r / (s * s))
+        u = r0 / s
+        H = [1.0, 2 * u]
+        for j in range(1, p):
+            H.append(2 * u * H[j] - 2 * j * H[j - 1])
+        der = [(-1 / s) ** j * H[j] * math.exp(-u * u) for j in range(p)]
+        kend = math.exp(-0.25 / (s * s))
+    else:
+        K = lambda r: np.exp(-r / s)
+        der = [(-1 / s) ** j * math.exp(-r0 / s) for j in range(p)]
+        kend = math.exp(-0.5 / s)
+    A = np.zeros((2 * p, 2 * p))
+    rhs = np.zeros(2 * p)
+    for j in range(p):
+        A[j, j] = math.factorial(j)
+        rhs[j] = epsB ** j * der[j]
+        for i in range(j, 2 * p):
+            A[p + j, i] = math.factorial(i) / math.factorial(i - j)
+        rhs[p + j] = kend if j == 0 else 0.0
+    coef = np.linalg.solve(A, rhs)
+
+    def KR(r):
+        t = (r - r0) / epsB
+        out = np.where((r > r0) & (r < 0.5), np.polyval(coef[::-1], t), K(r))
+        return np.where(r >= 0.5, kend, out)
+
+    k = np.fft.fftfreq(N, d=1.0 / N) / N
+    g3 = np.meshgrid(k, k, k, indexing="ij")
+    bh = np.fft.fftn(KR(np.sqrt(g3[0] ** 2 + g3[1] ** 2 + g3[2] ** 2))).real / N ** 3
+    M = 2 * N
+    big = np.zeros((M, M, M))
+    idx = np.fft.fftfreq(N, d=1.0 / N).astype(int) % M
+    big[np.ix_(idx, idx, idx)] = bh
+    for ax in range(3):                 # the frequency -N/2 counts half at +-N/2
+        a = np.moveaxis(big, ax, 0)
+        half = 0.5 * a[M - N // 2].copy()
+        a[M - N // 2] = half
+        a[N // 2] = half
+    krf = np.fft.ifftn(big).real * M ** 3
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    m = np.round(v * ((0.25 - epsB / 2) * rng.random(n) ** (1 / 3))[:, None] * M).astype(int)
+    x = rng.standard_normal(n)
+    dm = (m[:, None, :] - m[None, :, :]) % M
+    r = np.sqrt((((m[:, None, :] - m[None, :, :]) / M) ** 2).sum(-1))
+    off = ~np.eye(n, dtype=bool)
+    W = K(r) * off
+    Wt = krf[dm[..., 0], dm[..., 1], dm[..., 2]] * off
+    return np.linalg.norm((Wt - W) @ x) / np.linalg.norm(W @ x)
+
+
+def test_laplacian_kernel_series_decays_algebraically():
+    g64 = _truncation_error("gauss", 0.1, 64)
+    l32 = _truncation_error("lap", 0.1, 32)
+    l64 = _truncation_error("lap", 0.1, 64)
+    assert g64 < 1e-10                       # the Gaussian: spectral accuracy
+    assert l64 > 1e-4                        # the Laplacian RBF misses even the FP32 gate
+    assert 2.0 < l32 / l64 < 12.0            # and gains only a small factor per doubling of N
