@@ -81,21 +81,34 @@ static void ensure_ws(Graph &g, int bs) {
         g.br.resize(nb);
         g.ws_bs = 0;
     }
-    std::vector<void *> before{g.Zs.p, g.Fs.p};
+    // layers that read the shared FP32 slice of x in the API's products
+    std::vector<char> shared(g.T, 0);
+    bool any_shared = false;
+    for (int t = 0; t < g.T; ++t) {
+        const Layer &L = g.layers[t];
+        shared[t] = L.kp.method == MLG_METHOD_NFFT && L.kp.precision == 32 &&
+                    nfft_scaled_input_ok(L.nf, L.win, bs) && (!g.has_degrees || L.zsc.p);
+        any_shared |= shared[t] != 0;
+    }
+    std::vector<void *> before{g.Zs.p, g.Fs.p, g.X32.p};
     for (auto &w : g.br) before.insert(before.end(), {w.patch.p, w.grid.p, w.part.p});
     g.Zs.ensure(zs);
     g.Fs.ensure(zs);
+    if (any_shared) g.X32.ensure((size_t)g.n * bs);
     for (int r = 0; r < nb; ++r) {
         g.br[r].patch.ensure(patch[r]);
         g.br[r].grid.ensure(grid[r]);
         g.br[r].part.ensure(part[r]);
     }
-    std::vector<void *> after{g.Zs.p, g.Fs.p};
+    std::vector<void *> after{g.Zs.p, g.Fs.p, g.X32.p};
     for (auto &w : g.br) after.insert(after.end(), {w.patch.p, w.grid.p, w.part.p});
     const bool moved = g.ws_bs != bs || before != after;
     if (!moved) return;
     for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
     g.caps.clear();
+    g.batches.clear();
+    g.unbatched.clear();
+    g.batch_bs = 0;
     g.slice = slice;
     g.ws_bs = bs;
     std::vector<LayerIO> io(g.T);
@@ -106,10 +119,15 @@ static void ensure_ws(Graph &g, int bs) {
         io[t].dinv = L.dinv.p;
         io[t].K0 = L.kp.method == MLG_METHOD_NFFT ? 1.0 : 0.0;
         io[t].is64 = L.kp.precision == 64;
-        io[t].pad = 0;
+        io[t].shared = 0;
     }
     g.io.alloc(g.T);
     MLG_HIP(hipMemcpyAsync(g.io.p, io.data(), sizeof(LayerIO) * g.T, hipMemcpyHostToDevice, g.stream));
+    g.shared = shared;
+    for (int t = 0; t < g.T; ++t) io[t].shared = shared[t];
+    g.io_sh.alloc(g.T);
+    MLG_HIP(hipMemcpyAsync(g.io_sh.p, io.data(), sizeof(LayerIO) * g.T, hipMemcpyHostToDevice,
+                           g.stream));
     MLG_HIP(hipStreamSynchronize(g.stream));
 }
 
@@ -120,17 +138,26 @@ struct StageTimer {
 
 // F_t = W~ z_t (NFFT) or W z_t (direct) for one layer, in its slices, on
 // stream s with the scratch of the layer's branch.
+// How the summations read their input: own slices, or (sh) the shared FP32
+// slice for the layers marked shared, scaled by D^-1/2 when use_dinv.
+struct InMode {
+    bool sh = false;
+    int use_dinv = 1;
+};
+
 template <class T>
-static void layer_core(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s) {
+static void layer_core(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s, InMode md) {
     Layer &L = g.layers[t];
     Graph::Scratch &w = g.br[t % g.br.size()];
-    T *Zs = reinterpret_cast<T *>(g.Zs.p + g.slice[t]);
+    const bool sh = md.sh && g.shared[t];
+    T *Zs = sh ? reinterpret_cast<T *>(g.X32.p) : reinterpret_cast<T *>(g.Zs.p + g.slice[t]);
     T *Fs = reinterpret_cast<T *>(g.Fs.p + g.slice[t]);
     float ms = 0.f;
     if (tm) MLG_HIP(hipEventRecord(tm->ev[5], s));
     if (L.kp.method == MLG_METHOD_NFFT) {
         nfft_apply<T>(L.nf, L.win, bs, Zs, Fs, reinterpret_cast<T *>(w.patch.p),
-                      reinterpret_cast<T *>(w.grid.p), s, tm ? tm->ev : nullptr);
+                      reinterpret_cast<T *>(w.grid.p), s, tm ? tm->ev : nullptr,
+                      sh && md.use_dinv ? L.zsc.p : nullptr);
     } else {
         const T *x = nullptr;
         if constexpr (sizeof(T) == 8) x = L.x64.p; else x = L.x32.p;
@@ -156,14 +183,63 @@ static void layer_core(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s) {
     }
 }
 
-static void core_layer(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s) {
+static void core_layer(Graph &g, int t, int bs, StageTimer *tm, hipStream_t s, InMode md) {
     if (g.layers[t].kp.precision == 64)
-        layer_core<double>(g, t, bs, tm, s);
+        layer_core<double>(g, t, bs, tm, s, md);
     else
-        layer_core<float>(g, t, bs, tm, s);
+        layer_core<float>(g, t, bs, tm, s, md);
 }
 
 int graph_branches(const Graph &g) { return std::min(g.T, kMaxBranches); }
+
+// Largest patch buffer of a layer that may join a batch (a batch holds the
+// patches of all its layers at once).
+constexpr size_t kBatchPatchBytes = (size_t)512 << 20;
+
+// Batches of the all-layer product for block stride bs: layers with the
+// same batch key (FP32 matrix-core NFFT, one dimension and patch edge) run
+// together when more of them share it than there are branches.  (A few
+// large layers do better as parallel branches, where one layer's short
+// gather, reduction and FFT kernels overlap another's matrix-core kernels;
+// many small layers do better as one launch per stage.)  Built outside any
+// stream capture.
+static void ensure_batches(Graph &g, int bs) {
+    if (g.batch_bs == bs) return;
+    g.batches.clear();
+    g.unbatched.clear();
+    std::vector<int> key(g.T, -1);
+    for (int t = 0; t < g.T; ++t) {
+        const Layer &L = g.layers[t];
+        int k = -1;
+        if (g.shared[t] && nfft_batchable(L, bs, &k) &&
+            nfft_patch_elems(L.nf, L.win, bs) * 4 <= kBatchPatchBytes)
+            key[t] = k;
+    }
+    std::vector<bool> done(g.T, false);
+    for (int t = 0; t < g.T; ++t) {
+        if (done[t]) continue;
+        std::vector<int> members;
+        if (key[t] >= 0)
+            for (int u = t; u < g.T; ++u)
+                if (!done[u] && key[u] == key[t]) members.push_back(u);
+        if ((int)members.size() <= kMaxBranches) {
+            g.unbatched.push_back(t);
+            done[t] = true;
+            continue;
+        }
+        std::vector<const Layer *> ls;
+        std::vector<float *> fs;
+        for (int u : members) {
+            done[u] = true;
+            ls.push_back(&g.layers[u]);
+            fs.push_back(reinterpret_cast<float *>(g.Fs.p + g.slice[u]));
+        }
+        g.batches.emplace_back();
+        nfft_batch_build(g.batches.back(), ls, members, g.X32.p, fs, bs, g.stream);
+    }
+    std::sort(g.unbatched.begin(), g.unbatched.end());
+    g.batch_bs = bs;
+}
 
 // Stream of branch r: g.stream for r = 0, else side stream r - 1 (created
 // on first use, default priority).
@@ -182,12 +258,22 @@ hipStream_t graph_branch_stream(Graph &g, int r) {
 // g.stream and joined back into it (used under stream capture, where this
 // makes parallel branches of the captured graph); otherwise in layer order
 // on stream s (g.stream if null).
-static void core(Graph &g, int layer, int bs, StageTimer *tm, bool fork = false,
+static void core(Graph &g, int layer, int bs, StageTimer *tm, InMode md, bool fork = false,
                  hipStream_t s = nullptr) {
     const int nb = (int)g.br.size();
+    // all-layer products on the shared slice (not stage-timed) run their
+    // batches, one launch per stage for all of a batch's layers; stage
+    // timing walks the layers
+    const bool batched = layer < 0 && md.sh && !tm && g.batch_bs == bs && !g.batches.empty();
+    if (batched && (!fork || nb < 2)) {
+        hipStream_t q = s ? s : g.stream;
+        for (const NfftBatch &B : g.batches) nfft_batch_apply(B, md.use_dinv, q);
+        for (int t : g.unbatched) core_layer(g, t, bs, nullptr, q, md);
+        return;
+    }
     if (!fork || layer >= 0 || nb < 2) {
         for (int t = 0; t < g.T; ++t)
-            if (layer < 0 || t == layer) core_layer(g, t, bs, tm, s ? s : g.stream);
+            if (layer < 0 || t == layer) core_layer(g, t, bs, tm, s ? s : g.stream, md);
         return;
     }
     for (int r = 1; r < nb; ++r) graph_branch_stream(g, r);
@@ -198,9 +284,22 @@ static void core(Graph &g, int layer, int bs, StageTimer *tm, bool fork = false,
     }
     MLG_HIP(hipEventRecord(g.fork_join[0], g.stream));
     for (int r = 1; r < nb; ++r) MLG_HIP(hipStreamWaitEvent(g.side[r - 1], g.fork_join[0], 0));
-    for (int t = 0; t < g.T; ++t) {
-        const int r = t % nb;
-        core_layer(g, t, bs, tm, r == 0 ? g.stream : g.side[r - 1]);
+    if (batched) {
+        // batch k on branch k mod nb; a layer alone on branch t mod nb, whose
+        // scratch it uses (the batches own theirs)
+        for (size_t k = 0; k < g.batches.size(); ++k) {
+            const int r = (int)(k % nb);
+            nfft_batch_apply(g.batches[k], md.use_dinv, r == 0 ? g.stream : g.side[r - 1]);
+        }
+        for (int t : g.unbatched) {
+            const int r = t % nb;
+            core_layer(g, t, bs, nullptr, r == 0 ? g.stream : g.side[r - 1], md);
+        }
+    } else {
+        for (int t = 0; t < g.T; ++t) {
+            const int r = t % nb;
+            core_layer(g, t, bs, tm, r == 0 ? g.stream : g.side[r - 1], md);
+        }
     }
     for (int r = 1; r < nb; ++r) {
         MLG_HIP(hipEventRecord(g.fork_join[r], g.side[r - 1]));
@@ -223,22 +322,28 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
     const int bs = block_stride(b);
     ensure_ws(g, bs);
     hipStream_t s = g.stream;
-    const LayerIO *io = layer >= 0 ? g.io.p + layer : g.io.p;
+    const LayerIO *io = layer >= 0 ? g.io_sh.p + layer : g.io_sh.p;
     const int nl = layer >= 0 ? 1 : g.T;
     const int use_dinv = op != MLG_OP_W;
     const double coef = layer < 0 ? 1.0 / g.T : 1.0;
+    bool need32 = false;
+    for (int t = 0; t < g.T; ++t) need32 |= (layer < 0 || t == layer) && g.shared[t];
+    float *X32 = need32 ? g.X32.p : nullptr;
+    InMode md;
+    md.sh = true;
+    md.use_dinv = use_dinv;
     if (stage_ms) {
         StageTimer tm;
         tm.acc = stage_ms;
         for (auto &e : tm.ev) MLG_HIP(hipEventCreate(&e));
         float ms;
         MLG_HIP(hipEventRecord(tm.ev[6], s));
-        launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
+        launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s, X32);
         MLG_HIP(hipEventRecord(tm.ev[7], s));
         MLG_HIP(hipStreamSynchronize(s));
         MLG_HIP(hipEventElapsedTime(&ms, tm.ev[6], tm.ev[7]));
         stage_ms[MLG_STAGE_PRE] += ms;
-        core(g, layer, bs, &tm);
+        core(g, layer, bs, &tm, md);
         MLG_HIP(hipEventRecord(tm.ev[6], s));
         launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
         MLG_HIP(hipEventRecord(tm.ev[7], s));
@@ -248,7 +353,7 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
         for (auto &e : tm.ev) (void)hipEventDestroy(e);
         return;
     }
-    graph_core_enqueue(g, layer, use_dinv, b, X, ldx);
+    graph_core_enqueue(g, layer, use_dinv, b, X, ldx, nullptr, true, false);
     launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
 }
 
@@ -259,23 +364,32 @@ const LayerIO *graph_layer_io(Graph &g, int b, int t) {
 }
 
 const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
-                                  int64_t ldx, hipStream_t stream, bool scatter) {
+                                  int64_t ldx, hipStream_t stream, bool scatter, bool own) {
     MLG_REQUIRE(layer >= -1 && layer < g.T, MLG_ERR_ARG, "layer out of range");
     MLG_REQUIRE(b >= 1 && b <= 64, MLG_ERR_ARG, "b must be in 1..64");
     const int bs = block_stride(b);
     ensure_ws(g, bs);
     hipStream_t s = stream ? stream : g.stream;
-    const LayerIO *io = layer >= 0 ? g.io.p + layer : g.io.p;
+    const LayerIO *iob = own ? g.io.p : g.io_sh.p;
+    const LayerIO *io = layer >= 0 ? iob + layer : iob;
     const int nl = layer >= 0 ? 1 : g.T;
-    if (scatter) launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s);
+    InMode md;
+    md.sh = !own;
+    md.use_dinv = use_dinv;
+    bool need32 = false;
+    for (int t = 0; t < g.T; ++t) need32 |= !own && (layer < 0 || t == layer) && g.shared[t];
+    if (layer < 0 && !own) ensure_batches(g, bs);
+    if (scatter) launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s, need32 ? g.X32.p : nullptr);
+    // captured launch sequences keyed by (layer, input mode, b)
+    const int mode = (own ? 0 : 2) + (use_dinv ? 1 : 0);
     hipGraphExec_t exec = nullptr;
     for (auto &c : g.caps)
-        if (c.layer == layer && c.b == bs) exec = c.exec;
+        if (c.layer == layer && c.op == mode && c.b == bs) exec = c.exec;
     if (!exec) {
         hipGraph_t graph;
         MLG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-            core(g, layer, bs, nullptr, s == g.stream, s);
+            core(g, layer, bs, nullptr, md, s == g.stream, s);
         } catch (...) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(s, &junk);
@@ -286,7 +400,7 @@ const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, cons
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         MLG_HIP(e);
-        g.caps.push_back({layer, 0, bs, exec});
+        g.caps.push_back({layer, mode, bs, exec});
     }
     MLG_HIP(hipGraphLaunch(exec, s));
     return io;
@@ -405,6 +519,12 @@ static void compute_degrees(Graph &g, Layer &L, const double *pts) {
                                                   : ""));
     L.dinv.alloc(n);
     launch_dinv(n, L.deg.p, L.dinv.p, s);
+    if (L.kp.method == MLG_METHOD_NFFT) {
+        // D^-1/2 in the layer's bin order, FP32: the factor its matrix-core
+        // spreading applies to the shared slice of x
+        L.zsc.alloc(n);
+        launch_sorted_f32(n, L.nf.perm.p, L.dinv.p, L.zsc.p, s);
+    }
     MLG_HIP(hipStreamSynchronize(s));
 }
 

@@ -80,6 +80,7 @@ struct Layer {
     NfftWindow win;          // matvec window
     DevBuf<double> deg;      // degrees, original order
     DevBuf<double> dinv;     // D^-1/2, original order
+    DevBuf<float> zsc;       // NFFT: D^-1/2 rounded to FP32, in bin order
     double deg_err = 0;      // NFFT: largest sampled absolute error of the degree pass
     double iso_thresh = 0;   // degrees <= this are isolated (MLG_ERR_ISOLATED)
 };
@@ -91,18 +92,24 @@ struct LayerIO {
     const double *dinv;      // D^-1/2, original order
     double K0;               // self term removed after the summation (0 for direct)
     int is64;
-    int pad;
+    // 1: the summation reads the shared FP32 slice of x and multiplies each
+    // row by D^-1/2 rounded to FP32 itself (its input value is the FP32
+    // product fl(x) fl(D^-1/2)); the entry kernel writes no slice for it
+    int shared;
 };
 
 // ---- layer_ops.hip ----------------------------------------------------------
+// X32: the shared FP32 slice of x (n x bs, node order) written once, or null.
 void launch_scatter_in(int64_t n, int b, int bs, const double *X, int64_t ldx, const LayerIO *L,
-                       int nl, int use_dinv, hipStream_t s);
+                       int nl, int use_dinv, hipStream_t s, float *X32 = nullptr);
 void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, double *Y,
                        int64_t ldy, const LayerIO *L, int nl, int use_dinv, int lsym, double coef,
                        hipStream_t s);
 void launch_fill_ones(int64_t n, double *Xr, hipStream_t s);
 void launch_check_degrees(int64_t n, const double *deg, double thresh, int *flag, hipStream_t s);
 void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s);
+// dst[p] = (float)src[perm[p]].
+void launch_sorted_f32(int64_t n, const int *perm, const double *src, float *dst, hipStream_t s);
 
 // ---- direct.hip ---------------------------------------------------------------
 // Scaled, centred coordinates of a direct layer (d x n SoA): x64 for the
@@ -130,10 +137,60 @@ int nfft_auto_bandwidth(double sigma_s, int d, int prec);
 void nfft_make_window(const Layer &L, NfftWindow &W, int w, int prec, int bs, hipStream_t s);
 size_t nfft_patch_elems(const NfftPlan &P, const NfftWindow &W, int bs);
 size_t nfft_grid_elems(const NfftPlan &P, int bs);
-// W~ applied to Zs (sorted, T, stride bs) -> Fs; uses patch and grid workspaces.
+// W~ applied to Zs (node order, T, stride bs) -> Fs; uses patch and grid
+// workspaces.  With zsc (FP32 matrix-core path only, see
+// nfft_scaled_input_ok), the summation input of point p (bin order) is row
+// perm[p] of Zs times zsc[p], as an FP32 product.
 template <class T>
 void nfft_apply(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs, T *Fs, T *patch,
-                T *grid, hipStream_t s, hipEvent_t *ev /* 5 events or null */);
+                T *grid, hipStream_t s, hipEvent_t *ev /* 5 events or null */,
+                const float *zsc = nullptr);
+bool nfft_scaled_input_ok(const NfftPlan &P, const NfftWindow &W, int bs);
+
+// Several FP32 matrix-core NFFT layers of one dimension and patch edge run
+// as one launch per stage (spreading, split-bin reductions, cell-table
+// gather, interpolation; the FFT once per group of equal N): the layers'
+// task lists are concatenated with a task -> layer map, patch slots and grid
+// regions laid out one layer after another in buffers the batch owns.  Each
+// layer's arithmetic is the per-layer path's, so results are the same bits.
+struct NfftBatch {
+    int D = 0, Pside = 0, bs = 0, bg = 0, nl = 0;
+    std::vector<int> layers;       // graph layer of each batch layer (sorted by N)
+    DevBuf<char> args, args_n;     // nl device LayerArgs: with D^-1/2 scaling, without
+    DevBuf<int4> stasks;           // spreading tasks, destination slots global
+    DevBuf<int> slayer;
+    int nst = 0;
+    DevBuf<int4> itasks;           // interpolation tasks
+    DevBuf<int> ilayer;
+    int nit = 0, isplit = 1, iper = 0;
+    DevBuf<int4> red1, red2;
+    int nred1 = 0, nred2 = 0;
+    DevBuf<int> cptr, cent;        // concatenated cell tables
+    DevBuf<int64_t> coff, goff;    // flat cell offsets (nl + 1), grid offsets (elements)
+    std::vector<int64_t> goff_h;
+    int64_t ncell = 0;
+    struct Sub {                   // layers first .. first + count - 1 share N
+        const NfftPlan *plan = nullptr;   // the first one's plan (N, grid, twiddles)
+        int first = 0, count = 0;
+        int64_t mstr = 0;
+        DevBuf<float> M;           // their multipliers, one after another
+    };
+    std::vector<Sub> subs;
+    DevBuf<float> patch, grid;
+    size_t patch_elems = 0, grid_elems = 0;
+};
+// Build a batch of the given layers (all FP32 NFFT on the matrix-core path
+// with a cell table, one D and patch edge) for block stride bs; Zs[i] / Fs[i]
+// are layer i's summation slices.
+// The batch reads the shared FP32 slice X32 and scales it by each layer's
+// zsc (use_dinv) or not (two argument tables).
+void nfft_batch_build(NfftBatch &B, const std::vector<const Layer *> &layers,
+                      const std::vector<int> &ids, const float *X32,
+                      const std::vector<float *> &Fs, int bs, hipStream_t s);
+// Whether a layer can join a batch for block stride bs, and its (D, patch
+// edge) key.
+bool nfft_batchable(const Layer &L, int bs, int *key);
+void nfft_batch_apply(const NfftBatch &B, int use_dinv, hipStream_t s);
 
 // ---- lanczos.hip ----------------------------------------------------------------
 struct Graph;
@@ -250,7 +307,19 @@ struct Graph {
     std::vector<hipEvent_t> fork_join;   // [0]: fork, [r]: join of branch r
     int ws_bs = 0;                 // block stride the slices are laid out for
     std::vector<size_t> slice;     // byte offset of layer t's slice
-    DevBuf<LayerIO> io;            // device copy of the T layer descriptors
+    DevBuf<LayerIO> io;            // device copy of the T layer descriptors (own slices)
+    // the API's products: FP32 matrix-core NFFT layers read one shared FP32
+    // slice of x (X32) and scale it per point themselves (shared[t]);
+    // io_sh marks them.  The Krylov power keeps own slices (its layers run
+    // different vectors at once).
+    DevBuf<float> X32;
+    std::vector<char> shared;
+    DevBuf<LayerIO> io_sh;
+    // all-layer products: batches of FP32 matrix-core layers (built for
+    // block stride batch_bs) and the layers that run alone
+    std::vector<NfftBatch> batches;
+    std::vector<int> unbatched;
+    int batch_bs = 0;
     // captured graphs keyed by (layer, op, b)
     struct Cap {
         int layer, op, b;
@@ -273,8 +342,11 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
 // to different branches (t mod graph_branches(g)).
 // With scatter = false the entry kernel is skipped: the caller has written
 // the layers' summation inputs itself (see graph_layer_io).
+// With own = false the layers marked shared read the shared FP32 slice
+// (the API's products); own = true keeps every layer on its own slice.
 const LayerIO *graph_core_enqueue(Graph &g, int layer, int use_dinv, int b, const double *X,
-                                  int64_t ldx, hipStream_t stream = nullptr, bool scatter = true);
+                                  int64_t ldx, hipStream_t stream = nullptr, bool scatter = true,
+                                  bool own = false);
 // Device descriptor of layer t's slices for blocks of b vectors (workspace
 // laid out for that block stride first).
 const LayerIO *graph_layer_io(Graph &g, int b, int t);

@@ -68,7 +68,7 @@ constexpr int kIoTile = 32;
 __global__ __launch_bounds__(256) void k_scatter_in(int64_t n, int b, int bs,
                                                     const double *__restrict__ X, int64_t ldx,
                                                     const LayerIO *__restrict__ L, int nl,
-                                                    int use_dinv) {
+                                                    int use_dinv, float *__restrict__ X32) {
     __shared__ float tile[256 * (kIoTile + 1)];
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t i = i0 + threadIdx.x;
@@ -87,8 +87,33 @@ __global__ __launch_bounds__(256) void k_scatter_in(int64_t n, int b, int bs,
 #pragma unroll
             for (int j = 0; j < kIoVG; ++j) x[gi][j] = 0.0;
     }
+    // the shared FP32 slice of x (layers marked shared scale it themselves)
+    if (X32) {
+        if (tiled) {
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi)
+                if (gi < ng)
+#pragma unroll
+                    for (int j = 0; j < kIoVG; ++j)
+                        if (j < vgw) tile[threadIdx.x * ldt + gi * vgw + j] = (float)x[gi][j];
+            __syncthreads();
+            float *dst = X32 + i0 * bs;
+            for (int e = threadIdx.x; e < rows * bs; e += 256) {
+                const int r = e / bs, c = e - r * bs;
+                dst[e] = tile[r * ldt + c];
+            }
+            __syncthreads();
+        } else if (live) {
+            for (int v0 = 0; v0 < bs; v0 += vgw) {
+                double xr[kIoVG];
+                load_block_row(X, ldx, i, b, v0, vgw, xr);
+                store_row<float>(X32, i * bs + v0, xr, vgw);
+            }
+        }
+    }
     for (int t = 0; t < nl; ++t) {
         const LayerIO d = L[t];
+        if (d.shared) continue;
         if (tiled && !d.is64) {
             const double di = (use_dinv && live) ? d.dinv[i] : 1.0;
 #pragma unroll
@@ -183,8 +208,11 @@ __global__ __launch_bounds__(256) void k_gather_out(int64_t n, int b, int bs, in
         for (int j = 0; j < kOutVG; ++j) {
             if (j < vgw) {
                 const double zx = use_dinv ? x[j] * di : x[j];
-                // the value the summation saw (FP32 layers round it)
-                const double z = d.is64 ? zx : (double)(float)zx;
+                // the value the summation saw (FP32 layers round it; a shared
+                // slice gives the FP32 product of the rounded factors)
+                const double z = d.is64 ? zx
+                                 : d.shared ? (double)(use_dinv ? (float)x[j] * (float)di : (float)x[j])
+                                            : (double)(float)zx;
                 double w = f[j] - d.K0 * z;
                 if (use_dinv) w *= di;
                 acc[j] += w;
@@ -218,15 +246,21 @@ __global__ void k_dinv(int64_t n, const double *deg, double *dinv) {
     if (i < n) dinv[i] = 1.0 / sqrt(deg[i]);
 }
 
+__global__ void k_sorted_f32(int64_t n, const int *__restrict__ perm, const double *__restrict__ src,
+                             float *__restrict__ dst) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) dst[p] = (float)src[perm[p]];
+}
+
 static inline unsigned blocks_for(int64_t work, int threads) {
     return (unsigned)((work + threads - 1) / threads);
 }
 
 void launch_scatter_in(int64_t n, int b, int bs, const double *X, int64_t ldx, const LayerIO *L,
-                       int nl, int use_dinv, hipStream_t s) {
+                       int nl, int use_dinv, hipStream_t s, float *X32) {
     MLG_REQUIRE(bs <= 64 && b <= bs, MLG_ERR_ARG, "block too wide");
     hipLaunchKernelGGL(k_scatter_in, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, b, bs, X, ldx, L,
-                       nl, use_dinv);
+                       nl, use_dinv, X32);
     MLG_LAUNCH_CHECK();
 }
 
@@ -252,6 +286,11 @@ void launch_fill_ones(int64_t n, double *Xr, hipStream_t s) {
 void launch_check_degrees(int64_t n, const double *deg, double thresh, int *flag, hipStream_t s) {
     hipLaunchKernelGGL(k_check_degrees, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, deg, thresh,
                        flag);
+    MLG_LAUNCH_CHECK();
+}
+
+void launch_sorted_f32(int64_t n, const int *perm, const double *src, float *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_sorted_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, perm, src, dst);
     MLG_LAUNCH_CHECK();
 }
 

@@ -363,6 +363,25 @@ struct Geom {
     // sorted position -> original index: the vector blocks Zs / Fs are kept
     // in the caller's node order, points in bin order
     const int *perm;
+    // optional per-point factor (bin order) applied to each z row as it is
+    // read: the matrix-core spreading of a layer that reads the shared FP32
+    // slice of x multiplies by its D^-1/2 (rounded to FP32) there
+    const float *zsc;
+};
+
+
+
+// One layer of a batched launch (several layers' tasks in one grid): the
+// matrix-core kernels take the layer of task k from tlayer[k] and its
+// geometry and arrays from here instead of their own arguments.
+struct LayerArgs {
+    Geom g;
+    const int *c32;
+    const float *f32;
+    const float *Zs;     // spreading input slice
+    float *Fs;           // interpolation output slice
+    const float *grid;   // interpolation input grid
+    float beta;
 };
 
 // (cell, fractional offset) of point p along dimension t.
@@ -626,22 +645,43 @@ constexpr int csr_batch() {
 // Gather through the cell table: sum of the cell's patch entries in entry
 // order (entries of one cell are sorted by run), NB entries in flight per
 // batch (NB x VPL values of at most 64 registers).
+// Batched form: the cells of nl layers in one flat index; layer t owns flat
+// cells [coff[t], coff[t+1]) and its grid starts goff[t] elements after
+// gridb; ptr / ent are the layers' tables concatenated (entries of patch
+// slots in the batch's shared patch buffer).
 template <class T, int VPL, int NB = csr_batch<T, VPL>()>
 __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
                                                     const int *__restrict__ ptr,
                                                     const int *__restrict__ ent,
                                                     const T *__restrict__ patch,
-                                                    T *__restrict__ grid) {
-    const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= G) return;
+                                                    T *__restrict__ grid_, int nl,
+                                                    const int64_t *__restrict__ coff,
+                                                    const int64_t *__restrict__ goff) {
+    const int64_t flat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t cell = flat;
+    T *__restrict__ grid = grid_;
+    if (nl > 0) {
+        if (flat >= coff[nl]) return;
+        int lo = 0, hi = nl - 1;   // the layer: largest t with coff[t] <= flat
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (coff[mid] <= flat) lo = mid;
+            else hi = mid - 1;
+        }
+        G = coff[lo + 1] - coff[lo];
+        cell = flat - coff[lo];
+        grid = grid_ + goff[lo];
+    } else if (cell >= G) {
+        return;
+    }
     const int v0 = blockIdx.y * VPL;
     T acc[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; ++v) acc[v] = T(0);
-    const int e1 = ptr[cell + 1];
+    const int e1 = ptr[flat + 1];
     // entries in batches of NB: indices, then rows, all in flight; summed in
     // entry order
-    for (int e0 = ptr[cell]; e0 < e1; e0 += NB) {
+    for (int e0 = ptr[flat]; e0 < e1; e0 += NB) {
         int idx[NB];
 #pragma unroll
         for (int u = 0; u < NB; ++u) idx[u] = e0 + u < e1 ? ent[e0 + u] : -1;
@@ -831,11 +871,19 @@ __device__ inline void task_origin(const Geom &g, unsigned key, int org[3]) {
 }
 
 template <int D, int P>
-__global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restrict__ tasks,
-                                                    const int *__restrict__ c32,
-                                                    const float *__restrict__ f32,
-                                                    const float *__restrict__ Zs, float beta,
-                                                    float *__restrict__ patch) {
+__global__ __launch_bounds__(64) void k_spread_mfma(Geom g_, const int4 *__restrict__ tasks,
+                                                    const int *__restrict__ c32_,
+                                                    const float *__restrict__ f32_,
+                                                    const float *__restrict__ Zs_, float beta_,
+                                                    float *__restrict__ patch,
+                                                    const LayerArgs *__restrict__ lay,
+                                                    const int *__restrict__ tlayer) {
+    const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x] : nullptr;
+    const Geom g = lp ? lp->g : g_;
+    const int *__restrict__ c32 = lp ? lp->c32 : c32_;
+    const float *__restrict__ f32 = lp ? lp->f32 : f32_;
+    const float *__restrict__ Zs = lp ? lp->Zs : Zs_;
+    const float beta = lp ? lp->beta : beta_;
     using S = MfShape<D, P>;
     constexpr int NT = S::NT, WSP = S::WSP;
     __shared__ __attribute__((aligned(16))) float wts[64 * WSP];
@@ -870,6 +918,7 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
 
     PtIn<D> pin;
     float4 zin[4];
+    float zf = 1.0f;   // the row's factor, applied when the row is staged
     // node rows of the points run one chunk ahead of their coordinates, so
     // no load waits on another inside the loop
     int rown;
@@ -881,6 +930,7 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
         rown = lane + 64 < tk.z ? g.perm[(int64_t)tk.y + 64 + lane] : 0;
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
@@ -888,7 +938,9 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
         __syncthreads();
         put_record<D, P>(pin, lane < cnt, org, g.w, two_over_w, beta, wts + lane * WSP);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) *reinterpret_cast<float4 *>(zv + lane * 16 + 4 * j) = zin[j];
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<float4 *>(zv + lane * 16 + 4 * j) =
+                make_float4(zin[j].x * zf, zin[j].y * zf, zin[j].z * zf, zin[j].w * zf);
         __syncthreads();
         const int c1 = c0 + 64;
         if (c1 < tk.z) {   // prefetch the next chunk while this one is multiplied
@@ -899,6 +951,7 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g, const int4 *__restri
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+            zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
             rown = lane + 64 < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
         }
 #pragma unroll
@@ -967,11 +1020,20 @@ __device__ inline void interp_chunk(const float *__restrict__ wts, const int (&q
 }
 
 template <int D, int P>
-__global__ __launch_bounds__(64) void k_interp_mfma(Geom g, const int4 *__restrict__ tasks,
-                                                    const int *__restrict__ c32,
-                                                    const float *__restrict__ f32,
-                                                    const float *__restrict__ grid, int bg,
-                                                    float beta, float *__restrict__ Fs) {
+__global__ __launch_bounds__(64) void k_interp_mfma(Geom g_, const int4 *__restrict__ tasks,
+                                                    const int *__restrict__ c32_,
+                                                    const float *__restrict__ f32_,
+                                                    const float *__restrict__ grid_, int bg,
+                                                    float beta_, float *__restrict__ Fs_,
+                                                    const LayerArgs *__restrict__ lay,
+                                                    const int *__restrict__ tlayer) {
+    const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x] : nullptr;
+    const Geom g = lp ? lp->g : g_;
+    const int *__restrict__ c32 = lp ? lp->c32 : c32_;
+    const float *__restrict__ f32 = lp ? lp->f32 : f32_;
+    const float *__restrict__ grid = lp ? lp->grid : grid_;
+    const float beta = lp ? lp->beta : beta_;
+    float *__restrict__ Fs = lp ? lp->Fs : Fs_;
     using S = MfShape<D, P>;
     constexpr int WSP = S::WSP;
     constexpr int KSV = (S::PD + 3) / 4;
@@ -1113,6 +1175,7 @@ __device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
 
     PtIn<3> pin;
     float4 zin[4];
+    float zf = 1.0f;   // the row's factor, applied when the row is staged
     // node rows of the points run one chunk ahead of their coordinates, so
     // no load waits on another inside the loop
     int rown;
@@ -1124,6 +1187,7 @@ __device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
         rown = lane + 64 < tk.z ? g.perm[(int64_t)tk.y + 64 + lane] : 0;
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
@@ -1150,7 +1214,9 @@ __device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
             *reinterpret_cast<float4 *>(wzs + lane * 8 + 4) = make_float4(zr[4], zr[5], zr[6], zr[7]);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) *reinterpret_cast<float4 *>(zv + lane * 16 + 4 * j) = zin[j];
+        for (int j = 0; j < 4; ++j)
+            *reinterpret_cast<float4 *>(zv + lane * 16 + 4 * j) =
+                make_float4(zin[j].x * zf, zin[j].y * zf, zin[j].z * zf, zin[j].w * zf);
         __syncthreads();
         const int c1 = c0 + 64;
         if (c1 < tk.z) {   // prefetch the next chunk while this one is multiplied
@@ -1161,6 +1227,7 @@ __device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+            zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
             rown = lane + 64 < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
         }
         // all 16 groups in one straight-line block (absent points carry zero
@@ -1243,21 +1310,33 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                      const int *__restrict__ c32,
                                                      const float *__restrict__ f32,
                                                      const float *__restrict__ Zs, float beta,
-                                                     float *__restrict__ patch) {
+                                                     float *__restrict__ patch,
+                                                     const LayerArgs *__restrict__ lay,
+                                                     const int *__restrict__ tlayer) {
     using S = MfShape3<P>;
     __shared__ __attribute__((aligned(16))) float wxy[64 * S::RS];
     __shared__ __attribute__((aligned(16))) float wzs[64 * 8];
     __shared__ __attribute__((aligned(16))) float zv[64 * 16];
-    spread3_task<P>(g, tasks[blockIdx.x], c32, f32, Zs, beta, patch, wxy, wzs, zv);
+    const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x] : nullptr;
+    spread3_task<P>(lp ? lp->g : g, tasks[blockIdx.x], lp ? lp->c32 : c32, lp ? lp->f32 : f32,
+                    lp ? lp->Zs : Zs, lp ? lp->beta : beta, patch, wxy, wzs, zv);
 }
 
 template <int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_interp_mfma3(Geom g, const int4 *__restrict__ tasks,
-                                                     const int *__restrict__ c32,
-                                                     const float *__restrict__ f32,
-                                                     const float *__restrict__ grid, int bg,
-                                                     float beta, float *__restrict__ Fs, int split,
-                                                     int per) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_interp_mfma3(Geom g_, const int4 *__restrict__ tasks,
+                                                     const int *__restrict__ c32_,
+                                                     const float *__restrict__ f32_,
+                                                     const float *__restrict__ grid_, int bg,
+                                                     float beta_, float *__restrict__ Fs_, int split,
+                                                     int per, const LayerArgs *__restrict__ lay,
+                                                     const int *__restrict__ tlayer) {
+    const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x / split] : nullptr;
+    const Geom g = lp ? lp->g : g_;
+    const int *__restrict__ c32 = lp ? lp->c32 : c32_;
+    const float *__restrict__ f32 = lp ? lp->f32 : f32_;
+    const float *__restrict__ grid = lp ? lp->grid : grid_;
+    const float beta = lp ? lp->beta : beta_;
+    float *__restrict__ Fs = lp ? lp->Fs : Fs_;
     using S = MfShape3<P>;
     constexpr int KS2 = S::KS2, ES = S::ES, NE = S::NE, C2 = S::C2;
     // entry-major weights: entry e of point p at wt[e * ES + p]; entries
@@ -1447,6 +1526,10 @@ struct FftPass {
     int logC, logOB;     // workgroup tile: C = 2^logC columns, OB = 2^logOB outers
     int64_t nachunk;     // ceil(A / C)
     int flat;            // lines numbered o * A + a, LINES consecutive ones per workgroup
+    // batched layers: plane q = blockIdx.y belongs to layer q / lq, whose
+    // multipliers start at M + (q / lq) mstr (mstr = 0: one set for all)
+    int lq;
+    int64_t mstr;
 };
 
 template <class C2, int LOGL, int LDL>
@@ -1621,7 +1704,8 @@ __device__ inline void fft64_r8_two(C2 *buf, const C2 *tw, bool inverse, const i
 template <class C2, int MODE>
 __global__ __launch_bounds__(256) void k_fft_xy64(C2 *__restrict__ data, int N, int64_t qstr,
                                                   const C2 *__restrict__ twg,
-                                                  const decltype(C2::x) *__restrict__ M) {
+                                                  const decltype(C2::x) *__restrict__ M, int lq,
+                                                  int64_t mstr) {
     constexpr int INV = MODE == 1;
     constexpr int L = 64, LD = 65, PER = L * L / 256;
     __shared__ C2 buf[L * LD];
@@ -1629,6 +1713,8 @@ __global__ __launch_bounds__(256) void k_fft_xy64(C2 *__restrict__ data, int N, 
     const int t = threadIdx.x;
     if (t < L / 2) tw[t] = twg[t];
     data += (int64_t)blockIdx.y * qstr + (int64_t)blockIdx.x * (L * L);
+    // batched layers: vector pair blockIdx.y belongs to layer blockIdx.y / lq
+    if (MODE == 2 && mstr) M += (int64_t)(blockIdx.y / lq) * mstr;
     C2 val[PER];
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
@@ -1691,6 +1777,7 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
     __shared__ C2 tw[L / 2];
     for (int j = threadIdx.x; j < L / 2; j += blockDim.x) tw[j] = twg[j];
     data += (int64_t)blockIdx.y * p.qstr;
+    if (p.mstr) M += (int64_t)(blockIdx.y / p.lq) * p.mstr;
     int C = 1 << p.logC;
     int64_t a0 = ((int64_t)blockIdx.x % p.nachunk) << p.logC;
     int64_t o0 = ((int64_t)blockIdx.x / p.nachunk) << p.logOB;
@@ -2434,11 +2521,13 @@ static void fft_dispatch(const NfftPlan &P, const FftPass &p, int nq, typename C
 //   z (ax = 2): the band x columns of the band y rows.
 template <class T>
 static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, int ax, int mode,
-                     const T *M, hipStream_t s) {
+                     const T *M, hipStream_t s, int nl = 1, int64_t mstr = 0) {
     const int64_t L = P.nos;
     FftPass p{};
     p.N = P.N;
     p.mode = mode;
+    p.lq = bg / 2;
+    p.mstr = M ? mstr : 0;
     p.qstr = 1;
     for (int t = 0; t < P.d; ++t) p.qstr *= L;
     if (ax == 0) {
@@ -2463,7 +2552,7 @@ static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, in
         p.ostr = L;
         p.obnd = 1;
     }
-    fft_dispatch<T>(P, p, bg / 2, grid, M, s);
+    fft_dispatch<T>(P, p, bg / 2 * nl, grid, M, s);
 }
 
 // Forward FFT, multiplication by M and inverse FFT with band pruning, plane
@@ -2478,45 +2567,48 @@ static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, in
 // (d = 2: the whole convolution).
 // Only entries with every frequency inside the band are ever multiplied;
 // the out-of-band ones are never read again.
+// With nl > 1 the grid holds nl layers of the same N one after another
+// (bg / 2 planes each) and their multipliers sit mstr apart from M on.
 template <class T>
 static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, const T *M,
-                         hipStream_t s) {
+                         hipStream_t s, int nl = 1, int64_t mstr = 0) {
     const int d = P.d;
+    const int nq = bg / 2 * nl;
     if (d == 1) {
-        fft_pass<T>(P, bg, grid, 0, 2, M, s);
+        fft_pass<T>(P, bg, grid, 0, 2, M, s, nl, mstr);
     } else if (d == 2) {
         if constexpr (std::is_same<T, float>::value) {
             if (P.nos == 64) {
-                MLG_REQUIRE(bg / 2 <= 65535, MLG_ERR_RANGE, "FFT grid too large");
-                hipLaunchKernelGGL((k_fft_xy64<float2, 2>), dim3(1, bg / 2), dim3(256), 0, s, grid, P.N,
-                                   (int64_t)64 * 64, tw_of<T>(P), M);
+                MLG_REQUIRE(nq <= 65535, MLG_ERR_RANGE, "FFT grid too large");
+                hipLaunchKernelGGL((k_fft_xy64<float2, 2>), dim3(1, nq), dim3(256), 0, s, grid, P.N,
+                                   (int64_t)64 * 64, tw_of<T>(P), M, bg / 2, mstr);
                 MLG_LAUNCH_CHECK();
                 return;
             }
         }
-        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s);
-        fft_pass<T>(P, bg, grid, 1, 2, M, s);
-        fft_pass<T>(P, bg, grid, 0, 1, nullptr, s);
+        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s, nl);
+        fft_pass<T>(P, bg, grid, 1, 2, M, s, nl, mstr);
+        fft_pass<T>(P, bg, grid, 0, 1, nullptr, s, nl);
     } else {
         if constexpr (std::is_same<T, float>::value) {
             if (P.nos == 64) {
                 const int64_t qstr = (int64_t)64 * 64 * 64;
-                MLG_REQUIRE(bg / 2 <= 65535, MLG_ERR_RANGE, "FFT grid too large");
-                hipLaunchKernelGGL((k_fft_xy64<float2, 0>), dim3(64, bg / 2), dim3(256), 0, s, grid,
-                                   P.N, qstr, tw_of<T>(P), nullptr);
+                MLG_REQUIRE(nq <= 65535, MLG_ERR_RANGE, "FFT grid too large");
+                hipLaunchKernelGGL((k_fft_xy64<float2, 0>), dim3(64, nq), dim3(256), 0, s, grid,
+                                   P.N, qstr, tw_of<T>(P), nullptr, bg / 2, (int64_t)0);
                 MLG_LAUNCH_CHECK();
-                fft_pass<T>(P, bg, grid, 2, 2, M, s);
-                hipLaunchKernelGGL((k_fft_xy64<float2, 1>), dim3(64, bg / 2), dim3(256), 0, s, grid,
-                                   P.N, qstr, tw_of<T>(P), nullptr);
+                fft_pass<T>(P, bg, grid, 2, 2, M, s, nl, mstr);
+                hipLaunchKernelGGL((k_fft_xy64<float2, 1>), dim3(64, nq), dim3(256), 0, s, grid,
+                                   P.N, qstr, tw_of<T>(P), nullptr, bg / 2, (int64_t)0);
                 MLG_LAUNCH_CHECK();
                 return;
             }
         }
-        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s);
-        fft_pass<T>(P, bg, grid, 1, 0, nullptr, s);
-        fft_pass<T>(P, bg, grid, 2, 2, M, s);
-        fft_pass<T>(P, bg, grid, 1, 1, nullptr, s);
-        fft_pass<T>(P, bg, grid, 0, 1, nullptr, s);
+        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s, nl);
+        fft_pass<T>(P, bg, grid, 1, 0, nullptr, s, nl);
+        fft_pass<T>(P, bg, grid, 2, 2, M, s, nl, mstr);
+        fft_pass<T>(P, bg, grid, 1, 1, nullptr, s, nl);
+        fft_pass<T>(P, bg, grid, 0, 1, nullptr, s, nl);
     }
 }
 
@@ -2576,8 +2668,9 @@ static void launch_interp(const Geom &g, const NfftPlan &P, const T *grid, int b
 
 template <class T, int D>
 static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs, T *Fs, T *patch,
-                    T *grid, hipStream_t s, hipEvent_t *ev) {
+                    T *grid, hipStream_t s, hipEvent_t *ev, const float *zsc) {
     Geom g;
+    g.zsc = zsc;
     g.d = D;
     g.nos = P.nos;
     g.B = P.B;
@@ -2604,10 +2697,11 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
 #define SPREADM_CALL(DD, PP)                                                                      \
     if constexpr (DD == 3)                                                                        \
         hipLaunchKernelGGL((k_spread_mfma3<PP>), dim3(sched ? P.nseg : P.ntasks, bs / 16), dim3(64), 0, s, \
-                           g, sched ? P.seg.p : P.tasks.p, P.c32.p, P.f32.p, Zs, beta, patch);   \
+                           g, sched ? P.seg.p : P.tasks.p, P.c32.p, P.f32.p, Zs, beta, patch,    \
+                           nullptr, nullptr);                                                     \
     else                                                                                          \
         hipLaunchKernelGGL((k_spread_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
-                           P.c32.p, P.f32.p, Zs, beta, patch)
+                           P.c32.p, P.f32.p, Zs, beta, patch, nullptr, nullptr)
                 MLG_P_SWITCH(D, g.P, SPREADM_CALL)
 #undef SPREADM_CALL
                 MLG_LAUNCH_CHECK();
@@ -2645,7 +2739,7 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     if (W.csr) {
 #define GATHERC_CALL(V)                                                                           \
     hipLaunchKernelGGL((k_gather_csr<T, V>), dim3(ceil_div(G, 256), bs / V), dim3(256), 0, s, G, bs, bg, \
-                       W.cell_ptr.p, W.cell_ent.p, patch, grid)
+                       W.cell_ptr.p, W.cell_ent.p, patch, grid, 0, nullptr, nullptr)
         MLG_VPL_SWITCH(vgat, GATHERC_CALL)
 #undef GATHERC_CALL
         MLG_LAUNCH_CHECK();
@@ -2676,10 +2770,10 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
 #define INTERPM_CALL(DD, PP)                                                                      \
     if constexpr (DD == 3)                                                                        \
         hipLaunchKernelGGL((k_interp_mfma3<PP>), dim3(ntk * isplit, bs / 16), dim3(64), 0, s, g,  \
-                           itk, P.c32.p, P.f32.p, grid, bg, beta, Fs, isplit, iper);             \
+                           itk, P.c32.p, P.f32.p, grid, bg, beta, Fs, isplit, iper, nullptr, nullptr); \
     else                                                                                          \
         hipLaunchKernelGGL((k_interp_mfma<DD, PP>), dim3(P.ntasks, bs / 16), dim3(64), 0, s, g, P.tasks.p, \
-                           P.c32.p, P.f32.p, grid, bg, beta, Fs)
+                           P.c32.p, P.f32.p, grid, bg, beta, Fs, nullptr, nullptr)
             MLG_P_SWITCH(D, g.P, INTERPM_CALL)
 #undef INTERPM_CALL
             MLG_LAUNCH_CHECK();
@@ -2696,18 +2790,297 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
 
 template <class T>
 void nfft_apply(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs, T *Fs, T *patch,
-                T *grid, hipStream_t s, hipEvent_t *ev) {
+                T *grid, hipStream_t s, hipEvent_t *ev, const float *zsc) {
+    MLG_REQUIRE(!zsc || (std::is_same<T, float>::value && nfft_scaled_input_ok(P, W, bs)),
+                MLG_ERR_ARG, "scaled summation input needs the matrix-core spreading");
     switch (P.d) {
-        case 1: apply_d<T, 1>(P, W, bs, Zs, Fs, patch, grid, s, ev); break;
-        case 2: apply_d<T, 2>(P, W, bs, Zs, Fs, patch, grid, s, ev); break;
-        case 3: apply_d<T, 3>(P, W, bs, Zs, Fs, patch, grid, s, ev); break;
+        case 1: apply_d<T, 1>(P, W, bs, Zs, Fs, patch, grid, s, ev, zsc); break;
+        case 2: apply_d<T, 2>(P, W, bs, Zs, Fs, patch, grid, s, ev, zsc); break;
+        case 3: apply_d<T, 3>(P, W, bs, Zs, Fs, patch, grid, s, ev, zsc); break;
         default: throw Error(MLG_ERR_RANGE, "NFFT layers need d in 1..3");
     }
 }
 
+bool nfft_scaled_input_ok(const NfftPlan &P, const NfftWindow &W, int bs) {
+    return W.prec == 32 && bs % 16 == 0 && mfma_patch_ok(P.d, patch_side(P, W)) && P.ntasks > 0;
+}
+
+// ------------------------------------------------------------------------------
+// batched layers (see NfftBatch)
+// ------------------------------------------------------------------------------
+__global__ void k_offset_copy(int64_t cnt, const int *__restrict__ src, int add, int *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < cnt) dst[e] = src[e] + add;
+}
+
+static Geom layer_geom(const Layer &L, int bs) {
+    Geom g;
+    g.d = L.d;
+    g.nos = L.nf.nos;
+    g.B = L.nf.B;
+    g.nb = L.nf.nb;
+    g.w = L.win.w;
+    g.P = patch_side(L.nf, L.win);
+    g.PD = patch_cells(L.nf, L.win);
+    g.bs = bs;
+    g.n = L.nf.n;
+    g.perm = L.nf.perm.p;
+    g.zsc = nullptr;
+    return g;
+}
+
+bool nfft_batchable(const Layer &L, int bs, int *key) {
+    if (L.kp.method != MLG_METHOD_NFFT || L.kp.precision != 32 || L.win.prec != 32) return false;
+    if (bs % 16 != 0 || !L.win.csr || L.nf.ntasks <= 0) return false;
+    const int side = patch_side(L.nf, L.win);
+    if (!mfma_patch_ok(L.d, side)) return false;
+    // one interpolation task form per batch
+    const bool isch = L.nf.niseg > 0 && uses_spread_schedule(L.nf, L.win, bs);
+    *key = (L.d * 64 + side) * 2 + (isch ? 1 : 0);
+    return true;
+}
+
+template <class V>
+static std::vector<V> to_host(const DevBuf<V> &b, size_t cnt, hipStream_t s) {
+    std::vector<V> h(cnt);
+    if (cnt) MLG_HIP(hipMemcpyAsync(h.data(), b.p, sizeof(V) * cnt, hipMemcpyDeviceToHost, s));
+    return h;
+}
+
+void nfft_batch_build(NfftBatch &B, const std::vector<const Layer *> &layers,
+                      const std::vector<int> &ids, const float *X32,
+                      const std::vector<float *> &Fs, int bs, hipStream_t s) {
+    const int nl = (int)layers.size();
+    MLG_REQUIRE(nl >= 1, MLG_ERR_ARG, "empty batch");
+    // batch order: by N (equal N adjacent for the batched FFT), then layer id
+    std::vector<int> ord(nl);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return layers[a]->nf.N < layers[b]->nf.N; });
+    B = NfftBatch();
+    B.nl = nl;
+    B.bs = bs;
+    B.bg = bs < 2 ? 2 : bs;
+    B.D = layers[0]->d;
+    B.Pside = patch_side(layers[0]->nf, layers[0]->win);
+    const int PD = patch_cells(layers[0]->nf, layers[0]->win);
+    std::vector<LayerArgs> la(nl);
+    std::vector<int4> st, it, r1, r2;
+    std::vector<int> sl, il;
+    std::vector<int64_t> coff(nl + 1, 0), goff(nl, 0);
+    std::vector<int64_t> eoff(nl + 1, 0);   // entry offsets of the concatenated cell tables
+    int64_t slot_off = 0;
+    std::vector<int64_t> slots(nl);
+    bool any_isched = false, any_plain = false;
+    for (int i = 0; i < nl; ++i) {
+        const Layer &L = *layers[ord[i]];
+        const NfftPlan &P = L.nf;
+        MLG_REQUIRE(L.d == B.D && patch_side(P, L.win) == B.Pside, MLG_ERR_ARG, "mixed batch");
+        B.layers.push_back(ids[ord[i]]);
+        LayerArgs &a = la[i];
+        a.g = layer_geom(L, bs);
+        a.c32 = P.c32.p;
+        a.f32 = P.f32.p;
+        a.Zs = X32;
+        a.g.zsc = L.zsc.p;
+        a.Fs = Fs[ord[i]];
+        int64_t G = 1;
+        for (int t = 0; t < L.d; ++t) G *= P.nos;
+        a.beta = (float)L.win.beta;
+        const bool sched = uses_spread_schedule(P, L.win, bs);
+        const bool isch = P.niseg > 0 && sched;
+        any_isched |= isch;
+        any_plain |= !isch;
+        slots[i] = (int64_t)P.nruns + P.nscratch + (sched ? P.nsscr : 0);
+        MLG_REQUIRE(slot_off + slots[i] < ((int64_t)1 << 31) / std::max(PD, 1), MLG_ERR_RANGE,
+                    "batched patch slots exceed the index range");
+        const int so = (int)slot_off;
+        // spreading tasks and reduction lists, slots shifted
+        {
+            const int n = sched ? P.nseg : P.ntasks;
+            std::vector<int4> tk = to_host(sched ? P.seg : P.tasks, (size_t)n, s);
+            std::vector<int4> g1 = to_host(sched ? P.sred1 : P.red1, (size_t)(sched ? P.nsred1 : P.nred1), s);
+            std::vector<int4> g2 = to_host(sched ? P.sred2 : P.red2, (size_t)(sched ? P.nsred2 : P.nred2), s);
+            std::vector<int4> ik = to_host(isch ? P.iseg : P.tasks, (size_t)(isch ? P.niseg : P.ntasks), s);
+            MLG_HIP(hipStreamSynchronize(s));
+            for (int4 t : tk) {
+                t.w += so;
+                st.push_back(t);
+                sl.push_back(i);
+            }
+            for (int4 t : g1) {
+                t.x += so;
+                t.z += so;
+                r1.push_back(t);
+            }
+            for (int4 t : g2) {
+                t.x += so;
+                t.y += so;
+                r2.push_back(t);
+            }
+            for (const int4 &t : ik) {
+                it.push_back(t);
+                il.push_back(i);
+            }
+        }
+        slot_off += slots[i];
+        coff[i + 1] = coff[i] + G;
+        if (i + 1 < nl) goff[i + 1] = goff[i] + (int64_t)B.bg * G;
+        eoff[i + 1] = eoff[i] + (int64_t)L.win.cell_ent.n;
+    }
+    // the interpolation of a batch runs one task per workgroup when every
+    // layer has its own interpolation schedule, else 256-point tasks in two
+    // halves (the per-layer path's choice for each layer)
+    MLG_REQUIRE(!(any_isched && any_plain), MLG_ERR_ARG, "batch mixes interpolation task forms");
+    B.isplit = any_isched ? 1 : (B.D == 3 ? 2 : 1);
+    B.iper = any_isched ? (1 << 30) : kMaxTaskPoints / B.isplit;
+    MLG_REQUIRE(eoff[nl] < ((int64_t)1 << 31), MLG_ERR_RANGE, "batched cell tables too large");
+    B.nst = (int)st.size();
+    B.nit = (int)it.size();
+    B.nred1 = (int)r1.size();
+    B.nred2 = (int)r2.size();
+    B.ncell = coff[nl];
+    upload(B.stasks, st.data(), st.size(), false, s);
+    upload(B.slayer, sl.data(), sl.size(), false, s);
+    upload(B.itasks, it.data(), it.size(), false, s);
+    upload(B.ilayer, il.data(), il.size(), false, s);
+    upload(B.red1, r1.data(), r1.size(), false, s);
+    upload(B.red2, r2.data(), r2.size(), false, s);
+    upload(B.coff, coff.data(), coff.size(), false, s);
+    upload(B.goff, goff.data(), goff.size(), false, s);
+    B.goff_h = goff;
+    // concatenated cell tables: pointers shifted by the entries before the
+    // layer, entries by its first patch slot
+    B.cptr.alloc((size_t)B.ncell + 1);
+    B.cent.alloc((size_t)std::max<int64_t>(eoff[nl], 1));
+    slot_off = 0;
+    for (int i = 0; i < nl; ++i) {
+        const Layer &L = *layers[ord[i]];
+        const int64_t G = coff[i + 1] - coff[i];
+        const int64_t cnt = i + 1 < nl ? G : G + 1;   // the last layer's end pointer too
+        hipLaunchKernelGGL(k_offset_copy, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, cnt,
+                           L.win.cell_ptr.p, (int)eoff[i], B.cptr.p + coff[i]);
+        MLG_LAUNCH_CHECK();
+        const int64_t ne = (int64_t)L.win.cell_ent.n;
+        if (ne > 0) {
+            hipLaunchKernelGGL(k_offset_copy, dim3(ceil_div(ne, 256)), dim3(256), 0, s, ne,
+                               L.win.cell_ent.p, (int)(slot_off * PD), B.cent.p + eoff[i]);
+            MLG_LAUNCH_CHECK();
+        }
+        slot_off += slots[i];
+    }
+    // groups of equal N for the FFT, their multipliers one after another
+    for (int i = 0; i < nl;) {
+        int j = i + 1;
+        while (j < nl && layers[ord[j]]->nf.N == layers[ord[i]]->nf.N) ++j;
+        NfftBatch::Sub sb;
+        sb.first = i;
+        sb.count = j - i;
+        sb.plan = &layers[ord[i]]->nf;
+        const int64_t G = coff[i + 1] - coff[i];
+        sb.mstr = G;
+        sb.M.alloc((size_t)G * sb.count);
+        for (int k = i; k < j; ++k)
+            MLG_HIP(hipMemcpyAsync(sb.M.p + (size_t)(k - i) * G, layers[ord[k]]->win.M32.p,
+                                   sizeof(float) * G, hipMemcpyDeviceToDevice, s));
+        B.subs.push_back(std::move(sb));
+        i = j;
+    }
+    B.patch_elems = (size_t)slot_off * PD * bs;
+    B.grid_elems = (size_t)B.bg * coff[nl];
+    B.patch.alloc(B.patch_elems);
+    B.grid.alloc(B.grid_elems);
+    for (int i = 0; i < nl; ++i) la[i].grid = B.grid.p + goff[i];   // the interpolation's input
+    B.args.alloc(sizeof(LayerArgs) * nl);
+    MLG_HIP(hipMemcpyAsync(B.args.p, la.data(), sizeof(LayerArgs) * nl, hipMemcpyHostToDevice, s));
+    // products without D^-1/2 (the weight matrix itself): no factor
+    for (int i = 0; i < nl; ++i) la[i].g.zsc = nullptr;
+    B.args_n.alloc(sizeof(LayerArgs) * nl);
+    MLG_HIP(hipMemcpyAsync(B.args_n.p, la.data(), sizeof(LayerArgs) * nl, hipMemcpyHostToDevice, s));
+    MLG_HIP(hipStreamSynchronize(s));
+    // the argument table is read by every batched launch; nothing above is
+    // needed on the host afterwards
+}
+
+void nfft_batch_apply(const NfftBatch &B, int use_dinv, hipStream_t s) {
+    const int bs = B.bs, bg = B.bg, D = B.D;
+    const LayerArgs *la = reinterpret_cast<const LayerArgs *>(use_dinv ? B.args.p : B.args_n.p);
+    const int PD = [&] {
+        int pd = 1;
+        for (int t = 0; t < D; ++t) pd *= B.Pside;
+        return pd;
+    }();
+    Geom g0{};
+    g0.bs = bs;
+    float *patch = B.patch.p, *grid = B.grid.p;
+    // spreading
+    if (B.nst > 0) {
+#define SPREADB_CALL(DD, PP)                                                                      \
+    if constexpr (DD == 3)                                                                        \
+        hipLaunchKernelGGL((k_spread_mfma3<PP>), dim3(B.nst, bs / 16), dim3(64), 0, s, g0, B.stasks.p, \
+                           nullptr, nullptr, nullptr, 0.0f, patch, la, B.slayer.p);              \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_spread_mfma<DD, PP>), dim3(B.nst, bs / 16), dim3(64), 0, s, g0, B.stasks.p, \
+                           nullptr, nullptr, nullptr, 0.0f, patch, la, B.slayer.p)
+        switch (D) {
+            case 1: MLG_P_SWITCH(1, B.Pside, SPREADB_CALL); break;
+            case 2: MLG_P_SWITCH(2, B.Pside, SPREADB_CALL); break;
+            case 3: MLG_P_SWITCH(3, B.Pside, SPREADB_CALL); break;
+            default: throw Error(MLG_ERR_ARG, "bad batch dimension");
+        }
+#undef SPREADB_CALL
+        MLG_LAUNCH_CHECK();
+    }
+    // split-bin reductions
+    const int64_t elems = (int64_t)PD * bs;
+    if (B.nred1 > 0) {
+        hipLaunchKernelGGL(k_reduce1<float>, dim3(B.nred1, ceil_div(elems, 256)), dim3(256), 0, s, elems,
+                           B.red1.p, patch);
+        MLG_LAUNCH_CHECK();
+    }
+    if (B.nred2 > 0) {
+        hipLaunchKernelGGL(k_reduce2<float>, dim3(B.nred2, ceil_div(elems, 256)), dim3(256), 0, s, elems,
+                           B.red2.p, patch);
+        MLG_LAUNCH_CHECK();
+    }
+    // cell-table gather over every layer's grid
+    const int vgat = std::min(bs, 4);
+#define GATHERB_CALL(V)                                                                           \
+    hipLaunchKernelGGL((k_gather_csr<float, V>), dim3(ceil_div(B.ncell, 256), bs / V), dim3(256), 0, s, \
+                       (int64_t)0, bs, bg, B.cptr.p, B.cent.p, patch, grid, B.nl, B.coff.p, B.goff.p)
+    MLG_VPL_SWITCH(vgat, GATHERB_CALL)
+#undef GATHERB_CALL
+    MLG_LAUNCH_CHECK();
+    // FFT, multiply, inverse FFT: one call per group of equal N (their grids
+    // are adjacent, bg / 2 planes each)
+    for (const NfftBatch::Sub &sb : B.subs)
+        fft_convolve<float>(*sb.plan, bg, reinterpret_cast<float2 *>(grid + B.goff_h[sb.first]), sb.M.p, s,
+                            sb.count, sb.mstr);
+    // interpolation
+    if (B.nit > 0) {
+#define INTERPB_CALL(DD, PP)                                                                      \
+    if constexpr (DD == 3)                                                                        \
+        hipLaunchKernelGGL((k_interp_mfma3<PP>), dim3(B.nit * B.isplit, bs / 16), dim3(64), 0, s, g0, \
+                           B.itasks.p, nullptr, nullptr, nullptr, bg, 0.0f, nullptr, B.isplit, B.iper, \
+                           la, B.ilayer.p);                                                       \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_interp_mfma<DD, PP>), dim3(B.nit, bs / 16), dim3(64), 0, s, g0, B.itasks.p, \
+                           nullptr, nullptr, nullptr, bg, 0.0f, nullptr, la, B.ilayer.p)
+        switch (D) {
+            case 1: MLG_P_SWITCH(1, B.Pside, INTERPB_CALL); break;
+            case 2: MLG_P_SWITCH(2, B.Pside, INTERPB_CALL); break;
+            case 3: MLG_P_SWITCH(3, B.Pside, INTERPB_CALL); break;
+            default: throw Error(MLG_ERR_ARG, "bad batch dimension");
+        }
+#undef INTERPB_CALL
+        MLG_LAUNCH_CHECK();
+    }
+}
+
 template void nfft_apply<float>(const NfftPlan &, const NfftWindow &, int, const float *, float *,
-                                float *, float *, hipStream_t, hipEvent_t *);
+                                float *, float *, hipStream_t, hipEvent_t *, const float *);
 template void nfft_apply<double>(const NfftPlan &, const NfftWindow &, int, const double *,
-                                 double *, double *, double *, hipStream_t, hipEvent_t *);
+                                 double *, double *, double *, hipStream_t, hipEvent_t *,
+                                 const float *);
 
 }  // namespace mlg

@@ -90,7 +90,7 @@ static void run(int64_t n, int d, int kernel, double sigma, int b, const double 
     v.dinv = nullptr;
     v.K0 = 0.0;
     v.is64 = sizeof(T) == 8;
-    v.pad = 0;
+    v.shared = 0;
     hipLaunchKernelGGL(k_set_layerio, dim3(1), dim3(1), 0, s, io, v);
     MLG_LAUNCH_CHECK();
     direct_coords_into(n, d, points, sigma, kernel, mid, x64, x32, s);

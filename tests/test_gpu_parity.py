@@ -305,3 +305,38 @@ def test_nfft_fp32_heavy_bin_two_level_reduction(mlg):
     assert rel_err(Y, oracle.kernel_matvec(pts, 0.3, X)) <= 1e-4
     Y64 = mlg.kernel_matvec(pts, 0.3, X[:, :2], mlg.kparams("nfft", 64, N=64, window=12))
     assert rel_err(Y64, oracle.kernel_matvec(pts, 0.3, X[:, :2])) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# batched layers: more FP32 matrix-core layers of one dimension and patch
+# edge than branches run as one launch per stage (uneven N grouped for the
+# FFT)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("b", [16, 32])
+def test_batched_layers_against_oracle_and_per_layer_path(mlg, b):
+    n = 5000
+    p2 = [gen.uniform_ball(n, 2, 1.0, 961 + t) for t in range(4)]
+    p3 = [gen.gaussian_mixture(n, 3, 3, 0.08, 971 + t)[0] for t in range(4)]
+    pts = p2[:2] + p3[:2] + p2[2:] + p3[2:]
+    sig = [0.35, 0.5, 0.2, 0.22, 0.45, 0.3, 0.25, 0.18]
+    Ns = [32, 64, 32, 64, 128, 32, 32, 32]
+    kp = [mlg.kparams("nfft", 32, N=N, window=6) for N in Ns]
+    g = mlg.Graph(pts, sig, kp)
+    import torch
+    X = gen.test_vectors(n, b, 981)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to("cuda")
+    case_id("batched layers n=%d T=8 (d=2 x4, d=3 x4) b=%d" % (n, b))
+    Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, Xd).cpu().numpy()
+    ref = oracle.lsym_matvec([oracle.Layer(q, s) for q, s in zip(pts, sig)], X)
+    assert rel_err(Y, ref) <= 1e-4
+    # the stage-profiled product walks the layers one by one without batches:
+    # the same bits
+    _, Yseq = g.profile_stages(-1, mlg.MLG_OP_LSYM, Xd, reps=1, return_y=True)
+    assert np.array_equal(Y, Yseq.cpu().numpy())
+    # and the layer mean equals the mean of the one-layer products
+    acc = 0
+    for t in range(len(pts)):
+        acc = acc + g.laplacian_matvec(t, mlg.MLG_OP_NADJ, Xd).cpu().numpy()
+    Y1 = g.laplacian_matvec(-1, mlg.MLG_OP_NADJ, Xd).cpu().numpy()
+    np.testing.assert_allclose(Y1, acc / len(pts), atol=1e-12 * np.abs(Y1).max())
+    g.close()
