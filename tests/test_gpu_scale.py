@@ -101,6 +101,16 @@ def test_ball_lanczos_fp64_residuals(mlg, ball):
     phi0 = np.sqrt(L.deg) / np.linalg.norm(np.sqrt(L.deg))
     assert abs(lam[0]) <= 1e-9
     assert abs(abs(phi0 @ V[:, 0]) - 1.0) <= 1e-8
+    # the 20 eigenvalues against the oracle's (stored: ARPACK on the FP64
+    # direct sum, tests/golden/make_golden.py), the FP64-path gate
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "ball_n100000_eigs.json")))
+    assert gold["n"] == n and gold["sigma"] == sig and gold["k"] == k
+    err = np.abs(lam - np.asarray(gold["eigenvalues"])).max()
+    case_id("  eigenvalue error vs oracle %.2e" % err)
+    assert err <= 1e-8
     g.close()
 
 

@@ -536,3 +536,18 @@ def test_laplacian_kernel_series_decays_algebraically():
     assert g64 < 1e-10                       # the Gaussian: spectral accuracy
     assert l64 > 1e-4                        # the Laplacian RBF misses even the FP32 gate
     assert 2.0 < l32 / l64 < 12.0            # and gains only a small factor per doubling of N
+
+
+def test_stored_ball_eigenvalues_recipe():
+    """The stored oracle eigenvalues of the 10^5-point ball belong to the
+    workload recipe (n, sigma, k), are ascending in [0, 2) and start at the
+    zero eigenvalue of L_sym (eigenvector D^1/2 1)."""
+    import json
+    import os
+    z = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "ball_n100000_eigs.json")))
+    c = gen.config2()
+    assert z["n"] == c["n"] and z["sigma"] == c["sigma"][0] and z["k"] == c["k"]
+    lam = np.asarray(z["eigenvalues"])
+    assert lam.shape == (c["k"],) and np.all(np.diff(lam) >= 0)
+    assert abs(lam[0]) < 1e-12 and lam[-1] < 2.0
