@@ -33,6 +33,10 @@ Pieces (each cites the passage it follows):
   f(lambda) = (lambda + delta)^p (Higham, Functions of Matrices, ch. 13).
 * ``allen_cahn`` / ``simplex_project`` / ``potential_grad`` -- Algorithm 2
   steps 2-4 in a fixed FP64 operation order (see ``ac.c``).
+* ``oracle.fourier`` -- the trigonometric sum W_RF X that Algorithm 1
+  evaluates fast (Sec. 4: regularised kernel, Fourier coefficients b_l,
+  f_RF through explicit non-equispaced Fourier matrices), so that the fast
+  summation's window error can be measured apart from the truncation error.
 """
 from __future__ import annotations
 
