@@ -384,6 +384,18 @@ struct LayerArgs {
     float beta;
 };
 
+// The arrays the matrix-core kernels read come either from their arguments or
+// from a LayerArgs entry in device memory; a pointer loaded from memory has no
+// known address space, and its loads compile to flat instructions.  Flat loads
+// count against the LDS wait counter too, so every LDS wait in the matrix loop
+// would also wait for the next chunk's prefetched rows.  Every such pointer
+// addresses global memory; typing it so gives global loads and stores.
+#define MLG_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MLG_GLOBAL T *to_global(T *p) {
+    return (MLG_GLOBAL T *)p;
+}
+
 // (cell, fractional offset) of point p along dimension t.
 template <class T>
 __device__ inline void point_coord(const double *u64, const int *c32, const float *f32,
@@ -787,6 +799,12 @@ __global__ __launch_bounds__(256) void k_gather(Geom g, int SB, int nsb,
 // ------------------------------------------------------------------------------
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Four consecutive floats (16-byte aligned) of global memory.
+__device__ __forceinline__ float4 load_row4(const MLG_GLOBAL float *p) {
+    const floatx4 v = *reinterpret_cast<const MLG_GLOBAL floatx4 *>(p);
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 template <int D, int P>
 struct MfShape {
     static constexpr int PD = D == 3 ? P * P * P : (D == 2 ? P * P : P);
@@ -806,9 +824,8 @@ struct PtIn {
     float frac[D];
 };
 
-template <int D>
-__device__ inline void fetch_point(const int *__restrict__ c32, const float *__restrict__ f32,
-                                   int64_t n, int64_t p, bool ok, PtIn<D> &pi) {
+template <int D, class IP, class FP>
+__device__ inline void fetch_point(IP c32, FP f32, int64_t n, int64_t p, bool ok, PtIn<D> &pi) {
 #pragma unroll
     for (int t = 0; t < D; ++t) {
         pi.cell[t] = ok ? c32[(int64_t)t * n + p] : 0;
@@ -880,9 +897,11 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g_, const int4 *__restr
                                                     const int *__restrict__ tlayer) {
     const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x] : nullptr;
     const Geom g = lp ? lp->g : g_;
-    const int *__restrict__ c32 = lp ? lp->c32 : c32_;
-    const float *__restrict__ f32 = lp ? lp->f32 : f32_;
-    const float *__restrict__ Zs = lp ? lp->Zs : Zs_;
+    const MLG_GLOBAL int *__restrict__ c32 = to_global(lp ? lp->c32 : c32_);
+    const MLG_GLOBAL float *__restrict__ f32 = to_global(lp ? lp->f32 : f32_);
+    const MLG_GLOBAL float *__restrict__ Zs = to_global(lp ? lp->Zs : Zs_);
+    const MLG_GLOBAL int *__restrict__ perm = to_global(g.perm);
+    const MLG_GLOBAL float *__restrict__ zsc = to_global(g.zsc);
     const float beta = lp ? lp->beta : beta_;
     using S = MfShape<D, P>;
     constexpr int NT = S::NT, WSP = S::WSP;
@@ -926,12 +945,12 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g_, const int4 *__restr
         const bool ok = lane < tk.z;
         const int64_t p = (int64_t)tk.y + lane;
         fetch_point<D>(c32, f32, g.n, p, ok, pin);
-        const int row = ok ? g.perm[p] : 0;
+        const int row = ok ? perm[p] : 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
-        zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
-        rown = lane + 64 < tk.z ? g.perm[(int64_t)tk.y + 64 + lane] : 0;
+            zin[j] = ok ? load_row4(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        zf = (ok && zsc) ? zsc[p] : 1.0f;
+        rown = lane + 64 < tk.z ? perm[(int64_t)tk.y + 64 + lane] : 0;
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
@@ -950,9 +969,9 @@ __global__ __launch_bounds__(64) void k_spread_mfma(Geom g_, const int4 *__restr
             const int row = rown;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
-            zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
-            rown = lane + 64 < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
+                zin[j] = ok ? load_row4(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+            zf = (ok && zsc) ? zsc[p] : 1.0f;
+            rown = lane + 64 < tk.z - c1 ? perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
         }
 #pragma unroll
         for (int gi = 0; gi < 16; ++gi) {
@@ -988,7 +1007,7 @@ template <int D, int P, int NQ>
 __device__ inline void interp_chunk(const float *__restrict__ wts, const int (&qa)[MfShape<D, P>::S4],
                                     const int (&qb)[MfShape<D, P>::S4], int li, int lk,
                                     const float *hb, int cnt, const int *wperm, int bs, int v0,
-                                    float *__restrict__ Fs) {
+                                    MLG_GLOBAL float *__restrict__ Fs) {
     using S = MfShape<D, P>;
     constexpr int WSP = S::WSP;
     constexpr int KSV = (S::PD + 3) / 4;
@@ -1029,11 +1048,12 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g_, const int4 *__restr
                                                     const int *__restrict__ tlayer) {
     const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x] : nullptr;
     const Geom g = lp ? lp->g : g_;
-    const int *__restrict__ c32 = lp ? lp->c32 : c32_;
-    const float *__restrict__ f32 = lp ? lp->f32 : f32_;
-    const float *__restrict__ grid = lp ? lp->grid : grid_;
+    const MLG_GLOBAL int *__restrict__ c32 = to_global(lp ? lp->c32 : c32_);
+    const MLG_GLOBAL float *__restrict__ f32 = to_global(lp ? lp->f32 : f32_);
+    const MLG_GLOBAL float *__restrict__ grid = to_global(lp ? lp->grid : grid_);
+    const MLG_GLOBAL int *__restrict__ perm = to_global(g.perm);
     const float beta = lp ? lp->beta : beta_;
-    float *__restrict__ Fs = lp ? lp->Fs : Fs_;
+    MLG_GLOBAL float *__restrict__ Fs = to_global(lp ? lp->Fs : Fs_);
     using S = MfShape<D, P>;
     constexpr int WSP = S::WSP;
     constexpr int KSV = (S::PD + 3) / 4;
@@ -1052,7 +1072,7 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g_, const int4 *__restr
     __shared__ int wperm[64];
     PtIn<D> pin;
     fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + lane, lane < tk.z, pin);
-    int prow = lane < tk.z ? g.perm[(int64_t)tk.y + lane] : 0;
+    int prow = lane < tk.z ? perm[(int64_t)tk.y + lane] : 0;
     // B fragments: the task's patch of the grid, cell 4s + lk, vector li
     float hb[KSV];
 #pragma unroll
@@ -1086,7 +1106,7 @@ __global__ __launch_bounds__(64) void k_interp_mfma(Geom g_, const int4 *__restr
         const int c1 = c0 + 64;
         if (c1 < tk.z) {
             fetch_point<D>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
-            prow = lane < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + lane] : 0;
+            prow = lane < tk.z - c1 ? perm[(int64_t)tk.y + c1 + lane] : 0;
         }
         interp_chunk<D, P, 4>(wts, qa, qb, li, lk, hb, cnt, wperm, bs, v0, Fs);
     }
@@ -1139,14 +1159,16 @@ struct SpreadTiles3 {
 // One task (points of one bin) of the d = 3 matrix-core spreading, written to
 // its patch slot tk.w.  LDS: wxy (64 RS), wzs (64 x 8), zv (64 x 16).
 template <int P>
-__device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
-                                             const int *__restrict__ c32,
-                                             const float *__restrict__ f32,
-                                             const float *__restrict__ Zs, float beta,
+__device__ __forceinline__ void spread3_task(const Geom g, const int4 tk,
+                                             const MLG_GLOBAL int *__restrict__ c32,
+                                             const MLG_GLOBAL float *__restrict__ f32,
+                                             const MLG_GLOBAL float *__restrict__ Zs, float beta,
                                              float *__restrict__ patch, float *wxy, float *wzs,
                                              float *zv) {
     using S = MfShape3<P>;
     using U = SpreadTiles3<P>;
+    const MLG_GLOBAL int *__restrict__ perm = to_global(g.perm);
+    const MLG_GLOBAL float *__restrict__ zsc = to_global(g.zsc);
     constexpr int RS = S::RS, C2 = S::C2, TF = U::TF, RR = U::RR, TR = U::TR;
     const int bs = g.bs;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
@@ -1183,12 +1205,12 @@ __device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
         const bool ok = lane < tk.z;
         const int64_t p = (int64_t)tk.y + lane;
         fetch_point<3>(c32, f32, g.n, p, ok, pin);
-        const int row = ok ? g.perm[p] : 0;
+        const int row = ok ? perm[p] : 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
-        zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
-        rown = lane + 64 < tk.z ? g.perm[(int64_t)tk.y + 64 + lane] : 0;
+            zin[j] = ok ? load_row4(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+        zf = (ok && zsc) ? zsc[p] : 1.0f;
+        rown = lane + 64 < tk.z ? perm[(int64_t)tk.y + 64 + lane] : 0;
     }
     for (int c0 = 0; c0 < tk.z; c0 += 64) {
         const int cnt = (tk.z - c0) < 64 ? (tk.z - c0) : 64;
@@ -1226,9 +1248,9 @@ __device__ __forceinline__ void spread3_task(const Geom &g, const int4 tk,
             const int row = rown;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                zin[j] = ok ? *reinterpret_cast<const float4 *>(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
-            zf = (ok && g.zsc) ? g.zsc[p] : 1.0f;
-            rown = lane + 64 < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
+                zin[j] = ok ? load_row4(Zs + (int64_t)row * bs + v0 + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+            zf = (ok && zsc) ? zsc[p] : 1.0f;
+            rown = lane + 64 < tk.z - c1 ? perm[(int64_t)tk.y + c1 + 64 + lane] : 0;
         }
         // all 16 groups in one straight-line block (absent points carry zero
         // records); the operands of group gi + 1 are read from LDS before the
@@ -1318,8 +1340,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     __shared__ __attribute__((aligned(16))) float wzs[64 * 8];
     __shared__ __attribute__((aligned(16))) float zv[64 * 16];
     const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x] : nullptr;
-    spread3_task<P>(lp ? lp->g : g, tasks[blockIdx.x], lp ? lp->c32 : c32, lp ? lp->f32 : f32,
-                    lp ? lp->Zs : Zs, lp ? lp->beta : beta, patch, wxy, wzs, zv);
+    const Geom gl = lp ? lp->g : g;
+    spread3_task<P>(gl, tasks[blockIdx.x], to_global(lp ? lp->c32 : c32),
+                    to_global(lp ? lp->f32 : f32), to_global(lp ? lp->Zs : Zs),
+                    lp ? lp->beta : beta, patch, wxy, wzs, zv);
 }
 
 template <int P>
@@ -1332,11 +1356,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                                                      const int *__restrict__ tlayer) {
     const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x / split] : nullptr;
     const Geom g = lp ? lp->g : g_;
-    const int *__restrict__ c32 = lp ? lp->c32 : c32_;
-    const float *__restrict__ f32 = lp ? lp->f32 : f32_;
-    const float *__restrict__ grid = lp ? lp->grid : grid_;
+    const MLG_GLOBAL int *__restrict__ c32 = to_global(lp ? lp->c32 : c32_);
+    const MLG_GLOBAL float *__restrict__ f32 = to_global(lp ? lp->f32 : f32_);
+    const MLG_GLOBAL float *__restrict__ grid = to_global(lp ? lp->grid : grid_);
+    const MLG_GLOBAL int *__restrict__ perm = to_global(g.perm);
     const float beta = lp ? lp->beta : beta_;
-    float *__restrict__ Fs = lp ? lp->Fs : Fs_;
+    MLG_GLOBAL float *__restrict__ Fs = to_global(lp ? lp->Fs : Fs_);
     using S = MfShape3<P>;
     constexpr int KS2 = S::KS2, ES = S::ES, NE = S::NE, C2 = S::C2;
     // entry-major weights: entry e of point p at wt[e * ES + p]; entries
@@ -1364,7 +1389,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     __shared__ int wperm[64];
     PtIn<3> pin;
     fetch_point<3>(c32, f32, g.n, (int64_t)tk.y + lane, lane < tk.z, pin);
-    int prow = lane < tk.z ? g.perm[(int64_t)tk.y + lane] : 0;
+    int prow = lane < tk.z ? perm[(int64_t)tk.y + lane] : 0;
     // B fragments: grid at (cx, cy) = 4s + lk, cz, vector li.  Addresses:
     // the lane's vector plane (grid_index layout) plus twice the cell index,
     // cell = task origin + cx + cy nos + cz nos^2 with (cx, cy) stepped
@@ -1373,13 +1398,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     {
         const int64_t nos = g.nos, nos2 = nos * nos;
         const int v = v0 + li;
-        const float *gl = grid + 2 * ((int64_t)(v >> 1) * G) + (v & 1) +
+        const MLG_GLOBAL float *gl = grid + 2 * ((int64_t)(v >> 1) * G) + (v & 1) +
                           2 * ((int64_t)org[0] + org[1] * nos + org[2] * nos2);
         int cx = lk, cy = 0;
 #pragma unroll
         for (int s = 0; s < KS2; ++s) {
             const bool ok = 4 * s + lk < C2;
-            const float *ps = gl + 2 * ((int64_t)cx + cy * nos);
+            const MLG_GLOBAL float *ps = gl + 2 * ((int64_t)cx + cy * nos);
 #pragma unroll
             for (int cz = 0; cz < P; ++cz) hb[cz][s] = ok ? ps[2 * cz * nos2] : 0.0f;
             cx += 4;
@@ -1408,7 +1433,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         const int c1 = c0 + 64;
         if (c1 < tk.z) {
             fetch_point<3>(c32, f32, g.n, (int64_t)tk.y + c1 + lane, lane < tk.z - c1, pin);
-            prow = lane < tk.z - c1 ? g.perm[(int64_t)tk.y + c1 + lane] : 0;
+            prow = lane < tk.z - c1 ? perm[(int64_t)tk.y + c1 + lane] : 0;
         }
         // four point groups of 16 in one straight-line block (absent points
         // carry zero weights and are not stored)
