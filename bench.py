@@ -585,7 +585,7 @@ def main():
     cpu = None
     if not a.no_cpu:
         import oracle
-        nrow = 1024
+        nrow = 4096
         rows = np.sort(gen.rng(c["base_seed"] + 400).choice(n, size=nrow, replace=False))
         Xh = X.cpu().numpy()
         errs, derrs, t_cpu, work = [], [], 0.0, 0

@@ -342,7 +342,8 @@ typedef struct {
  *   automatic bandwidth of mlg_graph_create with N = 0) and w in {4, 6, 8, 10}
  *   (FP32) or {4, 6, ..., 16} (FP64), bin in {1, 2, 4}, eps_B = 1/16,
  *   p_reg = 5.  For each (N, bin) the windows are tried in increasing order
- *   and the first within the budget is timed (5 products after one warm-up);
+ *   and the first within the budget is timed (the fastest of three rounds
+ *   of 5 products, after one warm-up);
  *   a later candidate (larger N or bin) replaces the current choice only if
  *   it is at least 5 % faster.
  *   Larger bins trade the matrix-core kernels (d = 3 needs bin + w - 1 <= 6)
