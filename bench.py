@@ -603,9 +603,19 @@ def main():
         acc.update({"W_rows": nrow, "max_rel_err_W_rows": max(errs),
                     "max_rowwise_rel_err_degrees": max(derrs)})
         model, threads, avail = host_cpu()
+        # context: the oracle's dense eigensolver on the 2000-point mixture
+        # (10 smallest eigenpairs of L_sym by LAPACK eigh on the assembled
+        # matrix); the 10^5-point ball's 20 eigenvalues by ARPACK on the
+        # direct sum took 3037 s on 8 host cores when the stored values were
+        # written (tests/golden/ball_n100000_eigs.json)
+        c1 = gen.config1()
+        t1 = time.perf_counter()
+        oracle.eigs_dense([oracle.Layer(c1["layers"][0], c1["sigma"][0])], c1["k"])
+        t_eig = time.perf_counter() - t1
         cpu = {"value": work / t_cpu, "unit": UNIT, "cores": threads, "kind": "oracle",
                "cpu_model": model, "host_cpus_available": avail,
                "seconds": round(t_cpu, 2),
+               "eigs_dense_n2000_k10_s": round(t_eig, 3),
                "sample": "%d sampled rows x all %d columns x %d layers x %d vectors of W_t X "
                          "(FP64 direct sum with compensated summation, OpenMP over rows)"
                          % (nrow, n, T, b)}

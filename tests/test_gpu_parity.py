@@ -154,6 +154,28 @@ def test_nfft_fp64_lsym_dims(mlg, d):
     assert rel_err(Y, oracle.lsym_matvec([L], X)) <= 1e-6
 
 
+@pytest.mark.parametrize("d,N,prec,window,gate", [(3, 128, 32, 6, 1e-4), (3, 128, 64, 12, 1e-6),
+                                                    (2, 256, 32, 6, 1e-4), (2, 256, 64, 12, 1e-6),
+                                                    (1, 256, 64, 12, 1e-6)])
+def test_nfft_large_bandwidth_elementwise(mlg, d, N, prec, window, gate):
+    """Bandwidths of 128 and 256 (grids of 256^3 and 512^2 cells), with a
+    kernel narrow enough to need them: every row of W X and of L_sym X
+    against the oracle."""
+    n = 4000
+    pts = gen.uniform_ball(n, d, 1.0, 70 + d)
+    sig = 0.14 if N == 128 else 0.07
+    X = gen.test_vectors(n, 4, 75 + d)
+    case_id("nfft fp%d d=%d N=%d w=%d n=%d b=4" % (prec, d, N, window, n))
+    g = mlg.Graph([pts], [sig], mlg.kparams("nfft", prec, N=N, window=window))
+    assert g.layer_info(0)["N"] == N
+    L = oracle.Layer(pts, sig)
+    Yw = g.laplacian_matvec(0, mlg.MLG_OP_W, X)
+    assert rel_err(Yw, oracle.kernel_matvec(pts, sig, X)) <= gate
+    Y = g.laplacian_matvec(0, mlg.MLG_OP_LSYM, X)
+    assert rel_err(Y, oracle.lsym_matvec([L], X)) <= gate
+    g.close()
+
+
 @pytest.mark.parametrize("b", [1, 5, 16])
 def test_nfft_fp32_multilayer_mean(mlg, b):
     n = 4099
