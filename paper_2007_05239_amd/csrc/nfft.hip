@@ -811,7 +811,11 @@ struct MfShape {
     static constexpr int NT = (PD + 15) / 16;                    // 16-cell tiles
     static constexpr int OB = D == 3 ? 3 * P : P;                 // second factor: wyz (D=3) or wy
     static constexpr int ZS = D == 3 ? 3 * P + P * P : D * P;     // zero slot
-    static constexpr int WSP = (ZS + 1 + 3) / 4 * 4;             // record stride (floats)
+    // record stride (floats): a multiple of 4 (float4 stores) with an odd
+    // quotient, so that the 16 records one read instruction touches start in
+    // 16 different 4-bank groups
+    static constexpr int WSP4 = (ZS + 1 + 3) / 4 * 4;
+    static constexpr int WSP = (WSP4 / 4) % 2 == 1 ? WSP4 : WSP4 + 4;
     static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
     static constexpr int S16 = P / gcd(P, 16);   // period in tiles of (16t + li) mod P
     static constexpr int S4 = P / gcd(P, 4);     // period in steps of (4s + lk) mod P
