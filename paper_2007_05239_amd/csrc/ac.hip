@@ -406,8 +406,7 @@ __global__ __launch_bounds__(256) void k_ac_iter(int64_t n, int k, int m_rt,
     // the dispatch passes M = m for m <= kAcFastM: fold the class count
     const int m = (M <= kAcFastM) ? M : m_rt;
     extern __shared__ double lds[];
-    double *Vs = lds;                        // k x m
-    double *Rs = Vs + k * m;                 // 256 x m
+    double *Rs = lds;                        // 256 x m
     __shared__ double red[2][4];
     const int64_t ch = blockIdx.x;
     const int64_t i0 = ch * kAcChunk;
@@ -416,9 +415,6 @@ __global__ __launch_bounds__(256) void k_ac_iter(int64_t n, int k, int m_rt,
     const int64_t i = i0 + ii;
     const bool live = ii < cnt;
     const double *P = Pc + ch * (int64_t)k * kAcChunk;
-    if (!FIRST)
-        for (int e = threadIdx.x; e < k * m; e += blockDim.x) Vs[e] = V[e];
-    __syncthreads();
     double dn = 0.0, nn = 0.0;
     if (live) {
         double u[M];
@@ -430,12 +426,14 @@ __global__ __launch_bounds__(256) void k_ac_iter(int64_t n, int k, int m_rt,
 #pragma unroll
             for (int j = 0; j < M; ++j) ut[j] = 0.0;
 #pragma unroll 8
+            // V is the same for every thread: its entries come through the
+            // scalar cache (uniform addresses), not LDS
             for (int r = 0; r < k; ++r) {
                 const double ph = P[(int64_t)r * kAcChunk + ii];
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
                     if (j < m) {
-                        const double pr = ph * Vs[r * m + j];
+                        const double pr = ph * V[r * m + j];
                         ut[j] = ut[j] + pr;
                     }
                 }
@@ -505,7 +503,8 @@ __global__ __launch_bounds__(256) void k_ac_iter(int64_t n, int k, int m_rt,
     }
 
 static size_t ac_fused_lds(int k, int m) {
-    return (size_t)((int64_t)k * m + (int64_t)kAcChunk * m) * sizeof(double);
+    (void)k;
+    return (size_t)((int64_t)kAcChunk * m) * sizeof(double);
 }
 
 // Fused steps on chunk-major copies of the eigenvectors and of Z: each step
