@@ -171,6 +171,59 @@ __global__ void k_ac_tree(int64_t cnt, int len, const double *__restrict__ src,
         dst[e] = src[(cnt - 1) * len + x];
 }
 
+// Four levels of the same tree in one pass: dst[j] is node j four levels
+// above src (cnt nodes), formed from its up to 16 leaves with exactly the
+// pairs and odd-element copies of four one-level passes.
+__global__ void k_ac_tree4(int64_t cnt, int len, const double *__restrict__ src,
+                           double *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t c[5];
+    c[0] = cnt;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) c[l + 1] = c[l] / 2 + (c[l] & 1);
+    if (e >= c[4] * len) return;
+    const int64_t j = e / len;
+    const int x = (int)(e - j * len);
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t g = j * 16 + q;
+        v[q] = g < cnt ? src[g * len + x] : 0.0;
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int w = 8 >> l;  // nodes of level l + 1 under node j
+#pragma unroll
+        for (int i = 0; i < w; ++i) {
+            // node j * w + i of level l + 1 has children 2 (j w + i) and that + 1;
+            // one past the level's end is a copy, further ones are never read
+            const int64_t g = j * w + i;
+            v[i] = 2 * g + 1 < c[l] ? v[2 * i] + v[2 * i + 1] : v[2 * i];
+        }
+    }
+    dst[e] = v[0];
+}
+
+// Reduce cnt rows of len doubles at src to one by the pairwise tree, using dst
+// as the other buffer; returns the buffer that holds the result.
+static double *ac_tree_reduce(int64_t cnt, int len, double *src, double *dst, hipStream_t s) {
+    while (cnt > 1) {
+        int64_t outc = cnt / 2 + (cnt & 1);
+        if (cnt >= 16) {
+            for (int l = 1; l < 4; ++l) outc = outc / 2 + (outc & 1);
+            hipLaunchKernelGGL(k_ac_tree4, dim3(ceil_div(outc * len, 256)), dim3(256), 0, s, cnt, len,
+                               src, dst);
+        } else {
+            hipLaunchKernelGGL(k_ac_tree, dim3(ceil_div(outc * len, 256)), dim3(256), 0, s, cnt, len,
+                               src, dst);
+        }
+        MLG_LAUNCH_CHECK();
+        std::swap(src, dst);
+        cnt = outc;
+    }
+    return src;
+}
+
 // Chen & Ye projection of y onto the simplex.  The sort is an odd-even
 // transposition network (the sorted values are the same for any correct
 // sort); entries m..M-1 are +inf and sort last.
@@ -544,16 +597,7 @@ static void ac_run_fused(int64_t n, int k, int m, const double *evals, const dou
     int l = 0;
     double rc = 0.0;
     do {
-        double *src = pa.p, *dst = pb.p;
-        int64_t cnt = nch;
-        while (cnt > 1) {
-            const int64_t outc = cnt / 2 + (cnt & 1);
-            hipLaunchKernelGGL(k_ac_tree, dim3(ceil_div(outc * k * m, 256)), dim3(256), 0, s, cnt, k * m,
-                               src, dst);
-            MLG_LAUNCH_CHECK();
-            std::swap(src, dst);
-            cnt = outc;
-        }
+        double *src = ac_tree_reduce(nch, k * m, pa.p, pb.p, s);
         // src holds V; the step overwrites pa with the next partials
         double *Vd = src;
         if (src == pa.p) {
@@ -615,16 +659,7 @@ void ac_run(int64_t n, int k, int m, const double *evals, const double *evecs, i
     do {
         hipLaunchKernelGGL(k_ac_zr, dim3((unsigned)nch), dim3(256), 0, s, n, k, m, Z.p, R.p, pa.p);
         MLG_LAUNCH_CHECK();
-        double *src = pa.p, *dst = pb.p;
-        int64_t cnt = nch;
-        while (cnt > 1) {
-            const int64_t outc = cnt / 2 + (cnt & 1);
-            hipLaunchKernelGGL(k_ac_tree, dim3(ceil_div(outc * k * m, 256)), dim3(256), 0, s, cnt, k * m,
-                               src, dst);
-            MLG_LAUNCH_CHECK();
-            std::swap(src, dst);
-            cnt = outc;
-        }
+        double *src = ac_tree_reduce(nch, k * m, pa.p, pb.p, s);
         if (v_in_lds) {
             AC_M_SWITCH(m, hipLaunchKernelGGL((k_ac_update<MM, true>), dim3(ceil_div(n, 256)),
                                               dim3(256), v_lds, s, n, k, m, evecs, ldv, src, U,
