@@ -1152,28 +1152,38 @@ __device__ inline void window_factors(const PtIn<3> &pi, bool ok, const int org[
 // Spreading tiles: TF full tiles of 16 (cx, cy) rows serve every cz with
 // B = wz[cz] z; the RR = C2 mod 16 remaining (cx, cy) cells are packed with
 // cz into TR mixed tiles, rows (r, cz) -> A = wxy[16 TF + r] wz[cz], B = z.
+// Record layout: up to P = 6 a point's record holds its C2 products at
+// stride RS (16 mod 32), mixed-tile cells included.  At P = 7 (TF = 3, one
+// remaining cell) the record holds the 48 full-tile products at stride 48
+// and the remaining product sits in an array of its own, so the stride stays
+// 16 mod 32 without growing to 80 floats (LDS for two wavefronts per SIMD);
+// its mixed tile has rows cz = 0..15, of which those >= P are zeroed.
 template <int P>
 struct SpreadTiles3 {
     static constexpr int C2 = P * P;
     static constexpr int TF = C2 / 16;
     static constexpr int RR = C2 % 16;
     static constexpr int TR = (RR * P + 15) / 16;
+    static constexpr bool TAIL = P == 7;
+    static constexpr int RS = TAIL ? 16 * TF : MfShape3<P>::RS;
+    static constexpr int RW = TAIL ? 16 * TF : (C2 + 3) / 4 * 4;   // record entries written
 };
 
 // One task (points of one bin) of the d = 3 matrix-core spreading, written to
-// its patch slot tk.w.  LDS: wxy (64 RS), wzs (64 x 8), zv (64 x 16).
+// its patch slot tk.w.  LDS: wxy (64 RS), wzs (64 x 8), zv (64 x 16), and
+// for P = 7 wxt (64).
 template <int P>
 __device__ __forceinline__ void spread3_task(const Geom g, const int4 tk,
                                              const MLG_GLOBAL int *__restrict__ c32,
                                              const MLG_GLOBAL float *__restrict__ f32,
                                              const MLG_GLOBAL float *__restrict__ Zs, float beta,
                                              float *__restrict__ patch, float *wxy, float *wzs,
-                                             float *zv) {
-    using S = MfShape3<P>;
+                                             float *zv, float *wxt) {
     using U = SpreadTiles3<P>;
     const MLG_GLOBAL int *__restrict__ perm = to_global(g.perm);
     const MLG_GLOBAL float *__restrict__ zsc = to_global(g.zsc);
-    constexpr int RS = S::RS, C2 = S::C2, TF = U::TF, RR = U::RR, TR = U::TR;
+    constexpr int RS = U::RS, RW = U::RW, C2 = U::C2, TF = U::TF, RR = U::RR, TR = U::TR;
+    constexpr bool TAIL = U::TAIL;
     const int bs = g.bs;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
     const int v0 = blockIdx.y * 16;
@@ -1189,8 +1199,11 @@ __device__ __forceinline__ void spread3_task(const Geom g, const int4 tk,
 #pragma unroll
     for (int u = 0; u < TR; ++u) accr[u] = floatx4{0.f, 0.f, 0.f, 0.f};
     // mixed-tile row of this lane: (cx, cy) cell 16 TF + r, z slice cz
-    // (cz < 8 for every P <= 6; slots cz >= P select a zero factor)
-    static_assert(TR == 0 || (16 * TR - 1) / (RR > 0 ? RR : 1) < 8, "mixed tile rows exceed the z slots");
+    // (cz < 8 for every P <= 6; slots cz >= P select a zero factor; at P = 7
+    // rows cz >= 8 are zeroed when the operand is formed)
+    static_assert(TAIL || TR == 0 || (16 * TR - 1) / (RR > 0 ? RR : 1) < 8,
+                  "mixed tile rows exceed the z slots");
+    static_assert(!TAIL || (RR == 1 && TR == 1), "separate tail holds one cell");
     int rr_cell[TR > 0 ? TR : 1], rr_cz[TR > 0 ? TR : 1];
 #pragma unroll
     for (int u = 0; u < TR; ++u) {
@@ -1222,17 +1235,14 @@ __device__ __forceinline__ void spread3_task(const Geom g, const int4 tk,
         {
             float wv[3][P];
             window_factors<P>(pin, lane < cnt, org, g.w, two_over_w, beta, wv);
-            float rec[RS];
+            float rec[RW];
 #pragma unroll
-            for (int e = 0; e < RS; ++e) rec[e] = 0.0f;
-#pragma unroll
-            for (int cy = 0; cy < P; ++cy)
-#pragma unroll
-                for (int cx = 0; cx < P; ++cx) rec[cx + P * cy] = wv[0][cx] * wv[1][cy];
+            for (int e = 0; e < RW; ++e) rec[e] = e < C2 ? wv[0][e % P] * wv[1][e / P] : 0.0f;
             float *wp = wxy + lane * RS;
 #pragma unroll
-            for (int e = 0; e < RS; e += 4)
+            for (int e = 0; e < RW; e += 4)
                 *reinterpret_cast<float4 *>(wp + e) = make_float4(rec[e], rec[e + 1], rec[e + 2], rec[e + 3]);
+            if constexpr (TAIL) wxt[lane] = wv[0][(C2 - 1) % P] * wv[1][(C2 - 1) / P];
             float zr[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) zr[e] = e < P ? wv[2][e] : 0.0f;
@@ -1270,8 +1280,13 @@ __device__ __forceinline__ void spread3_task(const Geom g, const int4 tk,
             // mixed-tile factors; z slots >= P of a record hold zero
 #pragma unroll
             for (int u = 0; u < TR; ++u) {
-                o.rx[u] = wxy[pp * RS + rr_cell[u]];
-                o.rz[u] = wzs[pp * 8 + rr_cz[u]];
+                if constexpr (TAIL) {
+                    o.rx[u] = wxt[pp];
+                    o.rz[u] = wzs[pp * 8 + (rr_cz[u] & 7)];
+                } else {
+                    o.rx[u] = wxy[pp * RS + rr_cell[u]];
+                    o.rz[u] = wzs[pp * 8 + rr_cz[u]];
+                }
             }
             const float4 wz0 = *reinterpret_cast<const float4 *>(wzs + pp * 8);
             const float4 wz1 = *reinterpret_cast<const float4 *>(wzs + pp * 8 + 4);
@@ -1293,7 +1308,10 @@ __device__ __forceinline__ void spread3_task(const Geom g, const int4 tk,
 #pragma unroll
             for (int cz = 0; cz < P; ++cz) bb[cz] = cur.z * cur.wz[cz];
 #pragma unroll
-            for (int u = 0; u < TR; ++u) rb[u] = cur.rx[u] * cur.rz[u];
+            for (int u = 0; u < TR; ++u) {
+                rb[u] = cur.rx[u] * cur.rz[u];
+                if constexpr (TAIL) rb[u] = rr_cz[u] < P ? rb[u] : 0.0f;
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int cz = 0; cz < P; ++cz) {
@@ -1339,19 +1357,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
                                                      float *__restrict__ patch,
                                                      const LayerArgs *__restrict__ lay,
                                                      const int *__restrict__ tlayer) {
-    using S = MfShape3<P>;
-    __shared__ __attribute__((aligned(16))) float wxy[64 * S::RS];
+    using U = SpreadTiles3<P>;
+    __shared__ __attribute__((aligned(16))) float wxy[64 * U::RS];
     __shared__ __attribute__((aligned(16))) float wzs[64 * 8];
     __shared__ __attribute__((aligned(16))) float zv[64 * 16];
+    __shared__ float wxt[U::TAIL ? 64 : 1];
     const LayerArgs *lp = lay ? lay + tlayer[blockIdx.x] : nullptr;
     const Geom gl = lp ? lp->g : g;
     spread3_task<P>(gl, tasks[blockIdx.x], to_global(lp ? lp->c32 : c32),
                     to_global(lp ? lp->f32 : f32), to_global(lp ? lp->Zs : Zs),
-                    lp ? lp->beta : beta, patch, wxy, wzs, zv);
+                    lp ? lp->beta : beta, patch, wxy, wzs, zv, wxt);
 }
 
 template <int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_interp_mfma3(Geom g_, const int4 *__restrict__ tasks,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P <= 6 ? 3 : 2))) void k_interp_mfma3(Geom g_, const int4 *__restrict__ tasks,
                                                      const int *__restrict__ c32_,
                                                      const float *__restrict__ f32_,
                                                      const float *__restrict__ grid_, int bg,
@@ -1474,7 +1493,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // Patch edges with a compiled matrix-core variant, per dimension.
 static bool mfma_patch_ok(int D, int P) {
     if (P < 2) return false;
-    if (D == 3) return P <= 6;
+    if (D == 3) return P <= 7;
     if (D == 2) return P <= 12;
     return P <= 16;
 }
@@ -1486,10 +1505,10 @@ static bool mfma_patch_ok(int D, int P) {
         case 4: CALL(D, 4); break;                                                 \
         case 5: CALL(D, 5); break;                                                 \
         case 6: CALL(D, 6); break;                                                 \
+        case 7: CALL(D, 7); break;                                                 \
         default:                                                                   \
             if constexpr (D < 3) {                                                 \
                 switch (p) {                                                       \
-                    case 7: CALL(D, 7); break;                                     \
                     case 8: CALL(D, 8); break;                                     \
                     case 9: CALL(D, 9); break;                                     \
                     case 10: CALL(D, 10); break;                                   \

@@ -141,6 +141,55 @@ def test_nfft_bins(mlg, bin_, prec, window, gate, d):
     assert rel_err(Y, oracle.lsym_matvec([L], X)) <= gate
 
 
+@pytest.mark.parametrize("b", [16, 32])
+def test_nfft_fp32_bin2_matrix_core(mlg, b):
+    """d = 3, bin 2, window 6: patches of 7^3 cells on the matrix-core
+    kernels (three full tiles of (cx, cy) rows plus the one remaining cell).
+    A dense core puts thousands of points in one bin (split tasks and their
+    reductions).  Against the oracle at the FP32 gate, and against the
+    vector-ALU kernels on the same plan (the first 8 vectors as a block of
+    8), which differ only in FP32 rounding."""
+    g = gen.rng(1201)
+    n = 12007
+    core = 0.004 * g.standard_normal((4000, 3))
+    rest = gen.gaussian_mixture(n - 4000, 3, 4, 0.05, 1202)[0]
+    pts = np.ascontiguousarray(np.vstack([core, rest]))
+    X = gen.test_vectors(n, b, 1203)
+    kp = mlg.kparams("nfft", 32, N=64, window=6, bin=2)
+    case_id("nfft fp32 W x d=3 bin=2 w=6 (patch 7) n=%d b=%d" % (n, b))
+    Y = mlg.kernel_matvec(pts, 0.3, X, kp)
+    assert rel_err(Y, oracle.kernel_matvec(pts, 0.3, X)) <= 1e-4
+    case_id("  same plan, block of 8 (vector-ALU kernels)")
+    Y8 = mlg.kernel_matvec(pts, 0.3, X[:, :8], kp)
+    assert rel_err(Y[:, :8], Y8) <= 2e-6
+
+
+def test_nfft_fp32_bin2_lsym_and_batches(mlg):
+    """L_sym through bin-2 (patch 7) matrix-core layers: one layer (scaled
+    summation input) and four layers of d = 3, which run as one batch."""
+    n = 5000
+    pts = [gen.gaussian_mixture(n, 3, 3, 0.08, 1211 + t)[0] for t in range(4)]
+    sig = [0.3, 0.25, 0.35, 0.28]
+    kp = [mlg.kparams("nfft", 32, N=64, window=6, bin=2) for _ in range(4)]
+    layers = [oracle.Layer(q, s) for q, s in zip(pts, sig)]
+    X = gen.test_vectors(n, 16, 1215)
+    case_id("nfft fp32 L_sym d=3 bin=2 one layer n=%d b=16" % n)
+    g1 = mlg.Graph(pts[:1], sig[:1], kp[:1])
+    assert g1.layer_info(0)["bin"] == 2
+    Y1 = g1.laplacian_matvec(0, mlg.MLG_OP_LSYM, X)
+    g1.close()
+    assert rel_err(Y1, oracle.lsym_matvec(layers[:1], X)) <= 1e-4
+    import torch
+    g = mlg.Graph(pts, sig, kp)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to("cuda")
+    case_id("nfft fp32 L_sym d=3 bin=2 four layers (batched) n=%d b=16" % n)
+    Y = g.laplacian_matvec(-1, mlg.MLG_OP_LSYM, Xd).cpu().numpy()
+    assert rel_err(Y, oracle.lsym_matvec(layers, X)) <= 1e-4
+    _, Yseq = g.profile_stages(-1, mlg.MLG_OP_LSYM, Xd, reps=1, return_y=True)
+    assert np.array_equal(Y, Yseq.cpu().numpy())
+    g.close()
+
+
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_nfft_fp64_lsym_dims(mlg, d):
     pts, _ = gen.gaussian_mixture(3001, d, 4, 0.08, 40 + d)

@@ -289,14 +289,19 @@ def test_large_fp32_and_fp64_rows(mlg):
     b = 16
     X = gen.test_vectors(n, b, c["base_seed"] + 300)
     Xd = device_block(X)
-    kp32 = [mlg.kparams("nfft", 32, N=c["N"], window=6) for _ in range(T)]
-    g = mlg.Graph(layers, c["sigma"], kp32, degrees=False)
+    # bins of 1 and of 2 grid cells per side (patches of 6^3 and 7^3 cells
+    # on the matrix-core kernels; the large-scale product runs with 2)
+    graphs = {bn: mlg.Graph(layers, c["sigma"],
+                            [mlg.kparams("nfft", 32, N=c["N"], window=6, bin=bn) for _ in range(T)],
+                            degrees=False) for bn in (1, 2)}
     for t in range(T):
-        case_id("large layer %d FP32 W x n=%d b=%d" % (t, n, b))
-        Y = g.laplacian_matvec(t, mlg.MLG_OP_W, Xd).cpu().numpy()
         ref = oracle.kernel_rows(c["layers"][t], c["sigma"][t], X, rows)
-        assert rows_rel_err(Y[rows], ref) <= 1e-4
-    g.close()
+        for bn, g in graphs.items():
+            case_id("large layer %d FP32 W x n=%d b=%d bin=%d" % (t, n, b, bn))
+            Y = g.laplacian_matvec(t, mlg.MLG_OP_W, Xd).cpu().numpy()
+            assert rows_rel_err(Y[rows], ref) <= 1e-4
+    for g in graphs.values():
+        g.close()
     kp64 = [mlg.kparams("nfft", 64, N=c["N"], window=12) for _ in range(T)]
     g = mlg.Graph(layers[:1], c["sigma"][:1], kp64[:1], degrees=False)
     case_id("large layer 0 FP64 W x n=%d b=1" % n)
@@ -307,18 +312,19 @@ def test_large_fp32_and_fp64_rows(mlg):
 
 
 def test_large_lanczos_30_eigenpairs(mlg):
-    """30 smallest eigenpairs of L_1 at n = 10^7 (three FP32 NFFT layers,
-    FP64 degrees, block Lanczos with FP64 CGS2 full reorthogonalisation):
-    every residual ||L_1 phi - lambda phi|| within tol (it bounds the
-    eigenvalue error of the symmetric operator), orthonormal vectors,
+    """30 smallest eigenpairs of L_1 at n = 10^7 (three FP32 NFFT layers with
+    bins of 2 cells, as the large-scale benchmark runs them; FP64 degrees,
+    block Lanczos with FP64 CGS2 full reorthogonalisation): every residual
+    ||L_1 phi - lambda phi|| within tol (it bounds the eigenvalue error of
+    the symmetric operator), orthonormal vectors,
     eigenvalues ascending in [0, 2), and sampled rows of the operator the
     residuals were taken with against the oracle's W rows."""
     import torch
     c = gen.config5()
     n, T, k = c["n"], len(c["layers"]), c["k"]
     layers = [device_block(L) for L in c["layers"]]
-    kp = [mlg.kparams("nfft", 32, N=c["N"], window=6) for _ in range(T)]
-    case_id("large graph with degrees n=%d T=%d" % (n, T))
+    kp = [mlg.kparams("nfft", 32, N=c["N"], window=6, bin=2) for _ in range(T)]
+    case_id("large graph with degrees n=%d T=%d bin=2" % (n, T))
     g = mlg.Graph(layers, c["sigma"], kp)
     tol = 1e-5
     case_id("large lanczos L_1 n=%d k=%d block=16 tol=%g" % (n, k, tol))
