@@ -1580,36 +1580,6 @@ struct FftPass {
     int64_t mstr;
 };
 
-template <class C2, int LOGL, int LDL>
-__device__ inline void fft_stages2(C2 *buf, const C2 *tw, bool inverse, int lines_log) {
-    constexpr int L = 1 << LOGL;
-    const int LINES = 1 << lines_log;
-#pragma unroll
-    for (int s = 0; s < LOGL; ++s) {
-        const int half = 1 << s;
-#pragma unroll
-        for (int it = 0; it < (L / 2) * (LDL - 1) / 256; ++it) {
-            const int e = threadIdx.x + 256 * it;
-            const int ln = e & (LINES - 1), bf = e >> lines_log;
-            const int grp = bf >> s, pos = bf & (half - 1);
-            const int i0 = (grp << (s + 1)) + pos, i1 = i0 + half;
-            C2 w = tw[pos << (LOGL - 1 - s)];
-            if (inverse) w.y = -w.y;
-            const C2 a = buf[i0 * LDL + ln], b = buf[i1 * LDL + ln];
-            C2 bw, r0, r1;
-            bw.x = b.x * w.x - b.y * w.y;
-            bw.y = b.x * w.y + b.y * w.x;
-            r0.x = a.x + bw.x;
-            r0.y = a.y + bw.y;
-            r1.x = a.x - bw.x;
-            r1.y = a.y - bw.y;
-            buf[i0 * LDL + ln] = r0;
-            buf[i1 * LDL + ln] = r1;
-        }
-        __syncthreads();
-    }
-}
-
 // 8-point DFT in registers (radix-2 decimation in frequency), natural order
 // in and out: a[k] <- sum_n a[n] exp(-+2 pi i n k / 8) (+ for the inverse).
 template <class C2>
@@ -1638,6 +1608,89 @@ __device__ inline void dft8(C2 (&a)[8], bool inverse) {
     a[5] = sub(c4, c5);
     a[3] = add(c6, c7);
     a[7] = sub(c6, c7);
+}
+
+// 4- and 2-point DFTs in registers, natural order (same sign convention).
+template <class C2>
+__device__ inline void dft4(C2 (&a)[4], bool inverse) {
+    using T = decltype(a[0].x);
+    const T sg = inverse ? T(1) : T(-1);
+    C2 b0, b1, b2, b3;
+    b0.x = a[0].x + a[2].x; b0.y = a[0].y + a[2].y;
+    b1.x = a[0].x - a[2].x; b1.y = a[0].y - a[2].y;
+    b2.x = a[1].x + a[3].x; b2.y = a[1].y + a[3].y;
+    // (a1 - a3) times sg i
+    b3.x = -sg * (a[1].y - a[3].y);
+    b3.y = sg * (a[1].x - a[3].x);
+    a[0].x = b0.x + b2.x; a[0].y = b0.y + b2.y;
+    a[2].x = b0.x - b2.x; a[2].y = b0.y - b2.y;
+    a[1].x = b1.x + b3.x; a[1].y = b1.y + b3.y;
+    a[3].x = b1.x - b3.x; a[3].y = b1.y - b3.y;
+}
+
+template <class C2>
+__device__ inline void dft2(C2 (&a)[2], bool) {
+    const C2 u = a[0], v = a[1];
+    a[0].x = u.x + v.x; a[0].y = u.y + v.y;
+    a[1].x = u.x - v.x; a[1].y = u.y - v.y;
+}
+
+// Mixed-radix Stockham FFT of the LINES = 2^LOGLINES lines held in buf
+// (element k of a line at buf[k * LDL + line]; natural order in and out):
+// radix-8 stages, the last one of radix 4 or 2 when log2 L is not a
+// multiple of 3.  A stage of radix R after sub-transforms of length Ns (the
+// product of the earlier radices) takes, for butterfly j < L / R of a line,
+// the inputs x[j + r L / R] (r < R), multiplies input r by
+// W_{Ns R}^{(j mod Ns) r}, does an R-point DFT and writes output r to
+// (j div Ns) Ns R + (j mod Ns) + r Ns.  All reads of a stage come before a
+// barrier, all writes after it, so the stage runs in place.  tw[q] =
+// exp(-2 pi i q / L), q < L / 2; 256 threads, each reaching every barrier.
+template <class C2, int LOGL, int LDL, int LOGLINES, int LOGNS = 0>
+__device__ inline void fft_stockham(C2 *buf, const C2 *tw, bool inverse) {
+    constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES;
+    constexpr int LOGR = (LOGL - LOGNS) >= 3 ? 3 : (LOGL - LOGNS);
+    if constexpr (LOGR > 0) {
+        constexpr int R = 1 << LOGR, NS = 1 << LOGNS;
+        constexpr int NB = (L / R) * LINES;   // butterflies of the stage
+        constexpr int BPT = (NB + 255) / 256;
+        C2 v[BPT][R];
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            const int b = threadIdx.x + 256 * i;
+            if (NB % 256 != 0 && b >= NB) continue;
+            const int ln = b & (LINES - 1), j = b >> LOGLINES, k = j & (NS - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[i][r] = buf[(j + r * (L / R)) * LDL + ln];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const int q = (k * r) << (LOGL - LOGNS - LOGR);
+                C2 w = tw[q & (L / 2 - 1)];
+                if (q & (L / 2)) {
+                    w.x = -w.x;
+                    w.y = -w.y;
+                }
+                if (inverse) w.y = -w.y;
+                const C2 u = v[i][r];
+                v[i][r].x = u.x * w.x - u.y * w.y;
+                v[i][r].y = u.x * w.y + u.y * w.x;
+            }
+            if constexpr (R == 8) dft8(v[i], inverse);
+            else if constexpr (R == 4) dft4(v[i], inverse);
+            else dft2(v[i], inverse);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            const int b = threadIdx.x + 256 * i;
+            if (NB % 256 != 0 && b >= NB) continue;
+            const int ln = b & (LINES - 1), j = b >> LOGLINES, k = j & (NS - 1);
+            const int dst = ((j >> LOGNS) << (LOGNS + LOGR)) + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[(dst + r * NS) * LDL + ln] = v[i][r];
+        }
+        __syncthreads();
+        fft_stockham<C2, LOGL, LDL, LOGLINES, LOGNS + LOGR>(buf, tw, inverse);
+    }
 }
 
 // 64-point FFTs of the 32 lines in buf (buf[k * LDL + line], natural order
@@ -1818,8 +1871,8 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
                                              const T *__restrict__ M) {
     using C2 = typename Cplx<T>::type;
     constexpr int L = 1 << LOGL, LINES = 1 << LOGLINES, LDL = LINES + 1;
-    // 64-point lines, 32 per workgroup: 8 x 8 in registers (fft64_r8),
-    // natural order; otherwise radix-2 stages on bit-reversed input
+    // 64-point lines, 32 per workgroup: 8 x 8 in registers (fft64_r8);
+    // other lengths: Stockham stages of radix 8 (natural order throughout)
     constexpr bool R8 = LOGL == 6 && LOGLINES == 5;
     __shared__ C2 buf[L * LDL];
     __shared__ C2 tw[L / 2];
@@ -1863,12 +1916,11 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
         const int cc = e & (C - 1);
         const int k = (e >> p.logC) & (L - 1);
         const int oo = e >> (p.logC + LOGL);
-        const int rk = R8 ? k : (int)(__brev((unsigned)k) >> (32 - LOGL));
-        buf[rk * LDL + (oo << p.logC) + cc] = val[it];
+        buf[k * LDL + (oo << p.logC) + cc] = val[it];
     }
     __syncthreads();
     if constexpr (R8) fft64_r8<C2, LDL>(buf, tw, p.mode == 1);
-    else fft_stages2<C2, LOGL, LDL>(buf, tw, p.mode == 1, LOGLINES);
+    else fft_stockham<C2, LOGL, LDL, LOGLINES>(buf, tw, p.mode == 1);
     if (p.mode == 2) {
         T m[PER];
 #pragma unroll
@@ -1894,23 +1946,8 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
             buf[i] = v;
         }
         __syncthreads();
-        if constexpr (R8) {
-            fft64_r8<C2, LDL>(buf, tw, true);
-        } else {
-#pragma unroll
-            for (int it = 0; it < PER; ++it) {
-                const int e = threadIdx.x + 256 * it;
-                const int ln = e & (LINES - 1), k = e >> LOGLINES;
-                const int rk = (int)(__brev((unsigned)k) >> (32 - LOGL));
-                if (k < rk) {
-                    const C2 t0 = buf[k * LDL + ln];
-                    buf[k * LDL + ln] = buf[rk * LDL + ln];
-                    buf[rk * LDL + ln] = t0;
-                }
-            }
-            __syncthreads();
-            fft_stages2<C2, LOGL, LDL>(buf, tw, true, LOGLINES);
-        }
+        if constexpr (R8) fft64_r8<C2, LDL>(buf, tw, true);
+        else fft_stockham<C2, LOGL, LDL, LOGLINES>(buf, tw, true);
     }
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
