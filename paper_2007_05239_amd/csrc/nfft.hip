@@ -656,7 +656,10 @@ constexpr int csr_batch() {
 
 // Gather through the cell table: sum of the cell's patch entries in entry
 // order (entries of one cell are sorted by run), NB entries in flight per
-// batch (NB x VPL values of at most 64 registers).
+// batch (NB x VPL values of at most 64 registers).  Workgroup w takes cells
+// 256 (w div ng) on and vector group w mod ng (ng = bs / VPL): the groups of
+// one cell range run side by side, so each patch row and table entry comes
+// from HBM once and is shared through L2.
 // Batched form: the cells of nl layers in one flat index; layer t owns flat
 // cells [coff[t], coff[t+1]) and its grid starts goff[t] elements after
 // gridb; ptr / ent are the layers' tables concatenated (entries of patch
@@ -669,7 +672,8 @@ __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
                                                     T *__restrict__ grid_, int nl,
                                                     const int64_t *__restrict__ coff,
                                                     const int64_t *__restrict__ goff) {
-    const int64_t flat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ng = bs / VPL, vg = (int)(blockIdx.x % (unsigned)ng);
+    const int64_t flat = (int64_t)(blockIdx.x / (unsigned)ng) * blockDim.x + threadIdx.x;
     int64_t cell = flat;
     T *__restrict__ grid = grid_;
     if (nl > 0) {
@@ -686,7 +690,7 @@ __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
     } else if (cell >= G) {
         return;
     }
-    const int v0 = blockIdx.y * VPL;
+    const int v0 = vg * VPL;
     T acc[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; ++v) acc[v] = T(0);
@@ -712,7 +716,7 @@ __global__ __launch_bounds__(256) void k_gather_csr(int64_t G, int bs, int bg,
                 for (int v = 0; v < VPL; ++v) acc[v] += h[u][v];
     }
     grid_store<T, VPL>(grid, G, cell, v0, acc);
-    if (bg > bs && blockIdx.y == 0)
+    if (bg > bs && vg == 0)
         for (int v = bs; v < bg; ++v) grid[grid_index<T>(G, cell, v)] = T(0);
 }
 
@@ -2823,7 +2827,7 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     const int vgat = std::min(bs, 4);
     if (W.csr) {
 #define GATHERC_CALL(V)                                                                           \
-    hipLaunchKernelGGL((k_gather_csr<T, V>), dim3(ceil_div(G, 256), bs / V), dim3(256), 0, s, G, bs, bg, \
+    hipLaunchKernelGGL((k_gather_csr<T, V>), dim3(ceil_div(G, 256) * (bs / V)), dim3(256), 0, s, G, bs, bg, \
                        W.cell_ptr.p, W.cell_ent.p, patch, grid, 0, nullptr, nullptr)
         MLG_VPL_SWITCH(vgat, GATHERC_CALL)
 #undef GATHERC_CALL
@@ -3131,7 +3135,7 @@ void nfft_batch_apply(const NfftBatch &B, int use_dinv, hipStream_t s) {
     // cell-table gather over every layer's grid
     const int vgat = std::min(bs, 4);
 #define GATHERB_CALL(V)                                                                           \
-    hipLaunchKernelGGL((k_gather_csr<float, V>), dim3(ceil_div(B.ncell, 256), bs / V), dim3(256), 0, s, \
+    hipLaunchKernelGGL((k_gather_csr<float, V>), dim3(ceil_div(B.ncell, 256) * (bs / V)), dim3(256), 0, s, \
                        (int64_t)0, bs, bg, B.cptr.p, B.cent.p, patch, grid, B.nl, B.coff.p, B.goff.p)
     MLG_VPL_SWITCH(vgat, GATHERB_CALL)
 #undef GATHERB_CALL
