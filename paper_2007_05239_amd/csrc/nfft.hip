@@ -1965,6 +1965,77 @@ __global__ __launch_bounds__(256) void k_fft(typename Cplx<T>::type *__restrict_
     }
 }
 
+// The first FFT pass fused with the cell-table gather, for blocks of 16
+// vectors on grids of side L >= 128: workgroup o takes x line o (cells
+// o L .. o L + L - 1) of all eight complex planes.  Each cell's patch entries
+// are summed in entry order (the sums k_gather_csr writes to the grid) into
+// LDS as buf[x][plane]; the eight x lines are transformed (the x pass of
+// mode 0) and only their band entries are stored, so the gathered grid is
+// never written to HBM nor read back.
+template <class T, int LOGL>
+__global__ __launch_bounds__(256) void k_gather_fftx(typename Cplx<T>::type *__restrict__ data,
+                                                     int64_t G, int N, const int *__restrict__ ptr,
+                                                     const int *__restrict__ ent,
+                                                     const T *__restrict__ patch,
+                                                     const typename Cplx<T>::type *__restrict__ twg) {
+    using C2 = typename Cplx<T>::type;
+    constexpr int L = 1 << LOGL, LOGLINES = 3, LINES = 8, LDL = LINES + 1;
+    constexpr int BS = 16, VPL = 4, NG = BS / VPL, NB = csr_batch<T, VPL>();
+    constexpr int ITEMS = L * NG / 256;   // (cell, vector group) items per thread
+    __shared__ C2 buf[L * LDL];
+    __shared__ C2 tw[L / 2];
+    for (int j = threadIdx.x; j < L / 2; j += 256) tw[j] = twg[j];
+    const int64_t c0 = (int64_t)blockIdx.x * L;
+    int e0[ITEMS], e1[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int x = (threadIdx.x + 256 * it) / NG;
+        e0[it] = ptr[c0 + x];
+        e1[it] = ptr[c0 + x + 1];
+    }
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int i = threadIdx.x + 256 * it, x = i / NG, vg = i % NG;
+        T acc[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) acc[v] = T(0);
+        for (int e = e0[it]; e < e1[it]; e += NB) {
+            int idx[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) idx[u] = e + u < e1[it] ? ent[e + u] : -1;
+            T h[NB][VPL];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                if (idx[u] >= 0) load_vec<T, VPL>(patch + (int64_t)idx[u] * BS + vg * VPL, h[u]);
+                else
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) h[u][v] = T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                if (idx[u] >= 0)
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) acc[v] += h[u][v];
+        }
+        // vectors 4 vg .. 4 vg + 3: planes 2 vg and 2 vg + 1 (re, im)
+        C2 a, b;
+        a.x = acc[0];
+        a.y = acc[1];
+        b.x = acc[2];
+        b.y = acc[3];
+        buf[x * LDL + 2 * vg] = a;
+        buf[x * LDL + 2 * vg + 1] = b;
+    }
+    __syncthreads();
+    fft_stockham<C2, LOGL, LDL, LOGLINES>(buf, tw, false);
+#pragma unroll
+    for (int it = 0; it < L * LINES / 256; ++it) {
+        const int e = threadIdx.x + 256 * it;
+        const int q = e >> LOGL, k = e & (L - 1);
+        if (in_band(k, N, L)) data[(int64_t)q * G + c0 + k] = buf[k * LDL + q];
+    }
+}
+
 // Interpolation: one thread per (point, vector group); window weights in
 // registers, the footprint read from the grid.
 template <class T, int D, int VPL>
@@ -2658,9 +2729,44 @@ static void fft_pass(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, in
 // the out-of-band ones are never read again.
 // With nl > 1 the grid holds nl layers of the same N one after another
 // (bg / 2 planes each) and their multipliers sit mstr apart from M on.
+// Whether the first FFT pass of a plan takes the gather with it
+// (k_gather_fftx): one layer, blocks of 16, d >= 2, sides 128..512 (FP64:
+// up to 256, for its LDS tile), and a cell table.
+template <class T>
+static bool fused_gather_fft(const NfftPlan &P, const NfftWindow &W, int bs) {
+    const int maxL = sizeof(T) == 4 ? 512 : 256;
+    return W.csr && bs == 16 && P.d >= 2 && P.nos >= 128 && P.nos <= maxL;
+}
+
+template <class T>
+static void launch_gather_fftx(const NfftPlan &P, const NfftWindow &W, typename Cplx<T>::type *grid,
+                               const T *patch, hipStream_t s) {
+    int64_t G = 1;
+    for (int t = 0; t < P.d; ++t) G *= P.nos;
+    const int64_t lines = G / P.nos;
+    MLG_REQUIRE(lines < ((int64_t)1 << 31), MLG_ERR_RANGE, "FFT grid too large");
+#define GFX_CALL(LG)                                                                              \
+    hipLaunchKernelGGL((k_gather_fftx<T, LG>), dim3((unsigned)lines), dim3(256), 0, s, grid, G, P.N, \
+                       W.cell_ptr.p, W.cell_ent.p, patch, tw_of<T>(P))
+    switch (ilog2(P.nos)) {
+        case 7: GFX_CALL(7); break;
+        case 8: GFX_CALL(8); break;
+        case 9:
+            if constexpr (sizeof(T) == 4) {
+                GFX_CALL(9);
+                break;
+            }
+            [[fallthrough]];
+        default: throw Error(MLG_ERR_ARG, "fused gather: unsupported grid side");
+    }
+#undef GFX_CALL
+    MLG_LAUNCH_CHECK();
+}
+
+// With first_done the x pass of mode 0 has already run (k_gather_fftx).
 template <class T>
 static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid, const T *M,
-                         hipStream_t s, int nl = 1, int64_t mstr = 0) {
+                         hipStream_t s, int nl = 1, int64_t mstr = 0, bool first_done = false) {
     const int d = P.d;
     const int nq = bg / 2 * nl;
     if (d == 1) {
@@ -2675,7 +2781,7 @@ static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid
                 return;
             }
         }
-        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s, nl);
+        if (!first_done) fft_pass<T>(P, bg, grid, 0, 0, nullptr, s, nl);
         fft_pass<T>(P, bg, grid, 1, 2, M, s, nl, mstr);
         fft_pass<T>(P, bg, grid, 0, 1, nullptr, s, nl);
     } else {
@@ -2693,7 +2799,7 @@ static void fft_convolve(const NfftPlan &P, int bg, typename Cplx<T>::type *grid
                 return;
             }
         }
-        fft_pass<T>(P, bg, grid, 0, 0, nullptr, s, nl);
+        if (!first_done) fft_pass<T>(P, bg, grid, 0, 0, nullptr, s, nl);
         fft_pass<T>(P, bg, grid, 1, 0, nullptr, s, nl);
         fft_pass<T>(P, bg, grid, 2, 2, M, s, nl, mstr);
         fft_pass<T>(P, bg, grid, 1, 1, nullptr, s, nl);
@@ -2825,7 +2931,10 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     // short chains beat few wide ones (measured: 16 -> 4 vectors per thread
     // takes the d = 3 gathers of the image graph from 94 to 60 us)
     const int vgat = std::min(bs, 4);
-    if (W.csr) {
+    const bool fused = fused_gather_fft<T>(P, W, bs);
+    if (fused) {
+        // the gather runs inside the first FFT pass
+    } else if (W.csr) {
 #define GATHERC_CALL(V)                                                                           \
     hipLaunchKernelGGL((k_gather_csr<T, V>), dim3(ceil_div(G, 256) * (bs / V)), dim3(256), 0, s, G, bs, bg, \
                        W.cell_ptr.p, W.cell_ent.p, patch, grid, 0, nullptr, nullptr)
@@ -2839,7 +2948,8 @@ static void apply_d(const NfftPlan &P, const NfftWindow &W, int bs, const T *Zs,
     }
     if (ev) MLG_HIP(hipEventRecord(ev[2], s));
     using C2 = typename Cplx<T>::type;
-    fft_convolve<T>(P, bg, reinterpret_cast<C2 *>(grid), mult_of<T>(W), s);
+    if (fused) launch_gather_fftx<T>(P, W, reinterpret_cast<C2 *>(grid), patch, s);
+    fft_convolve<T>(P, bg, reinterpret_cast<C2 *>(grid), mult_of<T>(W), s, 1, 0, fused);
     if (ev) MLG_HIP(hipEventRecord(ev[3], s));
     if constexpr (std::is_same<T, float>::value) {
         if (mf && P.ntasks > 0) {

@@ -225,6 +225,29 @@ def test_nfft_large_bandwidth_elementwise(mlg, d, N, prec, window, gate):
     g.close()
 
 
+@pytest.mark.parametrize("d,N,prec,window,gate", [(3, 128, 32, 6, 1e-4), (3, 64, 64, 12, 1e-6),
+                                                    (2, 256, 32, 6, 1e-4), (2, 128, 64, 12, 1e-6)])
+def test_nfft_fused_gather_fft_b16(mlg, d, N, prec, window, gate):
+    """Blocks of 16 vectors on grids of side 128..512 sum the cell table
+    inside the first FFT pass: against the oracle, and against the separate
+    gather (a block of 32 vectors, first 16 columns: every stage treats each
+    vector the same way and the gathered sums are formed in the same order;
+    the two x-transform kernels may contract multiply-adds differently, so
+    the comparison is at rounding level: 1e-6 in FP32, 1e-13 in FP64)."""
+    n = 4000
+    pts = gen.uniform_ball(n, d, 1.0, 80 + d)
+    sig = 0.14 if 2 * N == 256 else (0.07 if N == 256 else 0.28)
+    X = gen.test_vectors(n, 32, 85 + d)
+    case_id("nfft fused gather fp%d d=%d N=%d w=%d n=%d b=16" % (prec, d, N, window, n))
+    g = mlg.Graph([pts], [sig], mlg.kparams("nfft", prec, N=N, window=window))
+    Y16 = g.laplacian_matvec(0, mlg.MLG_OP_W, np.ascontiguousarray(X[:, :16]))
+    assert rel_err(Y16, oracle.kernel_matvec(pts, sig, X[:, :16])) <= gate
+    case_id("  same plan, block of 32 (separate gather)")
+    Y32 = g.laplacian_matvec(0, mlg.MLG_OP_W, X)
+    g.close()
+    assert rel_err(Y16, Y32[:, :16]) <= (1e-6 if prec == 32 else 1e-13)
+
+
 @pytest.mark.parametrize("b", [1, 5, 16])
 def test_nfft_fp32_multilayer_mean(mlg, b):
     n = 4099
