@@ -33,6 +33,8 @@ constexpr int kRB = 16;        // rows per LDS batch
 // ---- C = A^T B, partials per row chunk --------------------------------------
 // Thread (ty, tx) of 16 x 16 owns C[ty + 16 a][tx + 16 c] for a < NA, c < NQ
 // (NA = ceil(p / 16), NQ = ceil(q / 16)); rows pass through LDS 16 at a time.
+// The next batch's loads are issued before the current batch is multiplied,
+// so each workgroup keeps a batch of rows in flight.
 template <int NA, int NQ>
 __global__ __launch_bounds__(256) void k_gemm_tn_part(int64_t n, int p, int q,
                                                       const double *__restrict__ A, int64_t lda,
@@ -48,18 +50,37 @@ __global__ __launch_bounds__(256) void k_gemm_tn_part(int64_t n, int p, int q,
     for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int c = 0; c < NQ; ++c) acc[a][c] = 0.0;
-    for (int64_t rb = r0; rb < r1; rb += kRB) {
+    // element e = tid + 256 u of a batch: row rr = e mod 16, column e / 16
+    static_assert(kRB == 16, "batch layout");
+    double ra[NA], rb_[NQ];
+    auto fetch = [&](int64_t rb) {
         const int cnt = (int)((r1 - rb) < kRB ? (r1 - rb) : kRB);
-        __syncthreads();
-        for (int e = tid; e < kRB * NA * 16; e += 256) {
-            const int rr = e % kRB, i = e / kRB;
-            As[rr][i] = (rr < cnt && i < p) ? A[rb + rr + (int64_t)i * lda] : 0.0;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + 256 * u, rr = e % kRB, i = e / kRB;
+            ra[u] = (rr < cnt && i < p) ? A[rb + rr + (int64_t)i * lda] : 0.0;
         }
-        for (int e = tid; e < kRB * NQ * 16; e += 256) {
-            const int rr = e % kRB, j = e / kRB;
-            Bs[rr][j] = (rr < cnt && j < q) ? B[rb + rr + (int64_t)j * ldb] : 0.0;
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int e = tid + 256 * u, rr = e % kRB, j = e / kRB;
+            rb_[u] = (rr < cnt && j < q) ? B[rb + rr + (int64_t)j * ldb] : 0.0;
+        }
+    };
+    if (r0 < r1) fetch(r0);
+    for (int64_t rb = r0; rb < r1; rb += kRB) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + 256 * u;
+            As[e % kRB][e / kRB] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int e = tid + 256 * u;
+            Bs[e % kRB][e / kRB] = rb_[u];
         }
         __syncthreads();
+        if (rb + kRB < r1) fetch(rb + kRB);
 #pragma unroll 4
         for (int rr = 0; rr < kRB; ++rr) {
             double bv[NQ];
@@ -462,7 +483,9 @@ struct Lz {
     void setup(int64_t n_, hipStream_t s_) {
         n = n_;
         s = s_;
-        rc = std::max<int64_t>(1024, (n + 511) / 512);
+        // about 2048 row chunks at large n (eight workgroups per CU, all
+        // resident), at least 1024 rows each
+        rc = std::max<int64_t>(1024, (n + 2047) / 2048);
         rc = (rc + kRB - 1) / kRB * kRB;
         nchunks = ceil_div(n, rc);
         part.alloc((size_t)nchunks * kTnMaxP * kTnMaxQ);
