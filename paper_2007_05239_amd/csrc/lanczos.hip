@@ -31,26 +31,35 @@ constexpr int kTnMaxQ = 32;    // columns of C
 constexpr int kRB = 16;        // rows per LDS batch
 
 // ---- C = A^T B, partials per row chunk --------------------------------------
-// Thread (ty, tx) of 16 x 16 owns C[ty + 16 a][tx + 16 c] for a < NA, c < NQ
-// (NA = ceil(p / 16), NQ = ceil(q / 16)); rows pass through LDS 16 at a time.
-// The next batch's loads are issued before the current batch is multiplied,
-// so each workgroup keeps a batch of rows in flight.
+// Rows pass through LDS 16 at a time (element e = tid + 256 u of a batch:
+// row e mod 16, column e / 16, so each column's 16 rows are one 128-byte
+// load); the next batch's loads are issued before the current batch is
+// multiplied, so each workgroup keeps a batch of rows in flight.  The
+// products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64, K = 4 rows
+// per instruction): wavefront w owns the 16 x 16 tiles a = w, w + 4, ... of C
+// (rows i of A^T) for every column tile c, over all rows of the chunk.
+// Operand layout: A[i][k] in lane i + 16 k, B[k][v] in lane v + 16 k; the
+// result D[i][v] in lane v + 16 qq, element m, with i = qq + 4 m.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
 template <int NA, int NQ>
 __global__ __launch_bounds__(256) void k_gemm_tn_part(int64_t n, int p, int q,
                                                       const double *__restrict__ A, int64_t lda,
                                                       const double *__restrict__ B, int64_t ldb,
                                                       int64_t rc, double *__restrict__ part) {
-    __shared__ double As[kRB][NA * 16];
-    __shared__ double Bs[kRB][NQ * 16];
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    constexpr int AS = NA * 16 + 1, BS = NQ * 16 + 1;   // padded LDS rows
+    constexpr int NT = (NA + 3) / 4;                    // tiles per wavefront
+    __shared__ double As[kRB * AS];
+    __shared__ double Bs[kRB * BS];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
     const int64_t r0 = (int64_t)blockIdx.x * rc;
     const int64_t r1 = (r0 + rc < n) ? r0 + rc : n;
-    double acc[NA][NQ];
+    f64x4_t acc[NT][NQ];
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) acc[a][c] = 0.0;
-    // element e = tid + 256 u of a batch: row rr = e mod 16, column e / 16
+        for (int c = 0; c < NQ; ++c) acc[t][c] = f64x4_t{0.0, 0.0, 0.0, 0.0};
     static_assert(kRB == 16, "batch layout");
     double ra[NA], rb_[NQ];
     auto fetch = [&](int64_t rb) {
@@ -72,37 +81,46 @@ __global__ __launch_bounds__(256) void k_gemm_tn_part(int64_t n, int p, int q,
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int e = tid + 256 * u;
-            As[e % kRB][e / kRB] = ra[u];
+            As[(e % kRB) * AS + e / kRB] = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < NQ; ++u) {
             const int e = tid + 256 * u;
-            Bs[e % kRB][e / kRB] = rb_[u];
+            Bs[(e % kRB) * BS + e / kRB] = rb_[u];
         }
         __syncthreads();
         if (rb + kRB < r1) fetch(rb + kRB);
-#pragma unroll 4
-        for (int rr = 0; rr < kRB; ++rr) {
-            double bv[NQ];
+        // four K steps of four rows; rows past the chunk's end are zero
 #pragma unroll
-            for (int c = 0; c < NQ; ++c) bv[c] = Bs[rr][tx + 16 * c];
+        for (int s4 = 0; s4 < kRB / 4; ++s4) {
+            const int row = 4 * s4 + lk;
+            double bop[NQ];
 #pragma unroll
-            for (int a = 0; a < NA; ++a) {
-                const double av = As[rr][ty + 16 * a];
+            for (int c = 0; c < NQ; ++c) bop[c] = Bs[row * BS + 16 * c + li];
 #pragma unroll
-                for (int c = 0; c < NQ; ++c) acc[a][c] += av * bv[c];
+            for (int t = 0; t < NT; ++t) {
+                const int a = wv + 4 * t;
+                if (a < NA) {
+                    const double aop = As[row * AS + 16 * a + li];
+#pragma unroll
+                    for (int c = 0; c < NQ; ++c)
+                        acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[c], acc[t][c], 0, 0, 0);
+                }
             }
         }
     }
     double *o = part + (int64_t)blockIdx.x * p * q;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        const int i = ty + 16 * a;
+    for (int t = 0; t < NT; ++t) {
+        const int a = wv + 4 * t;
+        if (a >= NA) continue;
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) {
-            const int j = tx + 16 * c;
-            if (i < p && j < q) o[i * q + j] = acc[a][c];
-        }
+        for (int c = 0; c < NQ; ++c)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int i = 16 * a + lk + 4 * m, j = 16 * c + li;
+                if (i < p && j < q) o[i * q + j] = acc[t][c][m];
+            }
     }
 }
 
