@@ -144,14 +144,15 @@ __global__ __launch_bounds__(256) void k_sum_parts(int nparts, int total,
     if (lane == 0) C[e] = s;
 }
 
-// Out[:, j] (=, +=, -=) sum_i A[:, i] C[i][j] for the column group of QG
-// columns in blockIdx.y (C row-major p x q).  mode 0: =, 1: -=.
+// Out[:, j] (=, -=) sum_i A[:, i] C[i][j] for the column group of QG
+// columns in blockIdx.y (C row-major p x q; its p x QG slice in dynamic LDS).
+// mode 0: =, 1: -=.  A thread reads its whole row of A before it writes its
+// row of Out, so with a single column group (q <= QG) Out may be A itself.
 template <int QG>
-__global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int p, int q,
-                                                 const double *__restrict__ A, int64_t lda,
-                                                 const double *__restrict__ C,
-                                                 double *__restrict__ Out, int64_t ldo, int mode) {
-    __shared__ double Cs[kTnMaxP * QG];
+__global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int p, int q, const double *A,
+                                                 int64_t lda, const double *__restrict__ C,
+                                                 double *Out, int64_t ldo, int mode) {
+    extern __shared__ double Cs[];
     const int j0 = blockIdx.y * QG;
     const int qq = (q - j0) < QG ? (q - j0) : QG;
     for (int e = threadIdx.x; e < p * QG; e += 256) {
@@ -537,14 +538,23 @@ struct Lz {
                            part.p, Cout);
         MLG_LAUNCH_CHECK();
     }
+    // Whether nn(p, q, ...) runs as one column group, so that Out may be A
+    // (the product written over the first q columns of A in place).
+    static bool nn_single(int p, int q) { return q <= 32 || (q <= 64 && (size_t)p * 64 * 8 <= 65536); }
     void nn(int p, int q, const double *A, int64_t lda, const double *Cm, double *Out, int64_t ldo,
             int mode) {
+        MLG_REQUIRE(p >= 1 && p <= kTnMaxP && q >= 1, MLG_ERR_ARG, "nn shape");
+        MLG_REQUIRE(Out != A || nn_single(p, q), MLG_ERR_ARG, "nn in place needs one column group");
+        const dim3 t(256);
         if (q <= 16)
-            hipLaunchKernelGGL(k_gemm_nn<16>, dim3(ceil_div(n, 256), 1), dim3(256), 0, s, n, p, q, A,
-                               lda, Cm, Out, ldo, mode);
+            hipLaunchKernelGGL(k_gemm_nn<16>, dim3(ceil_div(n, 256), 1), t, (size_t)p * 16 * 8, s, n, p,
+                               q, A, lda, Cm, Out, ldo, mode);
+        else if (q <= 32 || !nn_single(p, q))
+            hipLaunchKernelGGL(k_gemm_nn<32>, dim3(ceil_div(n, 256), ceil_div(q, 32)), t,
+                               (size_t)p * 32 * 8, s, n, p, q, A, lda, Cm, Out, ldo, mode);
         else
-            hipLaunchKernelGGL(k_gemm_nn<32>, dim3(ceil_div(n, 256), ceil_div(q, 32)), dim3(256), 0, s,
-                               n, p, q, A, lda, Cm, Out, ldo, mode);
+            hipLaunchKernelGGL(k_gemm_nn<64>, dim3(ceil_div(n, 256), 1), t, (size_t)p * 64 * 8, s, n, p,
+                               q, A, lda, Cm, Out, ldo, mode);
         MLG_LAUNCH_CHECK();
     }
     void rowmul(int q, double *W, int64_t ldw, const double *M) {
@@ -733,10 +743,15 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
         hipLaunchKernelGGL(k_select_cols, dim3(ceil_div(m * keep, 256)), dim3(256), 0, s, m, Yd.p,
                            seld.p, keep, Ysel.p);
         MLG_LAUNCH_CHECK();
-        // V[:, :keep] = V[:, :m] Ysel via W-sized chunks of columns into a temp
-        DevBuf<double> tmp((size_t)n * keep);
-        z.nn(m, keep, V.p, n, Ysel.p, tmp.p, n, 0);
-        MLG_HIP(hipMemcpyAsync(V.p, tmp.p, sizeof(double) * n * keep, hipMemcpyDeviceToDevice, s));
+        // V[:, :keep] = V[:, :m] Ysel: in place when one column group covers
+        // keep (each row is read whole before it is written), else via a temp
+        if (Lz::nn_single(m, keep)) {
+            z.nn(m, keep, V.p, n, Ysel.p, V.p, n, 0);
+        } else {
+            DevBuf<double> tmp((size_t)n * keep);
+            z.nn(m, keep, V.p, n, Ysel.p, tmp.p, n, 0);
+            MLG_HIP(hipMemcpyAsync(V.p, tmp.p, sizeof(double) * n * keep, hipMemcpyDeviceToDevice, s));
+        }
         // move Q = V[:, m : m+b] to V[:, keep : keep+b]
         MLG_HIP(hipMemcpyAsync(V.p + (int64_t)keep * n, V.p + (int64_t)m * n, sizeof(double) * n * b,
                                hipMemcpyDeviceToDevice, s));
