@@ -77,6 +77,24 @@ def test_fp32_against_trigonometric_sum(mlg, d, N, sigma):
     assert err <= 2e-5
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_fp64_shortest_grid(mlg, d):
+    """N = 8 (grids of side 16, the shortest FFT lines: one radix-8 and one
+    radix-2 stage) against the trigonometric sum, at the two windows the
+    band margin admits (bin + w / 2 <= N / 2)."""
+    n, b, N, sigma = 2000, 4, 8, 0.5
+    pts = gen.uniform_ball(n, d, 1.0, 1151 + d)
+    X = gen.test_vectors(n, b, 1161 + d)
+    ref = fourier.fourier_sum(pts, sigma, X, N)
+    errs = []
+    for w in (4, 6):
+        case_id("NFFT steps FP64 d=%d N=%d w=%d n=%d" % (d, N, w, n))
+        Y = mlg.kernel_matvec(pts, sigma, X, mlg.kparams("nfft", 64, N=N, window=w))
+        errs.append(rel(Y, ref))
+    case_id("  window errors %s" % ["%.1e" % e for e in errs])
+    assert errs[1] < errs[0] and errs[1] <= 1e-4
+
+
 @pytest.mark.parametrize("prec,w,gate", [(64, 14, 1e-13), (32, 6, 1e-5)])
 def test_operator_symmetry(mlg, prec, w, gate):
     n, d, sigma = 4000, 3, 0.1
