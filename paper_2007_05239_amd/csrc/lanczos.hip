@@ -165,11 +165,25 @@ __global__ __launch_bounds__(256) void k_gemm_nn(int64_t n, int p, int q, const 
     double acc[QG];
 #pragma unroll
     for (int j = 0; j < QG; ++j) acc[j] = 0.0;
-#pragma unroll 4
-    for (int i = 0; i < p; ++i) {
-        const double a = A[r + (int64_t)i * lda];
+    // the next PF entries of the row are loaded while the current PF are
+    // used, so each thread keeps PF loads in flight; the sums still run over
+    // i in ascending order
+    constexpr int PF = 8;
+    double cur[PF], nxt[PF];
 #pragma unroll
-        for (int j = 0; j < QG; ++j) acc[j] += a * Cs[i * QG + j];
+    for (int u = 0; u < PF; ++u) cur[u] = u < p ? A[r + (int64_t)u * lda] : 0.0;
+    for (int i0 = 0; i0 < p; i0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) nxt[u] = i0 + PF + u < p ? A[r + (int64_t)(i0 + PF + u) * lda] : 0.0;
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            if (i0 + u < p) {
+#pragma unroll
+                for (int j = 0; j < QG; ++j) acc[j] += cur[u] * Cs[(i0 + u) * QG + j];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) cur[u] = nxt[u];
     }
 #pragma unroll
     for (int j = 0; j < QG; ++j) {
