@@ -346,8 +346,9 @@ typedef struct {
  *   of 5 products, after one warm-up);
  *   a later candidate (larger N or bin) replaces the current choice only if
  *   it is at least 5 % faster.
- *   Larger bins trade the matrix-core kernels (d = 3 needs bin + w - 1 <= 6)
- *   for fewer, fuller tasks when points are sparse on the grid.
+ *   Larger bins give fewer, fuller tasks when points are sparse on the grid;
+ *   the d = 3 matrix-core kernels take bin + w - 1 <= 7 (bins of 1 or 2 at
+ *   w = 6), wider patches run on the vector ALUs.
  *   points     n x d row-major FP64 (device pointer with MLG_DEVICE_PTRS, else
  *              host), d in 1..3; 2 <= n < 2^31.
  *   precision  32 or 64 (the summation precision of the candidates).

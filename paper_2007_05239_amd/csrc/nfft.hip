@@ -1543,7 +1543,7 @@ struct Cplx<float> { using type = float2; };
 template <>
 struct Cplx<double> { using type = double2; };
 
-// Batched radix-2 FFT of length L = 2^LOGL along one axis of each complex
+// Batched FFT of length L = 2^LOGL along one axis of each complex
 // plane of the grid (plane-major layout: plane q = blockIdx.y, qstr complex
 // entries apart; inside a plane the cells are [z][y][x], x contiguous).  A
 // line is addressed as  off(o) + k S + coff(a),  k = 0..L-1 along the axis:
@@ -2604,7 +2604,7 @@ static int patch_cells(const NfftPlan &P, const NfftWindow &W) {
 }
 
 // The d = 3 matrix-core spreading (FP32, blocks of 16 vectors, patches of
-// at most 6^3 cells) runs the balanced schedule when the plan has one.
+// at most 7^3 cells) runs the balanced schedule when the plan has one.
 static bool uses_spread_schedule(const NfftPlan &P, const NfftWindow &W, int bs) {
     return P.nseg > 0 && P.d == 3 && W.prec == 32 && bs % 16 == 0 &&
            mfma_patch_ok(3, patch_side(P, W));
