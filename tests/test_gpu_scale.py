@@ -261,7 +261,7 @@ def test_cube_52_layers(mlg):
     g = mlg.Graph([device_block(L) for L in c["layers"]], c["sigma"], kp)
     X = gen.test_vectors(n, b, c["base_seed"] + 300)
     Xd = device_block(X)
-    rows = sample_rows(n, 24, c["base_seed"] + 400)
+    rows = sample_rows(n, 256, c["base_seed"] + 400)
     worst = 0.0
     for t in range(T):
         Y = g.laplacian_matvec(t, mlg.MLG_OP_W, Xd).cpu().numpy()
@@ -285,7 +285,7 @@ def test_large_fp32_and_fp64_rows(mlg):
     c = gen.config5()
     n, T = c["n"], len(c["layers"])
     layers = [device_block(L) for L in c["layers"]]
-    rows = sample_rows(n, 16, c["base_seed"] + 400)
+    rows = sample_rows(n, 256, c["base_seed"] + 400)
     b = 16
     X = gen.test_vectors(n, b, c["base_seed"] + 300)
     Xd = device_block(X)
@@ -340,7 +340,7 @@ def test_large_lanczos_30_eigenpairs(mlg):
     res = torch.linalg.norm(LV - V * torch.from_numpy(lam).to(V.device)[None, :], dim=0)
     assert float(res.max()) <= tol * (1 + 1e-3), res
     # the W rows behind that operator, against the oracle (sampled rows)
-    rows = sample_rows(n, 16, c["base_seed"] + 402)
+    rows = sample_rows(n, 128, c["base_seed"] + 402)
     Vh = V[:, :4].cpu().numpy()
     for t in range(T):
         Y = g.laplacian_matvec(t, mlg.MLG_OP_W, V[:, :4].contiguous()).cpu().numpy()
