@@ -19,9 +19,19 @@ namespace mlg {
 static thread_local std::string g_last_error;
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
+// Instantiated graphs refer to the workspaces; they go whenever those move.
+static void drop_captures(Graph &g) {
+    for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
+    g.caps.clear();
+    for (auto &w : g.whole) {
+        (void)hipGraphExecDestroy(w.exec);
+        (void)hipGraphDestroy(w.graph);
+    }
+    g.whole.clear();
+}
+
 Graph::~Graph() {
-    for (auto &c : caps) (void)hipGraphExecDestroy(c.exec);
-    caps.clear();
+    drop_captures(*this);
     if (stream) (void)hipStreamSynchronize(stream);
     for (hipStream_t q : side) {
         (void)hipStreamSynchronize(q);
@@ -75,8 +85,7 @@ static void ensure_ws(Graph &g, int bs) {
         }
     }
     if ((int)g.br.size() != nb) {
-        for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
-        g.caps.clear();
+        drop_captures(g);
         g.br.clear();
         g.br.resize(nb);
         g.ws_bs = 0;
@@ -104,8 +113,7 @@ static void ensure_ws(Graph &g, int bs) {
     for (auto &w : g.br) after.insert(after.end(), {w.patch.p, w.grid.p, w.part.p});
     const bool moved = g.ws_bs != bs || before != after;
     if (!moved) return;
-    for (auto &c : g.caps) (void)hipGraphExecDestroy(c.exec);
-    g.caps.clear();
+    drop_captures(g);
     g.batches.clear();
     g.unbatched.clear();
     g.batch_bs = 0;
@@ -353,8 +361,53 @@ void graph_matvec_enqueue(Graph &g, int layer, int op, int b, const double *X, i
         for (auto &e : tm.ev) (void)hipEventDestroy(e);
         return;
     }
-    graph_core_enqueue(g, layer, use_dinv, b, X, ldx, nullptr, true, false);
-    launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
+    // entry kernel, layer summations and exit kernel as one graph launch
+    if (layer < 0) ensure_batches(g, bs);
+    Graph::WholeCap *w = nullptr;
+    for (auto &c : g.whole)
+        if (c.layer == layer && c.op == op && c.b == b) w = &c;
+    if (!w) {
+        hipGraph_t graph;
+        MLG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            launch_scatter_in(g.n, b, bs, X, ldx, io, nl, use_dinv, s, X32);
+            core(g, layer, bs, nullptr, md, true, s);
+            launch_gather_out(g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv, op == MLG_OP_LSYM, coef, s);
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(s, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        MLG_HIP(hipStreamEndCapture(s, &graph));
+        size_t cnt = 0;
+        hipError_t e = hipGraphGetNodes(graph, nullptr, &cnt);
+        std::vector<hipGraphNode_t> nodes(cnt);
+        if (e == hipSuccess) e = hipGraphGetNodes(graph, nodes.data(), &cnt);
+        hipGraphNode_t in = nullptr, out = nullptr;
+        for (size_t i = 0; e == hipSuccess && i < cnt; ++i) {
+            if (is_scatter_in_node(nodes[i])) in = nodes[i];
+            if (is_gather_out_node(nodes[i])) out = nodes[i];
+        }
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess && (!in || !out)) e = hipErrorInvalidValue;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            MLG_HIP(e);
+        }
+        g.whole.push_back({layer, op, b, graph, exec, in, out, X, ldx, Y, ldy});
+        w = &g.whole.back();
+    } else if (w->X != X || w->ldx != ldx || w->Y != Y || w->ldy != ldy) {
+        set_scatter_in_node(w->exec, w->in_node, g.n, b, bs, X, ldx, io, nl, use_dinv, X32);
+        set_gather_out_node(w->exec, w->out_node, g.n, b, bs, X, ldx, Y, ldy, io, nl, use_dinv,
+                            op == MLG_OP_LSYM, coef);
+        w->X = X;
+        w->ldx = ldx;
+        w->Y = Y;
+        w->ldy = ldy;
+    }
+    MLG_HIP(hipGraphLaunch(w->exec, s));
 }
 
 const LayerIO *graph_layer_io(Graph &g, int b, int t) {

@@ -105,6 +105,17 @@ void launch_scatter_in(int64_t n, int b, int bs, const double *X, int64_t ldx, c
 void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, double *Y,
                        int64_t ldy, const LayerIO *L, int nl, int use_dinv, int lsym, double coef,
                        hipStream_t s);
+// Graph nodes captured from the two launches above: whether a kernel node is
+// one of them, and re-pointing it at other X (and Y) blocks in an
+// instantiated graph (same shapes and layer tables as when captured).
+bool is_scatter_in_node(hipGraphNode_t node);
+bool is_gather_out_node(hipGraphNode_t node);
+void set_scatter_in_node(hipGraphExec_t e, hipGraphNode_t node, int64_t n, int b, int bs,
+                         const double *X, int64_t ldx, const LayerIO *L, int nl, int use_dinv,
+                         float *X32);
+void set_gather_out_node(hipGraphExec_t e, hipGraphNode_t node, int64_t n, int b, int bs,
+                         const double *X, int64_t ldx, double *Y, int64_t ldy, const LayerIO *L,
+                         int nl, int use_dinv, int lsym, double coef);
 void launch_fill_ones(int64_t n, double *Xr, hipStream_t s);
 void launch_check_degrees(int64_t n, const double *deg, double thresh, int *flag, hipStream_t s);
 void launch_dinv(int64_t n, const double *deg, double *dinv, hipStream_t s);
@@ -326,6 +337,20 @@ struct Graph {
         hipGraphExec_t exec;
     };
     std::vector<Cap> caps;
+    // whole products (entry kernel, layer summations, exit kernel) as one
+    // captured graph per (layer, op, b); the entry and exit nodes are
+    // re-pointed in the instantiated graph when X or Y change
+    struct WholeCap {
+        int layer, op, b;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+        hipGraphNode_t in_node, out_node;
+        const double *X;
+        int64_t ldx;
+        double *Y;
+        int64_t ldy;
+    };
+    std::vector<WholeCap> whole;
     ~Graph();
 };
 

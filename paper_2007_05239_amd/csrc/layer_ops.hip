@@ -278,6 +278,48 @@ void launch_gather_out(int64_t n, int b, int bs, const double *X, int64_t ldx, d
     MLG_LAUNCH_CHECK();
 }
 
+static bool node_runs(hipGraphNode_t node, const void *fn) {
+    hipGraphNodeType t;
+    if (hipGraphNodeGetType(node, &t) != hipSuccess || t != hipGraphNodeTypeKernel) return false;
+    hipKernelNodeParams p{};
+    MLG_HIP(hipGraphKernelNodeGetParams(node, &p));
+    return p.func == fn;
+}
+
+bool is_scatter_in_node(hipGraphNode_t node) {
+    return node_runs(node, reinterpret_cast<const void *>(&k_scatter_in));
+}
+
+bool is_gather_out_node(hipGraphNode_t node) {
+    return node_runs(node, reinterpret_cast<const void *>(&k_gather_out));
+}
+
+// The argument lists below follow the kernels' parameter lists exactly (types
+// included); the grid, block and function come from the captured node.
+void set_scatter_in_node(hipGraphExec_t e, hipGraphNode_t node, int64_t n, int b, int bs,
+                         const double *X, int64_t ldx, const LayerIO *L, int nl, int use_dinv,
+                         float *X32) {
+    hipKernelNodeParams p{};
+    MLG_HIP(hipGraphKernelNodeGetParams(node, &p));
+    void *args[] = {&n, &b, &bs, &X, &ldx, &L, &nl, &use_dinv, &X32};
+    p.kernelParams = args;
+    p.extra = nullptr;
+    MLG_HIP(hipGraphExecKernelNodeSetParams(e, node, &p));
+}
+
+void set_gather_out_node(hipGraphExec_t e, hipGraphNode_t node, int64_t n, int b, int bs,
+                         const double *X, int64_t ldx, double *Y, int64_t ldy, const LayerIO *L,
+                         int nl, int use_dinv, int lsym, double coef) {
+    hipKernelNodeParams p{};
+    MLG_HIP(hipGraphKernelNodeGetParams(node, &p));
+    int lng = 0;
+    while ((kOutVG << lng) < bs) ++lng;
+    void *args[] = {&n, &b, &bs, &lng, &X, &ldx, &Y, &ldy, &L, &nl, &use_dinv, &lsym, &coef};
+    p.kernelParams = args;
+    p.extra = nullptr;
+    MLG_HIP(hipGraphExecKernelNodeSetParams(e, node, &p));
+}
+
 void launch_fill_ones(int64_t n, double *Xr, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_ones, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, Xr);
     MLG_LAUNCH_CHECK();

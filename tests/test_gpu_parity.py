@@ -402,6 +402,48 @@ def test_nfft_fp32_heavy_bin_two_level_reduction(mlg):
 
 
 # ---------------------------------------------------------------------------
+# the whole product (entry, layer summations, exit) as one captured graph
+# whose entry and exit nodes are re-pointed when X or Y change
+# ---------------------------------------------------------------------------
+def test_whole_product_graph_replays(mlg):
+    """Products on alternating X and Y buffers enqueued back to back without
+    synchronisation (each launch re-points the graph's entry and exit nodes
+    while earlier launches may still be queued), then eager work, three
+    times over: every result equal bit for bit to the product computed
+    without the graph (layers one after another)."""
+    import torch
+    n, b = 5000, 16
+    p3a = gen.gaussian_mixture(n, 3, 3, 0.08, 1231)[0]
+    p2 = gen.uniform_ball(n, 2, 1.0, 1232)
+    p3b = gen.gaussian_mixture(n, 3, 4, 0.06, 1233)[0]
+    pts, sig = [p3a, p2, p3b], [0.3, 0.35, 0.25]
+    g = mlg.Graph(pts, sig, [mlg.kparams("nfft", 32, N=32, window=6) for _ in pts])
+    Xs = [torch.from_numpy(np.ascontiguousarray(gen.test_vectors(n, b, 1240 + i))).to("cuda")
+          for i in range(3)]
+    refs = [g.profile_stages(-1, mlg.MLG_OP_LSYM, X, reps=1, return_y=True)[1].cpu().numpy()
+            for X in Xs]
+    Xc = [X.t().contiguous() for X in Xs]
+    plan = [(0, 0), (1, 1), (2, 2), (0, 3), (2, 0)]   # (input, output buffer)
+    for rnd in range(3):
+        Yc = [torch.full((b, n), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4)]
+        torch.cuda.synchronize()
+        case_id("whole-product graph, round %d: %d products without synchronisation" % (rnd, len(plan)))
+        for xi, yi in plan:
+            g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc[xi], Yc[yi], sync=False)
+        torch.cuda.synchronize()
+        # buffer 0 was written twice (inputs 0, then 2): it holds the last
+        assert np.array_equal(Yc[0].t().cpu().numpy(), refs[2])
+        assert np.array_equal(Yc[1].t().cpu().numpy(), refs[1])
+        assert np.array_equal(Yc[2].t().cpu().numpy(), refs[2])
+        assert np.array_equal(Yc[3].t().cpu().numpy(), refs[0])
+        # eager work between the rounds: a one-layer product and a torch op
+        g.laplacian_matvec(0, mlg.MLG_OP_W, Xs[1][:, :4].contiguous())
+        Xs[1].mul_(1.0)
+        torch.cuda.synchronize()
+    g.close()
+
+
+# ---------------------------------------------------------------------------
 # batched layers: more FP32 matrix-core layers of one dimension and patch
 # edge than branches run as one launch per stage (uneven N grouped for the
 # FFT)
