@@ -200,8 +200,12 @@ mlg_status mlg_kernel_matvec(int64_t n, int d, const double *points, double sigm
  * Y = op X with op one of MLG_OP_* for layer `layer` (0..T-1), or for the
  * layer mean (layer = -1, p = 1 power mean of Sec. 2 eq. (1) and Sec. 3).
  * b: 1..64 vectors.  X and Y must not overlap.  The first call for a given
- * (layer, op, b) captures the launch sequence into a HIP graph; later calls
- * replay it.
+ * (layer, op, b) captures the whole launch sequence (entry kernel, the
+ * layers' summations, exit kernel) into one HIP graph; later calls replay
+ * it, re-pointing its entry and exit kernels when X, Y or their leading
+ * dimensions differ from the previous call's (launches already enqueued keep
+ * the buffers they were given).  With device pointers the call only
+ * enqueues on the graph's stream.
  */
 mlg_status mlg_laplacian_matvec(mlg_graph *g, int layer, int op, int b, const double *X,
                                 int64_t ldx, double *Y, int64_t ldy, int flags);
