@@ -393,11 +393,13 @@ def cube_leg(steps=20):
     Xc = X.t().contiguous()
     Yc = torch.empty_like(Xc)
     for _ in range(3):
-        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False, wait=False)
+    g.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False, wait=False)
+    g.synchronize()
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
     g.close()
@@ -477,12 +479,16 @@ def main():
         return
     Xc = X.t().contiguous()                 # column-major n x b block, resident in HBM
     Yc = torch.empty_like(Xc)
+    # steps enqueued back to back (MLG_ASYNC): every step is a whole product
+    # from X to Y, with no host round trip between steps
     for _ in range(a.warmup):
-        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False, wait=False)
+    g.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False)
+        g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc, Yc, sync=False, wait=False)
+    g.synchronize()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = el / a.steps * 1e3

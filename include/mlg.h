@@ -30,7 +30,7 @@
  *  - Work is enqueued on the HIP stream given at creation (NULL = a
  *    non-blocking stream the handle creates and owns) and the call returns
  *    after that stream has drained, so device outputs are ready when it
- *    returns.
+ *    returns (except mlg_laplacian_matvec with MLG_ASYNC).
  *  - One handle must not be used from two threads at once.
  *  - Same inputs and same parameters give bit-identical outputs: no kernel
  *    accumulates floating point through atomics.
@@ -62,6 +62,13 @@ typedef enum {
  * products only (degree-normalised operators, degrees and Lanczos return
  * MLG_ERR_ARG). */
 #define MLG_SKIP_DEGREES 2
+/* mlg_laplacian_matvec with MLG_DEVICE_PTRS: enqueue the product on the
+ * graph's stream and return without waiting for it, so that back-to-back
+ * products leave no host round trip between them.  Y is ready, and X may be
+ * overwritten, once that stream has drained (mlg_graph_synchronize, or the
+ * caller's own stream given at creation); a kernel error then surfaces there.
+ * Ignored for host pointers. */
+#define MLG_ASYNC 4
 
 /* summation method */
 #define MLG_METHOD_DIRECT 0 /* O(n^2) tiled direct sum (Sec. 2 case (i))       */
@@ -184,6 +191,11 @@ mlg_status mlg_median_pairwise_distance(int64_t n, int D, const double *features
                                         double *sigma, int flags, void *stream);
 
 mlg_status mlg_graph_destroy(mlg_graph *g);
+
+/* Wait until all work enqueued on the graph's stream has finished (for
+ * products enqueued with MLG_ASYNC); reports a failed kernel of that work as
+ * MLG_ERR_HIP. */
+mlg_status mlg_graph_synchronize(mlg_graph *g);
 
 /* Copy layer `layer`'s degrees deg(x_i) (Sec. 2) into deg (n FP64). */
 mlg_status mlg_graph_degrees(mlg_graph *g, int layer, double *deg, int flags);

@@ -782,7 +782,7 @@ mlg_status mlg_laplacian_matvec(mlg_graph *h, int layer, int op, int b, const do
         MLG_REQUIRE(ldx >= g.n && ldy >= g.n, MLG_ERR_ARG, "leading dimension < n");
         if (flags & MLG_DEVICE_PTRS) {
             graph_matvec_enqueue(g, layer, op, b, X, ldx, Y, ldy, nullptr);
-            MLG_HIP(hipStreamSynchronize(g.stream));
+            if (!(flags & MLG_ASYNC)) MLG_HIP(hipStreamSynchronize(g.stream));
             return;
         }
         DevBuf<double> dX((size_t)g.n * b), dY((size_t)g.n * b);
@@ -790,6 +790,13 @@ mlg_status mlg_laplacian_matvec(mlg_graph *h, int layer, int op, int b, const do
         graph_matvec_enqueue(g, layer, op, b, dX.p, g.n, dY.p, g.n, nullptr);
         copy_cols(Y, ldy, dY.p, g.n, g.n, b, hipMemcpyDeviceToHost, g.stream);
         MLG_HIP(hipStreamSynchronize(g.stream));
+    });
+}
+
+mlg_status mlg_graph_synchronize(mlg_graph *h) {
+    return guard([&] {
+        MLG_REQUIRE(h, MLG_ERR_ARG, "null argument");
+        MLG_HIP(hipStreamSynchronize(h->g.stream));
     });
 }
 

@@ -25,6 +25,7 @@ MLG_ERR_HIP = -5
 MLG_ERR_NOT_IMPL = -6
 
 MLG_DEVICE_PTRS = 1
+MLG_ASYNC = 4
 MLG_SKIP_DEGREES = 2
 MLG_METHOD_DIRECT = 0
 MLG_METHOD_NFFT = 1
@@ -38,7 +39,7 @@ STAGES = ["scatter_in", "spread", "gather", "fft", "interp", "gather_out", "dire
 
 EXPORTED = ["mlg_last_error", "mlg_version", "mlg_graph_create", "mlg_graph_create_grouped",
             "mlg_median_pairwise_distance", "mlg_graph_destroy",
-            "mlg_graph_degrees", "mlg_kernel_matvec", "mlg_laplacian_matvec",
+            "mlg_graph_degrees", "mlg_graph_synchronize", "mlg_kernel_matvec", "mlg_laplacian_matvec",
             "mlg_lanczos_eigs", "mlg_power_mean_matvec", "mlg_allen_cahn_ssl",
             "mlg_profile_stages", "mlg_graph_layer_info", "mlg_autotune_layer",
             "mlg_kernel_matvec_noalloc"]
@@ -105,6 +106,7 @@ def _load():
         "mlg_kernel_matvec_noalloc": ([i64, I, P, ctypes.c_double, ctypes.POINTER(KParams), I, P,
                                        i64, P, i64, P], I),
         "mlg_laplacian_matvec": ([P, I, I, I, P, i64, P, i64, I], I),
+        "mlg_graph_synchronize": ([P], I),
         "mlg_lanczos_eigs": ([P, I, ctypes.c_double, I, I, ctypes.c_double, I, ctypes.c_uint64, P,
                               P, P, i64, ctypes.POINTER(EigInfo), ctypes.POINTER(PksmParams), I],
                              I),
@@ -346,15 +348,22 @@ class Graph:
         _check(_lib.mlg_laplacian_matvec(self._h, layer, op, b, _ptr(Xc)[0], n, _ptr(Y)[0], n, 0))
         return Y
 
-    def laplacian_matvec_into(self, layer, op, Xc, Yc, sync=True):
+    def laplacian_matvec_into(self, layer, op, Xc, Yc, sync=True, wait=True):
         """Device-only form: Xc, Yc are b x n contiguous CUDA tensors, i.e. the
-        column-major n x b blocks the C ABI takes; no copies are made."""
+        column-major n x b blocks the C ABI takes; no copies are made.  sync:
+        wait for torch's pending work first; wait=False: enqueue only
+        (MLG_ASYNC), Yc is ready after synchronize()."""
         b, n = Xc.shape
         if sync:
             _sync()
+        flags = MLG_DEVICE_PTRS | (0 if wait else MLG_ASYNC)
         _check(_lib.mlg_laplacian_matvec(self._h, layer, op, b, _ptr(Xc)[0], n, _ptr(Yc)[0], n,
-                                         MLG_DEVICE_PTRS))
+                                         flags))
         return Yc
+
+    def synchronize(self):
+        """Wait for the products enqueued with wait=False (mlg_graph_synchronize)."""
+        _check(_lib.mlg_graph_synchronize(self._h))
 
     def profile_stages(self, layer, op, X, reps=5, return_y=False):
         """Average ms per matvec in each stage (dict), device tensors only;

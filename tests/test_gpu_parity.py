@@ -406,11 +406,12 @@ def test_nfft_fp32_heavy_bin_two_level_reduction(mlg):
 # whose entry and exit nodes are re-pointed when X or Y change
 # ---------------------------------------------------------------------------
 def test_whole_product_graph_replays(mlg):
-    """Products on alternating X and Y buffers enqueued back to back without
-    synchronisation (each launch re-points the graph's entry and exit nodes
-    while earlier launches may still be queued), then eager work, three
-    times over: every result equal bit for bit to the product computed
-    without the graph (layers one after another)."""
+    """Products on alternating X and Y buffers enqueued back to back with
+    MLG_ASYNC (each call re-points the graph's entry and exit nodes while
+    earlier launches are still queued), then eager work, three times over;
+    and the same sequence waiting for each product: every result equal bit
+    for bit to the product computed without the graph (layers one after
+    another)."""
     import torch
     n, b = 5000, 16
     p3a = gen.gaussian_mixture(n, 3, 3, 0.08, 1231)[0]
@@ -424,12 +425,14 @@ def test_whole_product_graph_replays(mlg):
             for X in Xs]
     Xc = [X.t().contiguous() for X in Xs]
     plan = [(0, 0), (1, 1), (2, 2), (0, 3), (2, 0)]   # (input, output buffer)
-    for rnd in range(3):
+    for rnd in range(4):
         Yc = [torch.full((b, n), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4)]
         torch.cuda.synchronize()
-        case_id("whole-product graph, round %d: %d products without synchronisation" % (rnd, len(plan)))
+        wait = rnd == 3
+        case_id("whole-product graph, round %d: %d products, wait=%s" % (rnd, len(plan), wait))
         for xi, yi in plan:
-            g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc[xi], Yc[yi], sync=False)
+            g.laplacian_matvec_into(-1, mlg.MLG_OP_LSYM, Xc[xi], Yc[yi], sync=False, wait=wait)
+        g.synchronize()
         torch.cuda.synchronize()
         # buffer 0 was written twice (inputs 0, then 2): it holds the last
         assert np.array_equal(Yc[0].t().cpu().numpy(), refs[2])
