@@ -156,24 +156,11 @@ __global__ __launch_bounds__(256) void k_ac_zr(int64_t n, int k, int m, const do
     }
 }
 
-// One level of the pairwise tree: dst[j] = src[2j] + src[2j+1]; an odd last
-// element is copied.
-__global__ void k_ac_tree(int64_t cnt, int len, const double *__restrict__ src,
-                          double *__restrict__ dst) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t half = cnt / 2, outc = half + (cnt & 1);
-    if (e >= outc * len) return;
-    const int64_t j = e / len;
-    const int x = (int)(e - j * len);
-    if (j < half)
-        dst[e] = src[(2 * j) * len + x] + src[(2 * j + 1) * len + x];
-    else
-        dst[e] = src[(cnt - 1) * len + x];
-}
-
-// Four levels of the same tree in one pass: dst[j] is node j four levels
-// above src (cnt nodes), formed from its up to 16 leaves with exactly the
-// pairs and odd-element copies of four one-level passes.
+// The pairwise tree over chunk partials: each level forms node j from nodes
+// 2j and 2j+1 of the level below (src[2j] + src[2j+1]); an odd last node is
+// copied up.  One pass does four levels: dst[j] is node j four levels above
+// src (cnt nodes), formed from its up to 16 leaves with exactly those pairs
+// and copies.
 __global__ void k_ac_tree4(int64_t cnt, int len, const double *__restrict__ src,
                            double *__restrict__ dst) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -205,18 +192,14 @@ __global__ void k_ac_tree4(int64_t cnt, int len, const double *__restrict__ src,
 }
 
 // Reduce cnt rows of len doubles at src to one by the pairwise tree, using dst
-// as the other buffer; returns the buffer that holds the result.
+// as the other buffer; returns the buffer that holds the result.  Four levels
+// per launch at every count (below 16 rows the pass ends in one row).
 static double *ac_tree_reduce(int64_t cnt, int len, double *src, double *dst, hipStream_t s) {
     while (cnt > 1) {
-        int64_t outc = cnt / 2 + (cnt & 1);
-        if (cnt >= 16) {
-            for (int l = 1; l < 4; ++l) outc = outc / 2 + (outc & 1);
-            hipLaunchKernelGGL(k_ac_tree4, dim3(ceil_div(outc * len, 256)), dim3(256), 0, s, cnt, len,
-                               src, dst);
-        } else {
-            hipLaunchKernelGGL(k_ac_tree, dim3(ceil_div(outc * len, 256)), dim3(256), 0, s, cnt, len,
-                               src, dst);
-        }
+        int64_t outc = cnt;
+        for (int l = 0; l < 4; ++l) outc = outc / 2 + (outc & 1);
+        hipLaunchKernelGGL(k_ac_tree4, dim3(ceil_div(outc * len, 256)), dim3(256), 0, s, cnt, len,
+                           src, dst);
         MLG_LAUNCH_CHECK();
         std::swap(src, dst);
         cnt = outc;
@@ -594,9 +577,11 @@ static void ac_run_fused(int64_t n, int k, int m, const double *evals, const dou
                                       s, n, k, m, Pc.p, Zc.p, nullptr, U, labels, onepcdt, coefT,
                                       prm.dt, prm.omega0, pa.p, mxd.p, mxn.p));
     MLG_LAUNCH_CHECK();
-    int l = 0;
-    double rc = 0.0;
-    do {
+    // one step: tree over the chunk partials, the fused step, the change
+    // maximum.  The same launches with the same buffers every step, so they
+    // are captured once and replayed (no memset nodes: the step writes every
+    // value it later reads).
+    auto step = [&]() {
         double *src = ac_tree_reduce(nch, k * m, pa.p, pb.p, s);
         // src holds V; the step overwrites pa with the next partials
         double *Vd = src;
@@ -612,6 +597,33 @@ static void ac_run_fused(int64_t n, int k, int m, const double *evals, const dou
         MLG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_ac_finish_max, dim3(1), dim3(64), 0, s, nmx, mx.p, rcd.p);
         MLG_LAUNCH_CHECK();
+    };
+    struct GraphExec {
+        hipGraphExec_t e = nullptr;
+        ~GraphExec() {
+            if (e) (void)hipGraphExecDestroy(e);
+        }
+    } gx;
+    {
+        hipGraph_t graph;
+        MLG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            step();
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(s, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            throw;
+        }
+        MLG_HIP(hipStreamEndCapture(s, &graph));
+        const hipError_t e = hipGraphInstantiate(&gx.e, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        MLG_HIP(e);
+    }
+    int l = 0;
+    double rc = 0.0;
+    do {
+        MLG_HIP(hipGraphLaunch(gx.e, s));
         MLG_HIP(hipMemcpyAsync(&rc, rcd.p, 8, hipMemcpyDeviceToHost, s));
         MLG_HIP(hipStreamSynchronize(s));
         l = l + 1;
