@@ -382,7 +382,9 @@ def cube_leg(steps=20):
     from workloads import gen
     c = gen.config4()
     n, T, b = c["n"], len(c["layers"]), 16
-    kp = [mlg.kparams("nfft", 32, N=c["N"][t], window=6) for t in range(T)]
+    # bins chosen by the plan (bin = 0): the N = 128 layers' occupied bins
+    # hold about 125 points at one cell per bin, and take bins of 2
+    kp = [mlg.kparams("nfft", 32, N=c["N"][t], window=6, bin=0) for t in range(T)]
     layers = [torch.from_numpy(L).to("cuda") for L in c["layers"]]
     t0 = time.perf_counter()
     g = mlg.Graph(layers, c["sigma"], kp)
@@ -405,7 +407,9 @@ def cube_leg(steps=20):
     g.close()
     sr = step_roofline(infos, n, b, el)
     sr.pop("layers")
+    bins = [i["bin"] for i in infos]
     return {"workload": "hyperspectral512x512_52layer_L1_block16", "n": n, "layers": T, "block": b,
+            "bins": {str(k): bins.count(k) for k in sorted(set(bins))},
             "graph_create_s": round(plan, 3), "ms_per_step": round(el * 1e3, 4),
             "rows_per_s": n * T * b / el, "step_roofline": sr}
 

@@ -99,8 +99,15 @@ typedef enum {
  *              bin + w/2 <= N/2 (0 = 6 for precision 32, 12 for precision 64).
  *   eps_B      regularisation length of the periodised kernel, 0 < eps_B < 1/4.
  *   p_reg      smoothness degree of the regularisation, 1..12.
- *   bin        bin edge in grid cells used to group points (1, 2 or 4;
- *              0 = 1).
+ *   bin        bin edge in grid cells used to group points (1, 2 or 4),
+ *              or 0: automatic.  For precision 32 the plan starts at 1 and
+ *              doubles the edge (up to 4) while the occupied bins hold fewer
+ *              than 256 points on average, as long as bin + w/2 <= N/2 and
+ *              the patch edge bin + w - 1 stays within the matrix-core
+ *              kernels (7 in d = 3, 12 in d = 2, 16 in d = 1); precision 64
+ *              takes 1.  The bin only groups points, so the result differs
+ *              from another bin's by rounding alone; mlg_graph_layer_info
+ *              reports the edge chosen.
  *   kernel     MLG_KERNEL_GAUSSIAN (0) or MLG_KERNEL_LAPLACIAN.  The
  *              Laplacian RBF has a cusp at the origin, so its Fourier
  *              coefficients decay only algebraically and Algorithm 1 (no

@@ -1495,6 +1495,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P <= 6 ? 3 :
 }
 
 // Patch edges with a compiled matrix-core variant, per dimension.
+// Mean points per occupied bin below which an automatic bin edge doubles
+// (four 64-point matrix-core chunks).
+constexpr int64_t kAutoBinPoints = 256;
+
 static bool mfma_patch_ok(int D, int P) {
     if (P < 2) return false;
     if (D == 3) return P <= 7;
@@ -2332,8 +2336,9 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     MLG_REQUIRE(n < (int64_t)1 << 31, MLG_ERR_RANGE, "NFFT layers need n < 2^31");
     P.d = d;
     P.n = n;
+    MLG_REQUIRE(L.kp.bin == 0 || L.kp.bin == 1 || L.kp.bin == 2 || L.kp.bin == 4, MLG_ERR_RANGE,
+                "bin must be 0 (automatic), 1, 2 or 4");
     P.B = L.kp.bin > 0 ? L.kp.bin : 1;
-    MLG_REQUIRE(P.B == 1 || P.B == 2 || P.B == 4, MLG_ERR_RANGE, "bin must be 1, 2 or 4");
     P.eps_B = L.kp.eps_B;
     P.p_reg = L.kp.p_reg;
 
@@ -2379,46 +2384,64 @@ void nfft_plan_layer(Layer &L, const double *pts, hipStream_t s) {
     P.sigma_s = P.scale * L.sigma;
     P.N = L.kp.N > 0 ? L.kp.N : nfft_auto_bandwidth(P.sigma_s, d, L.kp.precision);
     P.nos = 2 * P.N;
-    P.nb = P.nos / P.B;
-    P.nbins = 1;
-    for (int t = 0; t < d; ++t) P.nbins *= P.nb;
 
-    // --- grid coordinates, keys, sort ---
+    // --- grid coordinates, keys, sort, runs of equal bins (for bin edge P.B) ---
     DevBuf<double> uun((size_t)d * n);
     DevBuf<unsigned> keys(n), skeys(n);
     DevBuf<int> idx(n);
     P.perm.alloc(n);
-    hipLaunchKernelGGL(k_coords_keys, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, pts,
-                       P.center[0], P.center[1], P.center[2], P.scale, P.nos, P.B, P.nb, uun.p,
-                       keys.p, idx.p);
-    MLG_LAUNCH_CHECK();
-    unsigned endbit = 1;
-    while (((int64_t)1 << endbit) < P.nbins) ++endbit;
-    DevBuf<char> tmp;
-    size_t tbytes = 0;
-    MLG_HIP(rocprim::radix_sort_pairs(nullptr, tbytes, keys.p, skeys.p, idx.p, P.perm.p,
-                                      (unsigned)n, 0u, endbit, s));
-    tmp.ensure(tbytes + 1);
-    MLG_HIP(rocprim::radix_sort_pairs(tmp.p, tbytes, keys.p, skeys.p, idx.p, P.perm.p,
-                                      (unsigned)n, 0u, endbit, s));
     P.u64.alloc((size_t)d * n);
     P.c32.alloc((size_t)d * n);
     P.f32.alloc((size_t)d * n);
-    hipLaunchKernelGGL(k_gather_coords, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, P.nos, uun.p,
-                       P.perm.p, P.u64.p, P.c32.p, P.f32.p);
-    MLG_LAUNCH_CHECK();
-
-    // --- runs of equal bins -> tasks ---
     DevBuf<unsigned> ukeys(n), counts(n), runs_dev(1);
-    tbytes = 0;
-    MLG_HIP(rocprim::run_length_encode(nullptr, tbytes, skeys.p, (unsigned)n, ukeys.p, counts.p,
-                                       runs_dev.p, s));
-    tmp.ensure(tbytes + 1);
-    MLG_HIP(rocprim::run_length_encode(tmp.p, tbytes, skeys.p, (unsigned)n, ukeys.p, counts.p,
-                                       runs_dev.p, s));
-    unsigned runs = 0;
-    MLG_HIP(hipMemcpyAsync(&runs, runs_dev.p, 4, hipMemcpyDeviceToHost, s));
-    MLG_HIP(hipStreamSynchronize(s));
+    DevBuf<char> tmp;
+    auto sort_bins = [&]() -> unsigned {
+        P.nb = P.nos / P.B;
+        P.nbins = 1;
+        for (int t = 0; t < d; ++t) P.nbins *= P.nb;
+        hipLaunchKernelGGL(k_coords_keys, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, pts,
+                           P.center[0], P.center[1], P.center[2], P.scale, P.nos, P.B, P.nb, uun.p,
+                           keys.p, idx.p);
+        MLG_LAUNCH_CHECK();
+        unsigned endbit = 1;
+        while (((int64_t)1 << endbit) < P.nbins) ++endbit;
+        size_t tbytes = 0;
+        MLG_HIP(rocprim::radix_sort_pairs(nullptr, tbytes, keys.p, skeys.p, idx.p, P.perm.p,
+                                          (unsigned)n, 0u, endbit, s));
+        tmp.ensure(tbytes + 1);
+        MLG_HIP(rocprim::radix_sort_pairs(tmp.p, tbytes, keys.p, skeys.p, idx.p, P.perm.p,
+                                          (unsigned)n, 0u, endbit, s));
+        hipLaunchKernelGGL(k_gather_coords, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, d, P.nos,
+                           uun.p, P.perm.p, P.u64.p, P.c32.p, P.f32.p);
+        MLG_LAUNCH_CHECK();
+        tbytes = 0;
+        MLG_HIP(rocprim::run_length_encode(nullptr, tbytes, skeys.p, (unsigned)n, ukeys.p, counts.p,
+                                           runs_dev.p, s));
+        tmp.ensure(tbytes + 1);
+        MLG_HIP(rocprim::run_length_encode(tmp.p, tbytes, skeys.p, (unsigned)n, ukeys.p, counts.p,
+                                           runs_dev.p, s));
+        unsigned r = 0;
+        MLG_HIP(hipMemcpyAsync(&r, runs_dev.p, 4, hipMemcpyDeviceToHost, s));
+        MLG_HIP(hipStreamSynchronize(s));
+        return r;
+    };
+    unsigned runs = sort_bins();
+    // Automatic bin edge (FP32): every occupied bin costs a patch and at
+    // least one 64-point chunk of matrix-core work, so the edge doubles
+    // while the occupied bins hold fewer than kAutoBinPoints points on
+    // average and the larger patch still fits the matrix-core kernels and
+    // the bandwidth (bin + w/2 <= N/2).  Only the grouping of points
+    // changes, not what is summed.
+    if (L.kp.bin == 0 && L.kp.precision == 32) {
+        const int w = L.kp.window > 0 ? L.kp.window : 6;
+        while (P.B < 4 && (int64_t)n < kAutoBinPoints * (int64_t)runs) {
+            const int B2 = 2 * P.B;
+            if (B2 + w / 2 > P.N / 2 || !mfma_patch_ok(d, B2 + w - 1)) break;
+            P.B = B2;
+            runs = sort_bins();
+        }
+    }
+
     DevBuf<unsigned> run_start(runs + 1), ntask(runs + 1), task_first(runs + 1), scr(runs + 1),
         scr_first(runs + 1), ism(runs + 1), multi_idx(runs + 1);
     auto xscan = [&](const unsigned *in, unsigned *out, size_t cnt) {

@@ -141,6 +141,43 @@ def test_nfft_bins(mlg, bin_, prec, window, gate, d):
     assert rel_err(Y, oracle.lsym_matvec([L], X)) <= gate
 
 
+@pytest.mark.parametrize("d,N,n,sig,expect", [(2, 128, 6000, 0.3, 4), (3, 64, 6000, 0.3, 2),
+                                               (2, 16, 60000, 1.0, 1)])
+def test_nfft_fp32_automatic_bin(mlg, d, N, n, sig, expect):
+    """bin = 0: the plan doubles the bin edge while occupied bins hold fewer
+    than 256 points on average, within the matrix-core patch limits (d = 3
+    stops at 2: patch edge 7).  Sparse layers end at 4 (d = 2) and 2 (d = 3),
+    a dense one stays at 1.  The product matches the oracle at the FP32 gate,
+    is bit-identical to the explicit bin's plan and differs from bin 1 by
+    FP32 rounding only."""
+    pts = gen.uniform_ball(n, d, 1.0, 1301 + d)
+    X = gen.test_vectors(n, 16, 1305 + d)
+    L = oracle.Layer(pts, sig)
+    case_id("nfft fp32 L_sym automatic bin d=%d N=%d n=%d b=16" % (d, N, n))
+    g = mlg.Graph([pts], [sig], mlg.kparams("nfft", 32, N=N, window=6, bin=0))
+    assert g.layer_info(0)["bin"] == expect
+    Y = g.laplacian_matvec(0, mlg.MLG_OP_LSYM, X)
+    g.close()
+    assert rel_err(Y, oracle.lsym_matvec([L], X)) <= 1e-4
+    case_id("  explicit bin=%d and bin=1 plans" % expect)
+    ge = mlg.Graph([pts], [sig], mlg.kparams("nfft", 32, N=N, window=6, bin=expect))
+    Ye = ge.laplacian_matvec(0, mlg.MLG_OP_LSYM, X)
+    ge.close()
+    assert np.array_equal(Y, Ye)
+    g1 = mlg.Graph([pts], [sig], mlg.kparams("nfft", 32, N=N, window=6, bin=1))
+    Y1 = g1.laplacian_matvec(0, mlg.MLG_OP_LSYM, X)
+    g1.close()
+    assert rel_err(Y, Y1) <= 2e-6
+
+
+def test_nfft_fp64_automatic_bin_is_one(mlg):
+    """bin = 0 with precision 64 plans bins of one cell."""
+    pts = gen.uniform_ball(3000, 2, 1.0, 1311)
+    g = mlg.Graph([pts], [0.3], mlg.kparams("nfft", 64, N=128, window=12, bin=0))
+    assert g.layer_info(0)["bin"] == 1
+    g.close()
+
+
 @pytest.mark.parametrize("b", [16, 32])
 def test_nfft_fp32_bin2_matrix_core(mlg, b):
     """d = 3, bin 2, window 6: patches of 7^3 cells on the matrix-core

@@ -257,8 +257,12 @@ def test_image_lanczos_negative_p(mlg, image, image_graph):
 def test_cube_52_layers(mlg):
     c = gen.config4()
     n, T, b = c["n"], len(c["layers"]), 16
-    kp = [mlg.kparams("nfft", 32, N=c["N"][t], window=6) for t in range(T)]
+    # bins chosen by the plan, as in the benchmark's cube product
+    kp = [mlg.kparams("nfft", 32, N=c["N"][t], window=6, bin=0) for t in range(T)]
     g = mlg.Graph([device_block(L) for L in c["layers"]], c["sigma"], kp)
+    bins = [g.layer_info(t)["bin"] for t in range(T)]
+    case_id("cube bins chosen: %s" % {k: bins.count(k) for k in sorted(set(bins))})
+    assert set(bins) <= {1, 2, 4}
     X = gen.test_vectors(n, b, c["base_seed"] + 300)
     Xd = device_block(X)
     rows = sample_rows(n, 256, c["base_seed"] + 400)
