@@ -383,7 +383,7 @@ def cube_leg(steps=20):
     c = gen.config4()
     n, T, b = c["n"], len(c["layers"]), 16
     # bins chosen by the plan (bin = 0): the N = 128 layers' occupied bins
-    # hold about 125 points at one cell per bin, and take bins of 2
+    # hold 82-137 points at one cell per bin, and take bins of 2
     kp = [mlg.kparams("nfft", 32, N=c["N"][t], window=6, bin=0) for t in range(T)]
     layers = [torch.from_numpy(L).to("cuda") for L in c["layers"]]
     t0 = time.perf_counter()
