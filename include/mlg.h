@@ -277,7 +277,10 @@ typedef struct {
  *   k            1..n/2 wanted pairs.
  *   block        vectors per Lanczos block, 1..32.
  *   tol          stop when every residual ||A phi - mu phi||_2 <= tol.
- *   max_restarts restarts allowed (0 = expand once, no restart).
+ *   max_restarts restarts allowed (0 = expand once, no restart).  The
+ *                basis grows to max(4k, k + 6 block) columns (rounded up to
+ *                whole blocks; at most 256 - block and n - block) before
+ *                each restart keeps the k + block best Ritz vectors.
  *   seed         start block: counter-based N(0,1) draws (SplitMix64 +
  *                Box-Muller) unless V0 is given.
  *   V0           optional n x block start block (same pointer kind as the

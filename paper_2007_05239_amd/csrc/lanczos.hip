@@ -616,14 +616,44 @@ struct Lz {
     }
 };
 
+// Dynamic LDS the Jacobi kernel may take: the device's limit per workgroup
+// (160 KB on gfx950) less 4 KB for the kernel's static rotation tables;
+// 60 KB if the device does not report one.  With it the projected matrix
+// of a 128-column basis (128 KB) is rotated in LDS.
+static int64_t jacobi_lds_budget() {
+    static int64_t budget = -1;
+    if (budget < 0) {
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            lim < 64 * 1024)
+            lim = 64 * 1024;
+        budget = (int64_t)lim - 4 * 1024;
+    }
+    return budget;
+}
+
 mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int max_restarts,
                        uint64_t seed, const double *V0, double *evals, double *evecs, int64_t ldv,
                        mlg_eig_info *info) {
     const int64_t n = g.n;
     hipStream_t s = g.stream;
-    int mmax = std::max(2 * k, k + 3 * b);
+    // Basis of up to mmax columns before a thick restart: wide enough that a
+    // restart adds about five blocks to the k + b kept Ritz vectors (fewer
+    // restarts and fewer products; the basis is small next to HBM), capped
+    // by the projected-matrix limit and by n.  30 pairs of a 10^7-node graph
+    // with blocks of 16: 128 columns take 63 block products and 11 restarts,
+    // 80 columns (max(2k, k + 3b)) took 115 and 55.
+    int mmax = std::max(4 * k, k + 6 * b);
     mmax = (mmax + b - 1) / b * b;
     while (mmax + b > kTnMaxP) mmax -= b;
+    while (mmax > k + b && (int64_t)mmax + b > n) mmax -= b;
+    // The first expansion also checks convergence every ~16 columns from
+    // max(2k, k + 3b) columns on, so that a problem which converges early
+    // does not run to the full basis (a few extra Rayleigh-Ritz steps once).
+    int mfirst = std::max(2 * k, k + 3 * b);
+    mfirst = (mfirst + b - 1) / b * b;
+    if (mfirst > mmax) mfirst = mmax;
     MLG_REQUIRE(mmax >= k + b, MLG_ERR_ARG, "k + 2 block exceeds the basis limit of 256 columns");
     MLG_REQUIRE((int64_t)mmax + b <= n, MLG_ERR_ARG, "basis larger than n");
     Lz z;
@@ -667,9 +697,10 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
     mlg_status st = MLG_WARN_NOT_CONVERGED;
     int nconv = 0;
     double maxres = 0.0;
+    int mstop = mfirst;   // columns at which the next Rayleigh-Ritz step runs
     for (;;) {
-        // ---- expand to mmax columns ----
-        while (m + b <= mmax) {
+        // ---- expand to mstop columns ----
+        while (m + b <= mstop) {
             double *Q = V.p + (int64_t)m * n;
             op.apply(b, Q, n, W.p, n);
             matvecs += b;
@@ -705,10 +736,11 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
         }
         // ---- Rayleigh-Ritz on H (m x m) ----
         MLG_HIP(hipMemcpyAsync(Ad.p, Hd.p, sizeof(double) * m * ldh, hipMemcpyDeviceToDevice, s));
-        if (2 * m * m * 8 <= 60 * 1024)
+        const int64_t jlds = jacobi_lds_budget();
+        if (2 * (int64_t)m * m * 8 <= jlds)
             hipLaunchKernelGGL((k_jacobi<true, true>), dim3(1), dim3(256), 2 * m * m * 8, s, m, Ad.p, ldh,
                                Yd.p, 40);
-        else if (m * m * 8 <= 60 * 1024)
+        else if ((int64_t)m * m * 8 <= jlds)
             hipLaunchKernelGGL((k_jacobi<true, false>), dim3(1), dim3(256), m * m * 8, s, m, Ad.p, ldh,
                                Yd.p, 40);
         else
@@ -735,7 +767,14 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
             if (rs[i] <= tol) ++nconv;
             maxres = std::max(maxres, rs[i]);
         }
-        const bool done = nconv == k || restarts >= max_restarts;
+        const bool full = m + b > mmax;
+        const bool done = nconv == k || (full && restarts >= max_restarts);
+        if (!done && !full) {
+            // an early check of the first expansion: the next one after
+            // about 16 more columns (one block of 16, four of 4)
+            mstop = std::min(mmax, m + b * std::max(1, 16 / b));
+            continue;
+        }
         if (done) {
             // Ritz vectors of the k wanted pairs, in descending mu
             hipLaunchKernelGGL(k_select_cols, dim3(ceil_div(m * k, 256)), dim3(256), 0, s, m, Yd.p, seld.p,
@@ -778,6 +817,7 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
         MLG_HIP(hipMemcpyAsync(Sd.p, S2.p, sizeof(double) * kTnMaxQ * kTnMaxP, hipMemcpyDeviceToDevice,
                                s));
         m = keep;
+        mstop = mmax;
         MLG_HIP(hipStreamSynchronize(s));
     }
     if (info) {
