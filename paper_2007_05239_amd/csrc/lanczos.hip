@@ -309,7 +309,11 @@ __global__ void k_store_R(int m, int b, const double *__restrict__ R, double *__
 // Parallel cyclic Jacobi (round-robin pairing) for a symmetric m x m matrix
 // in one workgroup.  A (ldh) is overwritten: diag = eigenvalues; Y (m x m,
 // row-major, column c = eigenvector c).  AL / YL: A / Y are worked on in LDS
-// (dynamic shared memory, A first) and written back at the end.
+// (dynamic shared memory, A first, rows padded to m + 1 doubles so that the
+// column rotations' rows fall in different banks) and written back at the
+// end.  A Y kept in global memory is worked on transposed (the column
+// rotations then touch consecutive addresses) and transposed in place at
+// the end.
 template <bool AL, bool YL>
 __global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ Ag, int ldag,
                                                 double *__restrict__ Yg, int max_sweeps) {
@@ -318,13 +322,16 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ Ag, 
     __shared__ int rotated;
     extern __shared__ double jsm[];
     double *A = AL ? jsm : Ag;
-    const int lda = AL ? m : ldag;
-    double *Y = YL ? (AL ? jsm + m * m : jsm) : Yg;
+    const int lda = AL ? m + 1 : ldag;
+    double *Y = YL ? (AL ? jsm + m * (m + 1) : jsm) : Yg;
+    // element (r, c) of Y at Y[r * yr + c * yc]
+    const int yr = YL ? m + 1 : 1, yc = YL ? 1 : m;
     const int tid = threadIdx.x;
     const int me = m + (m & 1);  // even, with a dummy index m if odd
     if (AL)
-        for (int e = tid; e < m * m; e += 256) A[e] = Ag[(e / m) * ldag + e % m];
-    for (int e = tid; e < m * m; e += 256) Y[e] = (e / m == e % m) ? 1.0 : 0.0;
+        for (int e = tid; e < m * m; e += 256) A[(e / m) * lda + e % m] = Ag[(e / m) * ldag + e % m];
+    for (int e = tid; e < m * m; e += 256)
+        Y[(e / m) * yr + (e % m) * yc] = (e / m == e % m) ? 1.0 : 0.0;
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         if (tid == 0) rotated = 0;
@@ -368,9 +375,9 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ Ag, 
                 double ap = A[r * lda + p], aq = A[r * lda + q];
                 A[r * lda + p] = c * ap - s * aq;
                 A[r * lda + q] = s * ap + c * aq;
-                double yp = Y[r * m + p], yq = Y[r * m + q];
-                Y[r * m + p] = c * yp - s * yq;
-                Y[r * m + q] = s * yp + c * yq;
+                double yp = Y[r * yr + p * yc], yq = Y[r * yr + q * yc];
+                Y[r * yr + p * yc] = c * yp - s * yq;
+                Y[r * yr + q * yc] = s * yp + c * yq;
             }
             __syncthreads();
             // rows: A <- J^T A
@@ -390,9 +397,20 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ Ag, 
     }
     __syncthreads();
     if (AL)
-        for (int e = tid; e < m * m; e += 256) Ag[(e / m) * ldag + e % m] = A[e];
-    if (YL)
-        for (int e = tid; e < m * m; e += 256) Yg[e] = Y[e];
+        for (int e = tid; e < m * m; e += 256) Ag[(e / m) * ldag + e % m] = A[(e / m) * lda + e % m];
+    if (YL) {
+        for (int e = tid; e < m * m; e += 256) Yg[e] = Y[(e / m) * yr + e % m];
+    } else {
+        // back to row-major: each pair (i < j) swapped by one thread
+        for (int e = tid; e < m * m; e += 256) {
+            const int i = e / m, j = e % m;
+            if (i < j) {
+                const double t = Yg[i * m + j];
+                Yg[i * m + j] = Yg[j * m + i];
+                Yg[j * m + i] = t;
+            }
+        }
+    }
 }
 
 // Residual norms ||S y_c|| for the selected Ritz columns sel[0..ns).
@@ -737,11 +755,12 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
         // ---- Rayleigh-Ritz on H (m x m) ----
         MLG_HIP(hipMemcpyAsync(Ad.p, Hd.p, sizeof(double) * m * ldh, hipMemcpyDeviceToDevice, s));
         const int64_t jlds = jacobi_lds_budget();
-        if (2 * (int64_t)m * m * 8 <= jlds)
-            hipLaunchKernelGGL((k_jacobi<true, true>), dim3(1), dim3(256), 2 * m * m * 8, s, m, Ad.p, ldh,
+        const int64_t jmat = (int64_t)m * (m + 1) * 8;   // one padded m x m matrix
+        if (2 * jmat <= jlds)
+            hipLaunchKernelGGL((k_jacobi<true, true>), dim3(1), dim3(256), 2 * jmat, s, m, Ad.p, ldh,
                                Yd.p, 40);
-        else if ((int64_t)m * m * 8 <= jlds)
-            hipLaunchKernelGGL((k_jacobi<true, false>), dim3(1), dim3(256), m * m * 8, s, m, Ad.p, ldh,
+        else if (jmat <= jlds)
+            hipLaunchKernelGGL((k_jacobi<true, false>), dim3(1), dim3(256), jmat, s, m, Ad.p, ldh,
                                Yd.p, 40);
         else
             hipLaunchKernelGGL((k_jacobi<false, false>), dim3(1), dim3(256), 0, s, m, Ad.p, ldh, Yd.p,
