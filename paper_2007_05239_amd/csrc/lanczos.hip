@@ -489,33 +489,78 @@ __global__ void k_randn(uint64_t seed, int64_t n, int b, double *__restrict__ X,
 
 // Sign convention: the largest-magnitude entry of each column is positive
 // (lowest index on ties).
-__global__ void k_fix_sign(int64_t n, double *__restrict__ V, int64_t ldv) {
-    __shared__ double sv[256];
+// Sign of each eigenvector: the entry of largest magnitude (lowest index on
+// ties) is made positive.  Two passes over kSignChunks row chunks per column:
+// chunk maxima (magnitude, index, value), then every chunk's workgroup
+// reduces its column's maxima in chunk order (all reach the same entry) and
+// negates its chunk if that entry is negative.  The value travels with the
+// maximum, so no workgroup reads an entry another one may be negating.
+constexpr int kSignChunks = 64;
+
+__global__ __launch_bounds__(256) void k_sign_part(int64_t n, const double *__restrict__ V,
+                                                   int64_t ldv, double *__restrict__ pa,
+                                                   int64_t *__restrict__ pi,
+                                                   double *__restrict__ pv) {
+    __shared__ double sa[256], sv[256];
     __shared__ int64_t si[256];
-    double *col = V + (int64_t)blockIdx.x * ldv;
-    double best = -1.0;
+    const double *col = V + (int64_t)blockIdx.x * ldv;
+    const int64_t len = (n + kSignChunks - 1) / kSignChunks;
+    const int64_t lo = (int64_t)blockIdx.y * len;
+    const int64_t hi = lo + len < n ? lo + len : n;
+    double best = -1.0, val = 0.0;
     int64_t bi = 0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        double a = fabs(col[i]);
-        if (a > best) { best = a; bi = i; }
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const double v = col[i];
+        const double a = fabs(v);
+        if (a > best) { best = a; bi = i; val = v; }
     }
-    sv[threadIdx.x] = best;
+    sa[threadIdx.x] = best;
     si[threadIdx.x] = bi;
+    sv[threadIdx.x] = val;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (threadIdx.x < off) {
-            double a = sv[threadIdx.x + off];
-            int64_t ai = si[threadIdx.x + off];
-            if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
-                sv[threadIdx.x] = a;
+            const double a = sa[threadIdx.x + off];
+            const int64_t ai = si[threadIdx.x + off];
+            if (a > sa[threadIdx.x] || (a == sa[threadIdx.x] && ai < si[threadIdx.x])) {
+                sa[threadIdx.x] = a;
                 si[threadIdx.x] = ai;
+                sv[threadIdx.x] = sv[threadIdx.x + off];
             }
         }
         __syncthreads();
     }
-    const bool flip = col[si[0]] < 0.0;
+    if (threadIdx.x == 0) {
+        const int64_t o = (int64_t)blockIdx.x * kSignChunks + blockIdx.y;
+        pa[o] = sa[0];
+        pi[o] = si[0];
+        pv[o] = sv[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sign_apply(int64_t n, double *__restrict__ V, int64_t ldv,
+                                                    const double *__restrict__ pa,
+                                                    const int64_t *__restrict__ pi,
+                                                    const double *__restrict__ pv) {
+    __shared__ int flip;
+    if (threadIdx.x == 0) {
+        const int64_t o = (int64_t)blockIdx.x * kSignChunks;
+        double best = -1.0, val = 0.0;
+        int64_t bi = 0;
+        for (int j = 0; j < kSignChunks; ++j) {
+            const double a = pa[o + j];
+            const int64_t ai = pi[o + j];
+            if (a > best || (a == best && ai < bi)) { best = a; bi = ai; val = pv[o + j]; }
+        }
+        flip = val < 0.0;
+    }
+    __syncthreads();
     if (!flip) return;
-    for (int64_t i = threadIdx.x; i < n; i += 256) col[i] = -col[i];
+    double *col = V + (int64_t)blockIdx.x * ldv;
+    const int64_t len = (n + kSignChunks - 1) / kSignChunks;
+    const int64_t lo = (int64_t)blockIdx.y * len;
+    const int64_t hi = lo + len < n ? lo + len : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) col[i] = -col[i];
 }
 
 __global__ void k_add(int cnt, double *a, const double *b) {
@@ -800,8 +845,17 @@ mlg_status lanczos_run(Graph &g, LanczosOp &op, int k, int b, double tol, int ma
                                k, Ysel.p);
             MLG_LAUNCH_CHECK();
             z.nn(m, k, V.p, n, Ysel.p, evecs, ldv, 0);
-            hipLaunchKernelGGL(k_fix_sign, dim3(k), dim3(256), 0, s, n, evecs, ldv);
-            MLG_LAUNCH_CHECK();
+            {
+                DevBuf<double> pa((size_t)k * kSignChunks), pv((size_t)k * kSignChunks);
+                DevBuf<int64_t> pi((size_t)k * kSignChunks);
+                hipLaunchKernelGGL(k_sign_part, dim3(k, kSignChunks), dim3(256), 0, s, n, evecs, ldv,
+                                   pa.p, pi.p, pv.p);
+                MLG_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_sign_apply, dim3(k, kSignChunks), dim3(256), 0, s, n, evecs, ldv,
+                                   pa.p, pi.p, pv.p);
+                MLG_LAUNCH_CHECK();
+                MLG_HIP(hipStreamSynchronize(s));
+            }
             for (int i = 0; i < k; ++i) evals[i] = op.lambda(th[order[i]]);
             st = nconv == k ? MLG_OK : MLG_WARN_NOT_CONVERGED;
             MLG_HIP(hipStreamSynchronize(s));
