@@ -366,18 +366,46 @@ __global__ __launch_bounds__(256) void k_jacobi(int m, double *__restrict__ Ag, 
                 sn[k] = s;
             }
             __syncthreads();
-            // columns: A <- A J
-            for (int e = tid; e < (me / 2) * m; e += 256) {
-                int k = e / m, r = e % m;
-                int p = pp[k], q = qq[k];
-                if (q >= m || sn[k] == 0.0) continue;
-                double c = cs[k], s = sn[k];
-                double ap = A[r * lda + p], aq = A[r * lda + q];
-                A[r * lda + p] = c * ap - s * aq;
-                A[r * lda + q] = s * ap + c * aq;
-                double yp = Y[r * yr + p * yc], yq = Y[r * yr + q * yc];
-                Y[r * yr + p * yc] = c * yp - s * yq;
-                Y[r * yr + q * yc] = s * yp + c * yq;
+            // columns: A <- A J.  The elements of one round are disjoint, so
+            // each thread loads kJacB of them before it stores any (a Y in
+            // global memory otherwise costs one memory latency per element).
+            constexpr int kJacB = 4;
+            const int ncol = (me / 2) * m;
+            for (int e0 = tid; e0 < ncol; e0 += 256 * kJacB) {
+                int ia[kJacB], ib[kJacB], ja[kJacB], jb[kJacB];
+                bool act[kJacB];
+                double c[kJacB], sv[kJacB], ap[kJacB], aq[kJacB], yp[kJacB], yq[kJacB];
+#pragma unroll
+                for (int u = 0; u < kJacB; ++u) {
+                    const int e = e0 + u * 256;
+                    act[u] = false;
+                    if (e < ncol) {
+                        const int k = e / m, r = e % m;
+                        const int p = pp[k], q = qq[k];
+                        act[u] = q < m && sn[k] != 0.0;
+                        c[u] = cs[k];
+                        sv[u] = sn[k];
+                        ia[u] = r * lda + p;
+                        ib[u] = r * lda + q;
+                        ja[u] = r * yr + p * yc;
+                        jb[u] = r * yr + q * yc;
+                    }
+                    if (act[u]) {
+                        ap[u] = A[ia[u]];
+                        aq[u] = A[ib[u]];
+                        yp[u] = Y[ja[u]];
+                        yq[u] = Y[jb[u]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kJacB; ++u) {
+                    if (act[u]) {
+                        A[ia[u]] = c[u] * ap[u] - sv[u] * aq[u];
+                        A[ib[u]] = sv[u] * ap[u] + c[u] * aq[u];
+                        Y[ja[u]] = c[u] * yp[u] - sv[u] * yq[u];
+                        Y[jb[u]] = sv[u] * yp[u] + c[u] * yq[u];
+                    }
+                }
             }
             __syncthreads();
             // rows: A <- J^T A
