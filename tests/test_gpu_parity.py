@@ -357,6 +357,22 @@ def test_lanczos_direct_config1(mlg):
     compare_eigvecs(lam_ref, V_ref, V)
 
 
+@pytest.mark.parametrize("n,k,block", [(30, 5, 4), (46, 8, 6)])
+def test_lanczos_basis_capped_by_n(mlg, n, k, block):
+    """Graphs so small that the basis rule max(4k, k + 6 block) is cut back
+    to n - block columns: eigenpairs against the dense oracle."""
+    pts, _ = gen.gaussian_mixture(n, 3, 3, 0.1, 1401 + n)
+    L = oracle.Layer(pts, 0.3)
+    lam_ref, V_ref = oracle.eigs_dense([L], k)
+    g = mlg.Graph([pts], [0.3], mlg.kparams("direct", 64))
+    case_id("lanczos direct fp64 n=%d k=%d block=%d (basis capped by n)" % (n, k, block))
+    lam, V, info = g.lanczos_eigs(0, k, block=block, tol=1e-10, seed=1405 + n)
+    g.close()
+    assert info["converged"], info
+    np.testing.assert_allclose(lam, lam_ref, atol=1e-8)
+    compare_eigvecs(lam_ref, V_ref, V)
+
+
 def test_lanczos_nfft_fp64_multilayer(mlg):
     n = 2500
     p3, _ = gen.gaussian_mixture(n, 3, 4, 0.05, 81)
