@@ -280,7 +280,9 @@ typedef struct {
  *   max_restarts restarts allowed (0 = expand once, no restart).  The
  *                basis grows to max(4k, k + 6 block) columns (rounded up to
  *                whole blocks; at most 256 - block and n - block) before
- *                each restart keeps the k + block best Ritz vectors.
+ *                each restart keeps the k + block best Ritz vectors; the
+ *                first expansion also stops for a convergence check every
+ *                ~16 columns from max(2k, k + 3 block) columns on.
  *   seed         start block: counter-based N(0,1) draws (SplitMix64 +
  *                Box-Muller) unless V0 is given.
  *   V0           optional n x block start block (same pointer kind as the
